@@ -1,0 +1,195 @@
+"""Benchmark of the hot path: one time step of the symmetric free-energy
+multicomponent LB method (Li & Wagner) on the ternary D2Q9 2048 x 2048
+immersion-precipitation workload, FP32, one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--storage f32|f64]
+                    [--workload NAME] [--no-cpu] [--calibrate-copy]
+
+Prints one JSON line.  `value` is MLUPS x components (sites x components x
+steps / second / 1e6) with the state resident in HBM; the timed region is K
+lb_step calls bracketed by synchronisation and HIP events on the stream the
+kernels run on.  `roofline` prices the fused step kernel against the HBM
+peak: its algorithmic traffic per launch is every population read once and
+written once, 2 * Q * N * S * bytes.  `cpu_baseline` times the FP64 CPU
+oracle on a bounded sample of the same workload on the host cores.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS×components at 2048² ternary, % HBM peak; serving p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_0704_3444_amd/csrc/k_fused2d.hip", "paper_0704_3444_amd/csrc/physics.hpp",
+                  "paper_0704_3444_amd/csrc/lattice.hpp"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def workload(name):
+    import lbinputs as LI
+
+    table = {
+        "ternary_d2q9_2048": lambda: LI.ternary_immersion(2048),
+        "binary_d2q9_1024": lambda: LI.binary_spinodal(1024, seed=1001),
+        "ternary_d3q19_256": lambda: LI.ternary_d3q19(256),
+        "five_d2q9_512": lambda: LI.five_component(512),
+        "binary_d2q9_64": lambda: LI.binary_spinodal(64),
+    }
+    return table[name]()
+
+
+def measured_traffic(name, storage):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{name}_{storage}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_sha") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(cfg, rho0, target_s=15.0):
+    """FP64 oracle on the host cores: calibrate with one step, then run as
+    many steps as fit in about target_s seconds (at most 50)."""
+    from oracle import Oracle, OracleParams
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    o = Oracle(OracleParams(**cfg), rho0)
+    t0 = time.perf_counter()
+    o.step(1)
+    t1 = time.perf_counter() - t0
+    n = max(1, min(50, int(target_s / max(t1, 1e-6))))
+    t0 = time.perf_counter()
+    o.step(n)
+    dt = time.perf_counter() - t0
+    sites = int(cfg["shape"][0]) * int(cfg["shape"][1]) * (int(cfg["shape"][2]) if len(cfg["shape"]) > 2 else 1)
+    value = sites * cfg["n_comp"] * n / dt / 1e6
+    return {"value": round(value, 3), "unit": "MLUPS×components", "cores": threads, "kind": "oracle",
+            "sample": f"{n} steps (after 1 warm-up step) of the full {cfg['shape'][0]}x{cfg['shape'][1]} "
+                      f"N={cfg['n_comp']} workload from its initial state, FP64, {dt:.1f} s"}
+
+
+def calibrate_copy(gib=1.0, reps=5):
+    """A plain device-to-device copy of known size, run under rocprofv3 --pmc
+    to scale FETCH_SIZE / WRITE_SIZE (each copy reads and writes `gib` GiB)."""
+    import torch
+
+    n = int(gib * (1 << 30))
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty(n, dtype=torch.uint8, device="cuda")
+    a.fill_(1)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_bytes": n, "reps": reps}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--storage", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--workload", default="ternary_d2q9_2048")
+    ap.add_argument("--path", default="auto", choices=["auto", "fused", "split"])
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one GPU only (a single lattice per device; multi-GPU "
+              "slab decomposition is not implemented); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
+
+    import numpy as np
+    import torch
+
+    from paper_0704_3444_amd import Simulation, lb
+
+    if not os.path.exists(lb.LIB_PATH):
+        from paper_0704_3444_amd import build as gpu_build
+        gpu_build.build()
+
+    cfg, rho0 = workload(args.workload)
+    shape = list(cfg["shape"]) + [1] * (3 - len(cfg["shape"]))
+    S = int(np.prod(shape))
+    N = int(cfg["n_comp"])
+    Q = {"D1Q3": 3, "D2Q9": 9, "D3Q19": 19}[cfg["lattice"]]
+    nbytes = 4 if args.storage == "f32" else 8
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    sim = Simulation(cfg, rho0, storage=args.storage, path=args.path, stream=stream)
+    print(f"bench: {args.workload} {shape} N={N} {args.storage} path={sim.path}; warmup {args.warmup}",
+          file=sys.stderr, flush=True)
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record(stream)
+    sim.step(args.steps)
+    end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = start.elapsed_time(end)
+    ms_per_step = ms / args.steps
+    value = S * N * args.steps / (ms / 1e3) / 1e6
+
+    # the state must still be physical after the timed steps
+    health = sim.moments(fields=False)
+    mass_drift = float(np.max(np.abs(health["mass"] / rho0.sum(axis=1) - 1)))
+    path = sim.path
+    sim.close()
+
+    kernels_per_step = 1 if path == "fused" else 3
+    alg_bytes = 2 * Q * N * S * nbytes
+    achieved = alg_bytes / (ms_per_step / 1e3) / 1e9
+    traffic = measured_traffic(args.workload, args.storage) if path == "fused" else None
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "k_fused_d2q9" if path == "fused" else "k_density+k_potential+k_collide",
+                "algorithmic_bytes_per_launch": alg_bytes, "launches_per_step": kernels_per_step,
+                "avg_launch_ms": round(ms_per_step / kernels_per_step, 5)}
+
+    cpu = None
+    if not args.no_cpu:
+        print("bench: timing the CPU oracle on the same workload", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(cfg, rho0)
+
+    line = {
+        "metric": METRIC, "value": round(value, 1), "unit": "MLUPS×components", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.storage, "data": "synthetic",
+        "config": {"workload": args.workload, "lattice": cfg["lattice"], "shape": shape[: len(cfg["shape"])],
+                   "n_comp": N, "storage": args.storage, "path": path, "force_form": cfg["force_form"]},
+        "hbm_frac": round(achieved / HBM_PEAK_GBS, 4),
+        "wall_s": round(wall, 4), "mass_drift": mass_drift, "status": health["status"],
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

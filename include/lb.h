@@ -1,0 +1,172 @@
+/*
+ * lb.h -- C ABI of the MI355X (gfx950) library for the symmetric
+ * free-energy multicomponent lattice Boltzmann method of Li & Wagner,
+ * "A Symmetric Free Energy Based Multi-Component Lattice Boltzmann Method"
+ * (arXiv:0704.3444).
+ *
+ * The library advances N component distributions f^sigma_i on a periodic
+ * lattice by the per-component lattice Boltzmann equation Eq. (ssLB) (BGK
+ * collision with relaxation time tau plus a forcing term, then streaming),
+ * with the equilibrium moments and forcing moments Eqs. (ff1)-(ff3) of
+ * Sec. III, the force of Eq. (definef), and the chemical potentials of the
+ * Flory-Huggins free energy Eq. (lgf) of Sec. IV (taken per mer, plus a
+ * square-gradient term -kappa lap rho^sigma).
+ *
+ * Conventions shared by every entry point:
+ *   - lattice units, dt = dx = 1, c_s^2 = 1/3;
+ *   - site index s = x + nx*(y + ny*z); every axis is periodic;
+ *   - host arrays are caller-owned FP64, component-major structure of
+ *     arrays (e.g. rho[sigma][s]);
+ *   - device state is owned by the context (in caller-provided device
+ *     memory when a workspace is passed to lb_init);
+ *   - all device work is issued on params.stream (a hipStream_t, NULL for
+ *     the null stream) in issue order; only lb_moments, lb_get_f and
+ *     lb_get_state/lb_set_state wait for the stream;
+ *   - calls on one context are not thread-safe; distinct contexts are
+ *     independent;
+ *   - no C++ exception crosses this boundary; every int-returning call
+ *     returns LB_OK or a negative lb_status.
+ */
+#ifndef LB_H
+#define LB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LB_MAX_COMP 8
+#define LB_ABI_VERSION 1
+
+typedef enum lb_status {
+  LB_OK = 0,
+  LB_EINVAL = -1,    /* invalid argument or parameter (message: lb_last_error) */
+  LB_ENOMEM = -2,    /* device or host allocation failed, or workspace too small */
+  LB_ENOTSUP = -3,   /* valid but not supported by this build                   */
+  LB_EDEVICE = -4,   /* a HIP runtime call failed                               */
+  LB_ENUMERIC = -5   /* a non-finite or non-positive density was detected       */
+} lb_status;
+
+/* Velocity sets: D1Q3 is the paper's (Sec. IV); D2Q9 and D3Q19 are the
+ * standard second-order sets with sum_i w_i v_i v_i = I/3. */
+typedef enum lb_lattice { LB_D1Q3 = 1, LB_D2Q9 = 2, LB_D3Q19 = 3 } lb_lattice;
+
+/* Storage and arithmetic precision of the populations.
+ *   LB_F64: stored and computed in FP64.
+ *   LB_F32: stored and computed in FP32. */
+typedef enum lb_storage { LB_F64 = 0, LB_F32 = 1 } lb_storage;
+
+/* Which line of Eq. (definef) forms the force rho^sigma a^sigma, with
+ * c = 1 - 1/(2 tau):
+ *   LB_FORCE_LOG:      -c rho^s grad(mu^s - (1/3) ln rho^s)  (first line)
+ *   LB_FORCE_EXPANDED: -c (rho^s grad mu^s - (1/3) grad rho^s) (second line)
+ * The two agree in the continuum.  Gradients use the isotropic lattice
+ * stencil grad g = 3 sum_i w_i v_i g(r + v_i); the Laplacian in mu is
+ * lap g = 6 sum_i w_i (g(r + v_i) - g(r)). */
+typedef enum lb_force_form { LB_FORCE_LOG = 0, LB_FORCE_EXPANDED = 1 } lb_force_form;
+
+/* Kernel path.  AUTO picks the fused single-kernel step where one exists
+ * for the lattice and precision, else the split path (density, potential
+ * and collide-stream kernels). */
+typedef enum lb_path { LB_PATH_AUTO = 0, LB_PATH_FUSED = 1, LB_PATH_SPLIT = 2 } lb_path;
+
+typedef struct lb_params {
+  int32_t n_comp;        /* N, 1 .. LB_MAX_COMP                                   */
+  int32_t lattice;       /* lb_lattice                                            */
+  int32_t storage;       /* lb_storage                                            */
+  int32_t force_form;    /* lb_force_form                                         */
+  int64_t nx, ny, nz;    /* box; D1Q3 needs ny = nz = 1, D2Q9 nz = 1; each >= 1  */
+  double tau[LB_MAX_COMP];  /* tau^sigma; all equal (the total-fluid equation,
+                              Eq. (sgLB), needs one tau) and > 1/2             */
+  double theta;          /* temperature of Eq. (lgf), > 0                         */
+  double kappa;          /* square-gradient coefficient, >= 0                     */
+  double m[LB_MAX_COMP]; /* polymerisation m^sigma > 0                            */
+  double chi[LB_MAX_COMP * LB_MAX_COMP]; /* chi^{sigma sigma'}, row-major with
+                              leading dimension LB_MAX_COMP; the N x N block must
+                              be symmetric with zero diagonal (Sec. IV)          */
+  int32_t path;          /* lb_path                                               */
+  int32_t check_every;   /* every K steps lb_step also checks every density for
+                            NaN or <= 0 (0: only in lb_moments); a failed check
+                            makes the next synchronising call return LB_ENUMERIC */
+  void* stream;          /* hipStream_t for all device work (NULL: null stream)   */
+} lb_params;
+
+typedef struct lb_ctx lb_ctx;
+
+/* Device bytes that lb_init needs for params p (two population copies plus
+ * scratch), or 0 when p is invalid. */
+size_t lb_workspace_bytes(const lb_params* p);
+
+/* Create a context and set every site to rest equilibrium,
+ * f^sigma_i = w_i rho0^sigma (the paper prescribes the initial volume
+ * fractions of a fluid at rest).
+ *   p          parameters, copied.
+ *   rho0       host FP64 [N][S] initial component densities, each > 0; copied.
+ *   workspace  device memory of at least lb_workspace_bytes(p) bytes, 256-byte
+ *              aligned, owned by the caller and kept alive until lb_free; or
+ *              NULL, in which case the library allocates (and frees) its own.
+ *   out        receives the context.
+ * Errors: LB_EINVAL (parameters, rho0 <= 0 or non-finite, misaligned
+ * workspace), LB_ENOMEM (workspace_bytes too small, allocation failure),
+ * LB_EDEVICE. */
+int lb_init(const lb_params* p, const double* rho0, void* workspace, size_t workspace_bytes,
+            lb_ctx** out);
+
+/* Advance nsteps >= 0 time steps of Eq. (ssLB): per site and component the
+ * moments, chemical potentials, force, equilibrium, forcing term, BGK
+ * collision and streaming.  Asynchronous on the context's stream. */
+int lb_step(lb_ctx* c, int64_t nsteps);
+
+/* Observables at the current time, computed on the device in FP64 from the
+ * stored populations and copied to caller-owned host buffers (any pointer
+ * may be NULL).  Synchronises the stream.
+ *   rho   [N][S]   component densities rho^sigma = sum_i f^sigma_i
+ *   U     [D][S]   macroscopic velocity U = u + (1/2) sum_sigma A^sigma / rho
+ *                  (Sec. III), u the barycentric velocity
+ *   mu    [N][S]   per-mer chemical potentials mu^sigma
+ *   P     [D(D+1)/2][S] pressure tensor xx, xy, (xz), yy, (yz), (zz) of the
+ *                  free energy with the square-gradient term; bulk part
+ *                  sum rho mu - psi, Eq. (ppp) (a diagnostic; the update does
+ *                  not use it)
+ *   mass  [N]      sum over sites of rho^sigma
+ *   mom   [D]      sum over sites and components of the first moments
+ *   step  [1]      number of steps taken
+ * Returns LB_ENUMERIC if any density is non-finite or <= 0 (outputs are
+ * still written). */
+int lb_moments(lb_ctx* c, double* rho, double* U, double* mu, double* P, double* mass,
+               double* mom, int64_t* step);
+
+/* Populations f^sigma_i(r, t) at the current time as host FP64 [N][Q][S],
+ * velocity order of the lattice tables (lb_lattice_tables).  Synchronises. */
+int lb_get_f(lb_ctx* c, double* f);
+
+/* Checkpoint: the raw device state (storage precision) plus the step
+ * counter.  lb_state_bytes gives the size; lb_get_state copies it to host
+ * memory, lb_set_state restores it into a context created with the same
+ * parameters.  Both synchronise. */
+size_t lb_state_bytes(const lb_ctx* c);
+int lb_get_state(lb_ctx* c, void* host, size_t bytes);
+int lb_set_state(lb_ctx* c, const void* host, size_t bytes);
+
+/* Lattice tables: Q, D, velocities v[Q][3] and weights w[Q] (host). */
+int lb_lattice_tables(int32_t lattice, int32_t* Q, int32_t* D, int32_t* v, double* w);
+
+/* Path that lb_step runs for this context (LB_PATH_FUSED or LB_PATH_SPLIT). */
+int lb_path_in_use(const lb_ctx* c);
+
+/* Release the context and any memory the library allocated.  NULL is a
+ * no-op.  Waits for the context's stream. */
+void lb_free(lb_ctx* c);
+
+/* Static description of a status code. */
+const char* lb_strerror(int code);
+
+/* Message of the last failed call on this thread (empty if none). */
+const char* lb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LB_H */

@@ -1,0 +1,254 @@
+// Fused single-kernel D2Q9 step.
+//
+// One launch per time step.  Each workgroup owns a TX x TY tile of sites and
+// runs the whole step of the method for it:
+//   A. pull the tile's populations (f_i(r) is slot (i, r - v_i)) into
+//      registers and form rho^sigma; stage rho in LDS;
+//   B. form rho^sigma on a two-site ring around the tile (the Laplacian in
+//      mu and the gradient of mu reach two sites) from the same pulled
+//      populations, into LDS; neighbouring workgroups read these rows too,
+//      so they come from L2 or the MALL rather than HBM;
+//   C. chemical potentials and the potential h on the tile plus one ring,
+//      in LDS;
+//   D. force, equilibrium, forcing term, BGK collision, and one coalesced
+//      store per population at the site itself (streaming happens through
+//      the pull of the next step).
+// Populations are read once and written once per step from HBM.  Workgroup
+// indices are remapped so that the eight XCDs (dispatched round-robin) each
+// sweep a contiguous band of tiles, keeping halo rows in their own L2.
+// No MFMA: the step is a bandwidth-bound stencil, not a contraction.
+#include <hip/hip_runtime.h>
+
+#include "lbm_internal.hpp"
+#include "physics.hpp"
+
+namespace lbm {
+
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int wrap_mod(int v, int n) {
+  int r = v % n;
+  return r < 0 ? r + n : r;
+}
+
+// rho^sigma at (x, y), summing the pulled populations in lattice order (the
+// same order as the split path's density kernel).
+template <typename T, int NC>
+__device__ __forceinline__ void pulled_density(const T* __restrict__ fin, long long S, int nx, int ny, int x,
+                                               int y, int n, T (&rho)[NC]) {
+  using L = Lattice<2>;
+  const int xm = wrap_add(x, -1, nx), xp = wrap_add(x, 1, nx);
+  const int ym = wrap_add(y, -1, ny), yp = wrap_add(y, 1, ny);
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    T acc = T(0);
+    if (k < n) {
+#pragma unroll
+      for (int i = 0; i < L::Q; ++i) {
+        const int sx = L::cx(i) > 0 ? xm : (L::cx(i) < 0 ? xp : x);
+        const int sy = L::cy(i) > 0 ? ym : (L::cy(i) < 0 ? yp : y);
+        acc += fin[((long long)k * L::Q + i) * S + (long long)sy * nx + sx];
+      }
+    }
+    rho[k] = acc;
+  }
+}
+
+template <typename T, int NC, int TX, int TY, int NT>
+__global__ void __launch_bounds__(NT) k_fused_d2q9(const T* __restrict__ fin, T* __restrict__ fout, Params<T> p,
+                                                   int nbx, int ntiles, int tiles_per_xcd) {
+  using L = Lattice<2>;
+  constexpr int Q = L::Q;
+  constexpr int HX = TX + 4, HY = TY + 4;  // rho region: tile + 2
+  constexpr int GX = TX + 2, GY = TY + 2;  // h region:   tile + 1
+  constexpr int RS = NT / TX;              // row stride between a thread's sites
+  constexpr int SPT = TY / RS;             // sites per thread
+  static_assert(NT % TX == 0 && TY % RS == 0, "tile shape");
+
+  __shared__ T s_rho[NC][HY][HX];
+  __shared__ T s_h[NC][GY][GX];
+
+  // XCD-aware tile order: workgroup b runs on XCD b % 8; give XCD c the
+  // contiguous tile range [c * tiles_per_xcd, (c + 1) * tiles_per_xcd).
+  const int b = blockIdx.x;
+  const int t = (b % kXcds) * tiles_per_xcd + b / kXcds;
+  if (t >= ntiles) return;
+  const int x0 = (t % nbx) * TX, y0 = (t / nbx) * TY;
+  const int nx = p.nx, ny = p.ny, n = p.n;
+  const long long S = p.S;
+  const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+
+  // ---- A: the tile's own populations, kept in registers -------------------
+  T f[SPT][NC][Q];
+  bool valid[SPT];
+#pragma unroll
+  for (int k = 0; k < SPT; ++k) {
+    const int x = x0 + tx, y = y0 + ty + k * RS;
+    valid[k] = x < nx && y < ny;
+    if (valid[k]) {
+      const int xm = wrap_add(x, -1, nx), xp = wrap_add(x, 1, nx);
+      const int ym = wrap_add(y, -1, ny), yp = wrap_add(y, 1, ny);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        T acc = T(0);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          const int sx = L::cx(i) > 0 ? xm : (L::cx(i) < 0 ? xp : x);
+          const int sy = L::cy(i) > 0 ? ym : (L::cy(i) < 0 ? yp : y);
+          f[k][c][i] = c < n ? fin[((long long)c * Q + i) * S + (long long)sy * nx + sx] : T(0);
+          acc += f[k][c][i];
+        }
+        s_rho[c][ty + k * RS + 2][tx + 2] = acc;
+      }
+    }
+  }
+
+  // ---- B: density on the ring (and on tile slots outside a ragged box) ----
+  const bool full = (x0 + TX <= nx) && (y0 + TY <= ny);
+  if (full) {
+    constexpr int RING = 4 * HX + 4 * TY;
+    for (int idx = threadIdx.x; idx < RING; idx += NT) {
+      int px, py;
+      if (idx < 2 * HX) {
+        py = idx / HX;
+        px = idx % HX;
+      } else if (idx < 4 * HX) {
+        const int j = idx - 2 * HX;
+        py = TY + 2 + j / HX;
+        px = j % HX;
+      } else if (idx < 4 * HX + 2 * TY) {
+        const int j = idx - 4 * HX;
+        py = 2 + j / 2;
+        px = j % 2;
+      } else {
+        const int j = idx - 4 * HX - 2 * TY;
+        py = 2 + j / 2;
+        px = TX + 2 + j % 2;
+      }
+      T r[NC];
+      pulled_density<T, NC>(fin, S, nx, ny, wrap_mod(x0 - 2 + px, nx), wrap_mod(y0 - 2 + py, ny), n, r);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) s_rho[c][py][px] = r[c];
+    }
+  } else {
+    for (int idx = threadIdx.x; idx < HX * HY; idx += NT) {
+      const int px = idx % HX, py = idx / HX;
+      const bool inner = px >= 2 && px < TX + 2 && py >= 2 && py < TY + 2 && x0 + px - 2 < nx && y0 + py - 2 < ny;
+      if (inner) continue;  // filled in phase A
+      T r[NC];
+      pulled_density<T, NC>(fin, S, nx, ny, wrap_mod(x0 - 2 + px, nx), wrap_mod(y0 - 2 + py, ny), n, r);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) s_rho[c][py][px] = r[c];
+    }
+  }
+  __syncthreads();
+
+  // ---- C: potential h on the tile plus one ring ---------------------------
+  for (int idx = threadIdx.x; idx < GX * GY; idx += NT) {
+    const int qx = idx % GX, qy = idx / GX;
+    const int cx = qx + 1, cy = qy + 1;  // position in the rho region
+    T r[NC], lap[NC], mu[NC], h[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      r[c] = c < n ? s_rho[c][cy][cx] : T(1);
+      lap[c] = c < n ? lattice_laplacian<2, T>(
+                           [&](int i) { return s_rho[c][cy + L::cy(i)][cx + L::cx(i)]; }, r[c])
+                     : T(0);
+    }
+    site_potential<T, NC>(p, r, lap, mu, h);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) s_h[c][qy][qx] = h[c];
+  }
+  __syncthreads();
+
+  // ---- D: force, equilibrium, forcing term, collision, store -------------
+#pragma unroll
+  for (int k = 0; k < SPT; ++k) {
+    if (!valid[k]) continue;
+    const int ly = ty + k * RS;
+    const int x = x0 + tx, y = y0 + ly;
+    T rs[NC], jx[NC], jy[NC];
+    T rt = T(0), ux = T(0), uy = T(0);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      T ax = T(0), ay = T(0);
+#pragma unroll
+      for (int i = 1; i < Q; ++i) {
+        if (L::cx(i)) ax += T(L::cx(i)) * f[k][c][i];
+        if (L::cy(i)) ay += T(L::cy(i)) * f[k][c][i];
+      }
+      jx[c] = ax;
+      jy[c] = ay;
+      rs[c] = s_rho[c][ly + 2][tx + 2];
+      if (c < n) {
+        ux += ax;
+        uy += ay;
+        rt += rs[c];
+      }
+    }
+    const T inv_rt = T(1) / rt;
+    ux *= inv_rt;
+    uy *= inv_rt;
+    const long long s = (long long)y * nx + x;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      if (c >= n) continue;
+      T Ax, Ay, Az;
+      lattice_force<2, T>([&](int i) { return s_h[c][ly + 1 + L::cy(i)][tx + 1 + L::cx(i)]; },
+                          [&](int i) { return s_rho[c][ly + 2 + L::cy(i)][tx + 2 + L::cx(i)]; }, rs[c], p, Ax,
+                          Ay, Az);
+      const T inv_rs = T(1) / rs[c];
+      collide<2, T>(f[k][c], rs[c], ux, uy, T(0), Ax, Ay, Az, jx[c] * inv_rs, jy[c] * inv_rs, T(0), p.inv_tau);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) fout[((long long)c * Q + i) * S + s] = f[k][c][i];
+    }
+  }
+}
+
+// ------------------------------------------------------------ dispatch ----
+template <typename T, int NC, int TX, int TY>
+static void launch_fused(const Ctx& c, const void* fin, void* fout) {
+  constexpr int NT = 256;
+  const int nbx = int((c.prm.nx + TX - 1) / TX);
+  const int nby = int((c.prm.ny + TY - 1) / TY);
+  const int ntiles = nbx * nby;
+  const int per_xcd = (ntiles + kXcds - 1) / kXcds;
+  k_fused_d2q9<T, NC, TX, TY, NT><<<per_xcd * kXcds, NT, 0, c.stream>>>(
+      static_cast<const T*>(fin), static_cast<T*>(fout), c.params<T>(), nbx, ntiles, per_xcd);
+}
+
+// Tile per precision and component count: registers hold SPT * N * 9
+// populations per thread and LDS holds N rho and N h tiles.
+template <typename T, int NC>
+static FusedStepFn pick() {
+  if constexpr (sizeof(T) == 4) {
+    if constexpr (NC <= 3) return launch_fused<T, NC, 64, 16>;
+    else if constexpr (NC <= 5) return launch_fused<T, NC, 64, 8>;
+    else return launch_fused<T, NC, 64, 4>;
+  } else {
+    if constexpr (NC <= 2) return launch_fused<T, NC, 64, 8>;
+    else return launch_fused<T, NC, 64, 4>;
+  }
+}
+
+template <typename T>
+static FusedStepFn pick_n(int n) {
+  switch (n) {
+    case 1: return pick<T, 1>();
+    case 2: return pick<T, 2>();
+    case 3: return pick<T, 3>();
+    case 4: return pick<T, 4>();
+    case 5: return pick<T, 5>();
+    case 6: return pick<T, 6>();
+    case 7: return pick<T, 7>();
+    case 8: return pick<T, 8>();
+    default: return nullptr;
+  }
+}
+
+FusedStepFn fused_step_for(int lattice, int storage, int n_comp) {
+  if (lattice != 2) return nullptr;
+  return storage == 0 ? pick_n<double>(n_comp) : pick_n<float>(n_comp);
+}
+
+}  // namespace lbm

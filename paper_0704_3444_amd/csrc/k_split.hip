@@ -1,0 +1,411 @@
+// Generic kernels for every lattice and precision.
+//
+// The split step runs three kernels: k_density (rho^sigma), k_potential
+// (mu^sigma and the potential the force differentiates) and k_collide
+// (force, equilibrium, forcing term, BGK, and the write that streams by
+// pull).  It is the path for D1Q3 and D3Q19 and the cross-check of the
+// fused D2Q9 kernel.  The same kernels, instantiated in FP64, produce the
+// observables of lb_moments.  k_diag/k_diag_final form the FP64 mass and
+// momentum sums and the density health flag with a fixed reduction order.
+#include <hip/hip_runtime.h>
+
+#include "lbm_internal.hpp"
+#include "physics.hpp"
+
+namespace lbm {
+
+constexpr int kBlock = 256;
+
+struct SiteCoord {
+  int x, y, z;
+};
+
+template <typename T>
+__device__ __forceinline__ SiteCoord coord_of(long long s, const Params<T>& p) {
+  SiteCoord c;
+  c.x = int(s % p.nx);
+  long long r = s / p.nx;
+  c.y = int(r % p.ny);
+  c.z = int(r / p.ny);
+  return c;
+}
+
+template <typename T>
+__device__ __forceinline__ long long site_of(int x, int y, int z, const Params<T>& p) {
+  return (long long)x + (long long)p.nx * ((long long)y + (long long)p.ny * z);
+}
+
+// Site r + sign * v_i.
+template <int LAT, typename T>
+__device__ __forceinline__ long long neighbour(const SiteCoord& c, int i, int sign, const Params<T>& p) {
+  using L = Lattice<LAT>;
+  return site_of(wrap_add(c.x, sign * L::cx(i), p.nx), wrap_add(c.y, sign * L::cy(i), p.ny),
+                 wrap_add(c.z, sign * L::cz(i), p.nz), p);
+}
+
+template <typename S>
+__device__ __forceinline__ double to_d(S v) { return double(v); }
+
+// ---------------------------------------------------------------- init ----
+// Rest equilibrium f_i(r, 0) = w_i rho0(r), written in pull storage: slot
+// (i, r) holds the value that arrives at r + v_i.
+template <int LAT, typename T>
+__global__ void __launch_bounds__(kBlock) k_init(const double* __restrict__ rho0, T* __restrict__ f,
+                                                 Params<T> p) {
+  using L = Lattice<LAT>;
+  const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= p.S) return;
+  const SiteCoord c = coord_of(s, p);
+  for (int k = 0; k < p.n; ++k) {
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+      const long long src = neighbour<LAT>(c, i, +1, p);
+      f[((long long)k * L::Q + i) * p.S + s] = T(L::w(i) * rho0[(long long)k * p.S + src]);
+    }
+  }
+}
+
+// ------------------------------------------------------------- density ----
+// rho^sigma(r) = sum_i f_i(r): the population at r in direction i is the
+// slot (i, r - v_i).  TO is the output type (T for the step, double for the
+// observables).
+template <int LAT, typename T, typename TO>
+__global__ void __launch_bounds__(kBlock) k_density(const T* __restrict__ f, TO* __restrict__ rho,
+                                                    Params<T> p) {
+  using L = Lattice<LAT>;
+  const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= p.S) return;
+  const SiteCoord c = coord_of(s, p);
+  long long src[L::Q];
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) src[i] = neighbour<LAT>(c, i, -1, p);
+  for (int k = 0; k < p.n; ++k) {
+    TO acc = TO(0);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) acc += TO(f[((long long)k * L::Q + i) * p.S + src[i]]);
+    rho[(long long)k * p.S + s] = acc;
+  }
+}
+
+// ----------------------------------------------------------- potential ----
+// lap rho^sigma = 6 sum_i w_i (rho^sigma(r + v_i) - rho^sigma(r)), then the
+// chemical potentials and the potential h^sigma the force differentiates.
+template <int LAT, typename T>
+__global__ void __launch_bounds__(kBlock) k_potential(const T* __restrict__ rho, T* __restrict__ mu_out,
+                                                      T* __restrict__ h_out, Params<T> p) {
+  using L = Lattice<LAT>;
+  const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= p.S) return;
+  const SiteCoord c = coord_of(s, p);
+  long long nb[L::Q];
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) nb[i] = neighbour<LAT>(c, i, +1, p);
+  T r[kMaxComp], lap[kMaxComp], mu[kMaxComp], h[kMaxComp];
+#pragma unroll
+  for (int k = 0; k < kMaxComp; ++k) {
+    r[k] = T(1);
+    lap[k] = T(0);
+    if (k < p.n) {
+      const T* rk = rho + (long long)k * p.S;
+      r[k] = rk[s];
+      lap[k] = lattice_laplacian<LAT, T>([&](int i) { return rk[nb[i]]; }, r[k]);
+    }
+  }
+  site_potential<T, kMaxComp>(p, r, lap, mu, h);
+  for (int k = 0; k < p.n; ++k) {
+    if (mu_out) mu_out[(long long)k * p.S + s] = mu[k];
+    h_out[(long long)k * p.S + s] = h[k];
+  }
+}
+
+// ------------------------------------------------------------- collide ----
+template <int LAT, typename T>
+__global__ void __launch_bounds__(kBlock) k_collide(const T* __restrict__ fin, T* __restrict__ fout,
+                                                    const T* __restrict__ rho, const T* __restrict__ h,
+                                                    Params<T> p) {
+  using L = Lattice<LAT>;
+  constexpr int Q = L::Q;
+  const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= p.S) return;
+  const SiteCoord c = coord_of(s, p);
+  long long src[Q], nb[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    src[i] = neighbour<LAT>(c, i, -1, p);
+    nb[i] = neighbour<LAT>(c, i, +1, p);
+  }
+  // barycentric velocity u = sum_sigma j^sigma / sum_sigma rho^sigma
+  T jx[kMaxComp], jy[kMaxComp], jz[kMaxComp];
+  T rt = T(0), ux = T(0), uy = T(0), uz = T(0);
+  for (int k = 0; k < p.n; ++k) {
+    const T* fk = fin + (long long)k * Q * p.S;
+    T ax = T(0), ay = T(0), az = T(0);
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      const T fi = fk[(long long)i * p.S + src[i]];
+      if (L::cx(i)) ax += T(L::cx(i)) * fi;
+      if (L::cy(i)) ay += T(L::cy(i)) * fi;
+      if (L::cz(i)) az += T(L::cz(i)) * fi;
+    }
+    jx[k] = ax;
+    jy[k] = ay;
+    jz[k] = az;
+    ux += ax;
+    uy += ay;
+    uz += az;
+    rt += rho[(long long)k * p.S + s];
+  }
+  const T inv_rt = T(1) / rt;
+  ux *= inv_rt;
+  uy *= inv_rt;
+  uz *= inv_rt;
+  for (int k = 0; k < p.n; ++k) {
+    const T* fk = fin + (long long)k * Q * p.S;
+    const T rs = rho[(long long)k * p.S + s];
+    T f[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[i] = fk[(long long)i * p.S + src[i]];
+    const T* hk = h + (long long)k * p.S;
+    const T* rk = rho + (long long)k * p.S;
+    T Ax, Ay, Az;
+    lattice_force<LAT, T>([&](int i) { return hk[nb[i]]; }, [&](int i) { return rk[nb[i]]; }, rs, p, Ax, Ay,
+                          Az);
+    const T inv_rs = T(1) / rs;
+    collide<LAT, T>(f, rs, ux, uy, uz, Ax, Ay, Az, jx[k] * inv_rs, jy[k] * inv_rs, jz[k] * inv_rs,
+                    p.inv_tau);
+    T* ok = fout + (long long)k * Q * p.S;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) ok[(long long)i * p.S + s] = f[i];
+  }
+}
+
+// --------------------------------------------------------- observables ----
+// U = u + (1/2) sum A / rho, and the pressure tensor
+//   P_ab = [p0 - kappa sum_s (rho lap rho + |grad rho|^2 / 2)] d_ab
+//        + kappa sum_s d_a rho d_b rho,     p0 = sum_s rho mu0 - psi,
+// all in FP64 from the stored populations (converted exactly to FP64).
+template <int LAT, typename T>
+__global__ void __launch_bounds__(kBlock) k_observe(const T* __restrict__ fin, const double* __restrict__ rho,
+                                                    const double* __restrict__ h, double* __restrict__ U,
+                                                    double* __restrict__ P, Params<double> p) {
+  using L = Lattice<LAT>;
+  constexpr int Q = L::Q, D = L::D;
+  const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= p.S) return;
+  const SiteCoord c = coord_of(s, p);
+  long long src[Q], nb[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    src[i] = neighbour<LAT>(c, i, -1, p);
+    nb[i] = neighbour<LAT>(c, i, +1, p);
+  }
+  double rt = 0, jt[3] = {0, 0, 0}, At[3] = {0, 0, 0};
+  double r[kMaxComp], lap[kMaxComp], g[kMaxComp][3];
+  for (int k = 0; k < kMaxComp; ++k) {
+    r[k] = 1.0;
+    lap[k] = 0.0;
+    g[k][0] = g[k][1] = g[k][2] = 0.0;
+  }
+  for (int k = 0; k < p.n; ++k) {
+    const T* fk = fin + (long long)k * Q * p.S;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      const double fi = to_d(fk[(long long)i * p.S + src[i]]);
+      jt[0] += L::cx(i) * fi;
+      jt[1] += L::cy(i) * fi;
+      jt[2] += L::cz(i) * fi;
+    }
+    const double* rk = rho + (long long)k * p.S;
+    r[k] = rk[s];
+    rt += r[k];
+    const double* hk = h + (long long)k * p.S;
+    double Ax, Ay, Az;
+    lattice_force<LAT, double>([&](int i) { return hk[nb[i]]; }, [&](int i) { return rk[nb[i]]; }, r[k], p,
+                               Ax, Ay, Az);
+    At[0] += Ax;
+    At[1] += Ay;
+    At[2] += Az;
+    double acc = 0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      const double rv = rk[nb[i]];
+      acc += L::w(i) * (rv - r[k]);
+      g[k][0] += 3.0 * L::w(i) * L::cx(i) * rv;
+      g[k][1] += 3.0 * L::w(i) * L::cy(i) * rv;
+      g[k][2] += 3.0 * L::w(i) * L::cz(i) * rv;
+    }
+    lap[k] = 6.0 * acc;
+  }
+  for (int a = 0; a < D; ++a) U[(long long)a * p.S + s] = (jt[a] + 0.5 * At[a]) / rt;
+  // bulk pressure from the potential without the gradient term
+  Params<double> pb = p;
+  pb.kappa = 0.0;
+  double zero[kMaxComp], mu0[kMaxComp], h0[kMaxComp];
+  for (int k = 0; k < kMaxComp; ++k) zero[k] = 0.0;
+  site_potential<double, kMaxComp>(pb, r, zero, mu0, h0);
+  double p0 = -site_psi<double, kMaxComp>(pb, r), iso = 0.0;
+  for (int k = 0; k < p.n; ++k) {
+    p0 += r[k] * mu0[k];
+    iso += r[k] * lap[k] + 0.5 * (g[k][0] * g[k][0] + g[k][1] * g[k][1] + g[k][2] * g[k][2]);
+  }
+  int m = 0;
+  for (int a = 0; a < D; ++a)
+    for (int b = a; b < D; ++b) {
+      double gg = 0;
+      for (int k = 0; k < p.n; ++k) gg += g[k][a] * g[k][b];
+      double v = p.kappa * gg;
+      if (a == b) v += p0 - p.kappa * iso;
+      P[(long long)m * p.S + s] = v;
+      ++m;
+    }
+}
+
+// Populations at the current time, FP64 [N][Q][S].
+template <int LAT, typename T>
+__global__ void __launch_bounds__(kBlock) k_unpull(const T* __restrict__ fin, double* __restrict__ out,
+                                                   Params<T> p) {
+  using L = Lattice<LAT>;
+  const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= p.S) return;
+  const SiteCoord c = coord_of(s, p);
+  for (int k = 0; k < p.n; ++k)
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+      const long long idx = ((long long)k * L::Q + i) * p.S;
+      out[idx + s] = to_d(fin[idx + neighbour<LAT>(c, i, -1, p)]);
+    }
+}
+
+// ---------------------------------------------------------- diagnostics ----
+// Per block: FP64 sums of rho^sigma (N values), of the first moments over
+// components (D values), and a flag (1 if any rho^sigma is NaN or <= 0).
+// Wave64 butterfly reduction, then the waves of the block in index order.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <int LAT, typename T>
+__global__ void __launch_bounds__(kBlock) k_diag(const T* __restrict__ fin, double* __restrict__ partial,
+                                                 Params<T> p) {
+  using L = Lattice<LAT>;
+  constexpr int Q = L::Q, D = L::D;
+  constexpr int K = kMaxComp + D + 1;
+  double acc[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) acc[q] = 0.0;
+  for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < p.S;
+       s += (long long)gridDim.x * blockDim.x) {
+    const SiteCoord c = coord_of(s, p);
+    long long src[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) src[i] = neighbour<LAT>(c, i, -1, p);
+#pragma unroll
+    for (int k = 0; k < kMaxComp; ++k) {
+      if (k < p.n) {
+        const T* fk = fin + (long long)k * Q * p.S;
+        double r = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          const double fi = to_d(fk[(long long)i * p.S + src[i]]);
+          r += fi;
+          jx += L::cx(i) * fi;
+          jy += L::cy(i) * fi;
+          jz += L::cz(i) * fi;
+        }
+        acc[k] += r;
+        acc[kMaxComp] += jx;
+        if (D > 1) acc[kMaxComp + 1] += jy;
+        if (D > 2) acc[kMaxComp + 2] += jz;
+        if (!(r > 0.0) || !(r < 1e300)) acc[K - 1] = 1.0;
+      }
+    }
+  }
+  __shared__ double red[kBlock / 64][K];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < K - 1; ++q) {
+    const double v = wave_sum(acc[q]);
+    if (lane == 0) red[wave][q] = v;
+  }
+  // the flag is a maximum, not a sum
+  double fl = acc[K - 1];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) fl = fmax(fl, __shfl_xor(fl, off, 64));
+  if (lane == 0) red[wave][K - 1] = fl;
+  __syncthreads();
+  if (threadIdx.x < K) {
+    double v = 0.0;
+    for (int wv = 0; wv < kBlock / 64; ++wv)
+      v = (threadIdx.x == K - 1) ? fmax(v, red[wv][threadIdx.x]) : v + red[wv][threadIdx.x];
+    partial[(long long)blockIdx.x * K + threadIdx.x] = v;
+  }
+}
+
+// Sum the block partials in block order (one thread per quantity), store
+// the totals, and OR the flag into the sticky health flag.
+__global__ void k_diag_final(const double* __restrict__ partial, int nblocks, int K,
+                             double* __restrict__ out, int* __restrict__ flag) {
+  const int q = threadIdx.x;
+  if (q >= K) return;
+  double v = 0.0;
+  for (int b = 0; b < nblocks; ++b) {
+    const double x = partial[(long long)b * K + q];
+    v = (q == K - 1) ? fmax(v, x) : v + x;
+  }
+  out[q] = v;
+  if (q == K - 1 && v != 0.0) flag[0] = 1;
+}
+
+// ------------------------------------------------------------ launchers ----
+static inline unsigned grid_for(long long S) { return unsigned((S + kBlock - 1) / kBlock); }
+
+template <int LAT, typename T>
+struct SplitOps {
+  static void init(const Ctx& c, const double* rho0_dev, void* f) {
+    k_init<LAT, T><<<grid_for(c.S), kBlock, 0, c.stream>>>(rho0_dev, static_cast<T*>(f), c.params<T>());
+  }
+  static void step(const Ctx& c, const void* fin, void* fout) {
+    const Params<T>& p = c.params<T>();
+    T* rho = static_cast<T*>(c.rho_scratch);
+    T* h = static_cast<T*>(c.h_scratch);
+    k_density<LAT, T, T><<<grid_for(c.S), kBlock, 0, c.stream>>>(static_cast<const T*>(fin), rho, p);
+    k_potential<LAT, T><<<grid_for(c.S), kBlock, 0, c.stream>>>(rho, nullptr, h, p);
+    k_collide<LAT, T><<<grid_for(c.S), kBlock, 0, c.stream>>>(static_cast<const T*>(fin),
+                                                               static_cast<T*>(fout), rho, h, p);
+  }
+  static void observe(const Ctx& c, const void* fin, double* rho, double* mu, double* h, double* U,
+                      double* P) {
+    k_density<LAT, T, double><<<grid_for(c.S), kBlock, 0, c.stream>>>(static_cast<const T*>(fin), rho,
+                                                                       c.params<T>());
+    k_potential<LAT, double><<<grid_for(c.S), kBlock, 0, c.stream>>>(rho, mu, h, c.pd);
+    k_observe<LAT, T><<<grid_for(c.S), kBlock, 0, c.stream>>>(static_cast<const T*>(fin), rho, h, U, P, c.pd);
+  }
+  static void unpull(const Ctx& c, const void* fin, double* out) {
+    k_unpull<LAT, T><<<grid_for(c.S), kBlock, 0, c.stream>>>(static_cast<const T*>(fin), out, c.params<T>());
+  }
+  static void diag(const Ctx& c, const void* fin) {
+    constexpr int K = kMaxComp + Lattice<LAT>::D + 1;
+    k_diag<LAT, T><<<c.diag_blocks, kBlock, 0, c.stream>>>(static_cast<const T*>(fin), c.diag_partial,
+                                                             c.params<T>());
+    k_diag_final<<<1, 64, 0, c.stream>>>(c.diag_partial, c.diag_blocks, K, c.diag_out, c.health_flag);
+  }
+};
+
+template <typename T>
+static const SplitTable& table_for_lattice(int lattice) {
+  static const SplitTable t1 = {SplitOps<1, T>::init, SplitOps<1, T>::step, SplitOps<1, T>::observe,
+                                SplitOps<1, T>::unpull, SplitOps<1, T>::diag};
+  static const SplitTable t2 = {SplitOps<2, T>::init, SplitOps<2, T>::step, SplitOps<2, T>::observe,
+                                SplitOps<2, T>::unpull, SplitOps<2, T>::diag};
+  static const SplitTable t3 = {SplitOps<3, T>::init, SplitOps<3, T>::step, SplitOps<3, T>::observe,
+                                SplitOps<3, T>::unpull, SplitOps<3, T>::diag};
+  return lattice == 1 ? t1 : (lattice == 2 ? t2 : t3);
+}
+
+const SplitTable& split_table(int lattice, int storage) {
+  return storage == 0 ? table_for_lattice<double>(lattice) : table_for_lattice<float>(lattice);
+}
+
+}  // namespace lbm

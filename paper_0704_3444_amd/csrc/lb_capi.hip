@@ -1,0 +1,410 @@
+// C ABI of the library (declared in include/lb.h): parameter validation,
+// workspace layout, the step loop, observables and checkpoints.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lb.h"
+#include "lbm_internal.hpp"
+
+using lbm::Ctx;
+
+struct lb_ctx {
+  Ctx c;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(LB_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(call)                                  \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return hip_fail(e_, #call);  \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int lattice_dims(int lattice, int* Q, int* D) {
+  switch (lattice) {
+    case LB_D1Q3: *Q = 3; *D = 1; return 0;
+    case LB_D2Q9: *Q = 9; *D = 2; return 0;
+    case LB_D3Q19: *Q = 19; *D = 3; return 0;
+    default: return -1;
+  }
+}
+
+int validate(const lb_params* p, std::string* why) {
+  auto bad = [&](const std::string& m) { *why = m; return LB_EINVAL; };
+  if (!p) return bad("params is NULL");
+  int Q, D;
+  if (lattice_dims(p->lattice, &Q, &D)) return bad("unknown lattice");
+  if (p->n_comp < 1 || p->n_comp > LB_MAX_COMP) return bad("n_comp must be in 1..8");
+  if (p->storage != LB_F64 && p->storage != LB_F32) return bad("unknown storage");
+  if (p->force_form != LB_FORCE_LOG && p->force_form != LB_FORCE_EXPANDED) return bad("unknown force_form");
+  if (p->path < LB_PATH_AUTO || p->path > LB_PATH_SPLIT) return bad("unknown path");
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) return bad("box sides must be >= 1");
+  if (p->nx > (1 << 30) || p->ny > (1 << 30) || p->nz > (1 << 30)) return bad("box side too large");
+  if (p->lattice == LB_D1Q3 && (p->ny != 1 || p->nz != 1)) return bad("D1Q3 needs ny = nz = 1");
+  if (p->lattice == LB_D2Q9 && p->nz != 1) return bad("D2Q9 needs nz = 1");
+  const double S = double(p->nx) * double(p->ny) * double(p->nz);
+  if (S * p->n_comp * Q > 4.0e12) return bad("lattice too large");
+  const int N = p->n_comp;
+  for (int k = 0; k < N; ++k) {
+    if (!std::isfinite(p->tau[k]) || !(p->tau[k] > 0.5)) return bad("tau must be > 1/2");
+    if (p->tau[k] != p->tau[0])
+      return bad("all tau^sigma must be equal (one total-fluid LB equation needs one tau)");
+    if (!std::isfinite(p->m[k]) || !(p->m[k] > 0.0)) return bad("m^sigma must be > 0");
+  }
+  if (!std::isfinite(p->theta) || !(p->theta > 0.0)) return bad("theta must be > 0");
+  if (!std::isfinite(p->kappa) || !(p->kappa >= 0.0)) return bad("kappa must be >= 0");
+  for (int a = 0; a < N; ++a)
+    for (int b = 0; b < N; ++b) {
+      const double v = p->chi[a * LB_MAX_COMP + b];
+      if (!std::isfinite(v)) return bad("chi must be finite");
+      if (v != p->chi[b * LB_MAX_COMP + a]) return bad("chi must be symmetric");
+      if (a == b && v != 0.0) return bad("chi^{sigma sigma} must be 0");
+    }
+  if (p->check_every < 0) return bad("check_every must be >= 0");
+  return LB_OK;
+}
+
+struct Layout {
+  size_t f, rho, h, diag_partial, diag_out, flag, total;
+  int diag_blocks;
+};
+
+Layout layout_of(const lb_params* p) {
+  int Q, D;
+  lattice_dims(p->lattice, &Q, &D);
+  const size_t S = size_t(p->nx) * size_t(p->ny) * size_t(p->nz);
+  const size_t rb = p->storage == LB_F64 ? 8 : 4;
+  Layout L;
+  const size_t fbytes = align_up(size_t(p->n_comp) * Q * S * rb);
+  const size_t rbytes = align_up(size_t(p->n_comp) * S * rb);
+  const size_t blocks = (S + 255) / 256;
+  L.diag_blocks = int(blocks < 1024 ? blocks : 1024);
+  const int K = LB_MAX_COMP + D + 1;
+  L.f = 0;
+  L.rho = 2 * fbytes;
+  L.h = L.rho + rbytes;
+  L.diag_partial = L.h + rbytes;
+  L.diag_out = L.diag_partial + align_up(size_t(L.diag_blocks) * K * sizeof(double));
+  L.flag = L.diag_out + align_up(K * sizeof(double));
+  L.total = L.flag + kAlign;
+  return L;
+}
+
+template <typename T>
+void fill_params(const lb_params* p, lbm::Params<T>* q) {
+  std::memset(q, 0, sizeof(*q));
+  q->n = p->n_comp;
+  q->log_form = p->force_form == LB_FORCE_LOG ? 1 : 0;
+  q->nx = int(p->nx);
+  q->ny = int(p->ny);
+  q->nz = int(p->nz);
+  q->S = (long long)p->nx * p->ny * p->nz;
+  q->inv_tau = T(1.0 / p->tau[0]);
+  q->cforce = T(1.0 - 0.5 / p->tau[0]);
+  q->theta = T(p->theta);
+  q->kappa = T(p->kappa);
+  for (int k = 0; k < lbm::kMaxComp; ++k) q->inv_m[k] = T(k < p->n_comp ? 1.0 / p->m[k] : 1.0);
+  for (int a = 0; a < lbm::kMaxComp; ++a)
+    for (int b = 0; b < lbm::kMaxComp; ++b)
+      q->chi[a * lbm::kMaxComp + b] =
+          T(a < p->n_comp && b < p->n_comp ? p->chi[a * LB_MAX_COMP + b] : 0.0);
+}
+
+// Step the context's state n times on its stream.
+int advance(Ctx& c, int64_t n) {
+  const lbm::SplitTable& st = lbm::split_table(c.prm.lattice, c.prm.storage);
+  lbm::FusedStepFn fused =
+      c.path == LB_PATH_FUSED ? lbm::fused_step_for(c.prm.lattice, c.prm.storage, c.prm.n_comp) : nullptr;
+  for (int64_t k = 0; k < n; ++k) {
+    void* fin = c.f[c.cur];
+    void* fout = c.f[1 - c.cur];
+    if (fused)
+      fused(c, fin, fout);
+    else
+      st.step(c, fin, fout);
+    c.cur = 1 - c.cur;
+    c.t += 1;
+    if (c.prm.check_every > 0 && c.t % c.prm.check_every == 0) st.diag(c, c.f[c.cur]);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return LB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lb_workspace_bytes(const lb_params* p) {
+  std::string why;
+  if (validate(p, &why) != LB_OK) {
+    g_last_error = why;
+    return 0;
+  }
+  return layout_of(p).total;
+}
+
+int lb_init(const lb_params* p, const double* rho0, void* workspace, size_t workspace_bytes, lb_ctx** out) {
+  std::string why;
+  if (!out) return fail(LB_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (validate(p, &why) != LB_OK) return fail(LB_EINVAL, why);
+  if (!rho0) return fail(LB_EINVAL, "rho0 is NULL");
+  const size_t S = size_t(p->nx) * size_t(p->ny) * size_t(p->nz);
+  for (size_t k = 0; k < size_t(p->n_comp) * S; ++k)
+    if (!std::isfinite(rho0[k]) || !(rho0[k] > 0.0))
+      return fail(LB_EINVAL, "rho0 must be finite and > 0 at every site (index " + std::to_string(k) + ")");
+  const Layout L = layout_of(p);
+  if (workspace) {
+    if (workspace_bytes < L.total)
+      return fail(LB_ENOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+      return fail(LB_EINVAL, "workspace must be 256-byte aligned");
+  }
+  lb_ctx* h = new (std::nothrow) lb_ctx;
+  if (!h) return fail(LB_ENOMEM, "host allocation failed");
+  Ctx& c = h->c;
+  c.prm = *p;
+  lattice_dims(p->lattice, &c.Q, &c.D);
+  c.S = (long long)S;
+  c.real_bytes = p->storage == LB_F64 ? 8 : 4;
+  c.stream = static_cast<hipStream_t>(p->stream);
+  if (workspace) {
+    c.ws = workspace;
+    c.ws_bytes = workspace_bytes;
+  } else {
+    hipError_t e = hipMalloc(&c.ws, L.total);
+    if (e != hipSuccess) {
+      delete h;
+      return fail(LB_ENOMEM, std::string("hipMalloc of workspace: ") + hipGetErrorString(e));
+    }
+    c.owns_ws = true;
+    c.ws_bytes = L.total;
+  }
+  char* base = static_cast<char*>(c.ws);
+  const size_t fbytes = size_t(p->n_comp) * c.Q * S * c.real_bytes;
+  c.f[0] = base + L.f;
+  c.f[1] = base + L.f + align_up(fbytes);
+  c.rho_scratch = base + L.rho;
+  c.h_scratch = base + L.h;
+  c.diag_partial = reinterpret_cast<double*>(base + L.diag_partial);
+  c.diag_out = reinterpret_cast<double*>(base + L.diag_out);
+  c.health_flag = reinterpret_cast<int*>(base + L.flag);
+  c.diag_blocks = L.diag_blocks;
+  fill_params(p, &c.pf);
+  fill_params(p, &c.pd);
+
+  lbm::FusedStepFn fused = lbm::fused_step_for(p->lattice, p->storage, p->n_comp);
+  if (p->path == LB_PATH_FUSED && !fused) {
+    lb_free(h);
+    return fail(LB_ENOTSUP, "no fused kernel for this lattice / storage / N");
+  }
+  c.path = (p->path == LB_PATH_SPLIT || !fused) ? LB_PATH_SPLIT : LB_PATH_FUSED;
+
+  double* rho_dev = nullptr;
+  hipError_t e = hipMalloc(&rho_dev, size_t(p->n_comp) * S * sizeof(double));
+  if (e != hipSuccess) {
+    lb_free(h);
+    return fail(LB_ENOMEM, std::string("hipMalloc of rho0 staging: ") + hipGetErrorString(e));
+  }
+  e = hipMemcpyAsync(rho_dev, rho0, size_t(p->n_comp) * S * sizeof(double), hipMemcpyHostToDevice, c.stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c.health_flag, 0, sizeof(int), c.stream);
+  if (e == hipSuccess) {
+    lbm::split_table(p->lattice, p->storage).init(c, rho_dev, c.f[0]);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
+  (void)hipFree(rho_dev);
+  if (e != hipSuccess) {
+    lb_free(h);
+    return hip_fail(e, "lb_init");
+  }
+  c.cur = 0;
+  c.t = 0;
+  *out = h;
+  return LB_OK;
+}
+
+int lb_step(lb_ctx* h, int64_t nsteps) {
+  if (!h) return fail(LB_EINVAL, "ctx is NULL");
+  if (nsteps < 0) return fail(LB_EINVAL, "nsteps must be >= 0");
+  return advance(h->c, nsteps);
+}
+
+int lb_moments(lb_ctx* h, double* rho, double* U, double* mu, double* P, double* mass, double* mom,
+               int64_t* step) {
+  if (!h) return fail(LB_EINVAL, "ctx is NULL");
+  Ctx& c = h->c;
+  const int N = c.prm.n_comp, D = c.D;
+  const size_t S = size_t(c.S);
+  const lbm::SplitTable& st = lbm::split_table(c.prm.lattice, c.prm.storage);
+  double *d_rho = nullptr, *d_mu = nullptr, *d_h = nullptr, *d_U = nullptr, *d_P = nullptr;
+  const bool fields = rho || U || mu || P;
+  int rc = LB_OK;
+  if (fields) {
+    const size_t nP = size_t(D) * (D + 1) / 2;
+    hipError_t e = hipMalloc(&d_rho, N * S * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&d_mu, N * S * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&d_h, N * S * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&d_U, D * S * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&d_P, nP * S * sizeof(double));
+    if (e != hipSuccess) {
+      rc = fail(LB_ENOMEM, std::string("lb_moments scratch: ") + hipGetErrorString(e));
+    } else {
+      st.observe(c, c.f[c.cur], d_rho, d_mu, d_h, d_U, d_P);
+      e = hipGetLastError();
+      if (e == hipSuccess && rho) e = hipMemcpyAsync(rho, d_rho, N * S * 8, hipMemcpyDeviceToHost, c.stream);
+      if (e == hipSuccess && mu) e = hipMemcpyAsync(mu, d_mu, N * S * 8, hipMemcpyDeviceToHost, c.stream);
+      if (e == hipSuccess && U) e = hipMemcpyAsync(U, d_U, D * S * 8, hipMemcpyDeviceToHost, c.stream);
+      if (e == hipSuccess && P) e = hipMemcpyAsync(P, d_P, nP * S * 8, hipMemcpyDeviceToHost, c.stream);
+      if (e != hipSuccess) rc = hip_fail(e, "lb_moments");
+    }
+  }
+  std::vector<double> out(lbm::kMaxComp + D + 1, 0.0);
+  int flag = 0;
+  if (rc == LB_OK) {
+    st.diag(c, c.f[c.cur]);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(out.data(), c.diag_out, out.size() * sizeof(double), hipMemcpyDeviceToHost, c.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&flag, c.health_flag, sizeof(int), hipMemcpyDeviceToHost, c.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
+    if (e != hipSuccess) rc = hip_fail(e, "lb_moments");
+  } else {
+    (void)hipStreamSynchronize(c.stream);
+  }
+  (void)hipFree(d_rho);
+  (void)hipFree(d_mu);
+  (void)hipFree(d_h);
+  (void)hipFree(d_U);
+  (void)hipFree(d_P);
+  if (rc != LB_OK) return rc;
+  if (mass)
+    for (int k = 0; k < N; ++k) mass[k] = out[k];
+  if (mom)
+    for (int a = 0; a < D; ++a) mom[a] = out[lbm::kMaxComp + a];
+  if (step) *step = c.t;
+  if (flag) return fail(LB_ENUMERIC, "a component density became non-finite or <= 0");
+  return LB_OK;
+}
+
+int lb_get_f(lb_ctx* h, double* f) {
+  if (!h || !f) return fail(LB_EINVAL, "NULL argument");
+  Ctx& c = h->c;
+  const size_t n = size_t(c.prm.n_comp) * c.Q * size_t(c.S);
+  double* d = nullptr;
+  HIP_TRY(hipMalloc(&d, n * sizeof(double)));
+  lbm::split_table(c.prm.lattice, c.prm.storage).unpull(c, c.f[c.cur], d);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(f, d, n * sizeof(double), hipMemcpyDeviceToHost, c.stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
+  (void)hipFree(d);
+  if (e != hipSuccess) return hip_fail(e, "lb_get_f");
+  return LB_OK;
+}
+
+size_t lb_state_bytes(const lb_ctx* h) {
+  if (!h) return 0;
+  const Ctx& c = h->c;
+  return size_t(c.prm.n_comp) * c.Q * size_t(c.S) * c.real_bytes + sizeof(int64_t);
+}
+
+int lb_get_state(lb_ctx* h, void* host, size_t bytes) {
+  if (!h || !host) return fail(LB_EINVAL, "NULL argument");
+  Ctx& c = h->c;
+  const size_t need = lb_state_bytes(h);
+  if (bytes < need) return fail(LB_EINVAL, "buffer too small for the state");
+  HIP_TRY(hipMemcpyAsync(host, c.f[c.cur], need - sizeof(int64_t), hipMemcpyDeviceToHost, c.stream));
+  HIP_TRY(hipStreamSynchronize(c.stream));
+  std::memcpy(static_cast<char*>(host) + need - sizeof(int64_t), &c.t, sizeof(int64_t));
+  return LB_OK;
+}
+
+int lb_set_state(lb_ctx* h, const void* host, size_t bytes) {
+  if (!h || !host) return fail(LB_EINVAL, "NULL argument");
+  Ctx& c = h->c;
+  const size_t need = lb_state_bytes(h);
+  if (bytes != need) return fail(LB_EINVAL, "state size does not match this context");
+  HIP_TRY(hipMemcpyAsync(c.f[c.cur], host, need - sizeof(int64_t), hipMemcpyHostToDevice, c.stream));
+  HIP_TRY(hipStreamSynchronize(c.stream));
+  std::memcpy(&c.t, static_cast<const char*>(host) + need - sizeof(int64_t), sizeof(int64_t));
+  return LB_OK;
+}
+
+int lb_lattice_tables(int32_t lattice, int32_t* Q, int32_t* D, int32_t* v, double* w) {
+  int q, d;
+  if (lattice_dims(lattice, &q, &d)) return fail(LB_EINVAL, "unknown lattice");
+  if (Q) *Q = q;
+  if (D) *D = d;
+  for (int i = 0; i < q; ++i) {
+    int cx, cy, cz;
+    double wi;
+    switch (lattice) {
+      case LB_D1Q3:
+        cx = lbm::Lattice<1>::cx(i); cy = lbm::Lattice<1>::cy(i); cz = lbm::Lattice<1>::cz(i);
+        wi = lbm::Lattice<1>::w(i);
+        break;
+      case LB_D2Q9:
+        cx = lbm::Lattice<2>::cx(i); cy = lbm::Lattice<2>::cy(i); cz = lbm::Lattice<2>::cz(i);
+        wi = lbm::Lattice<2>::w(i);
+        break;
+      default:
+        cx = lbm::Lattice<3>::cx(i); cy = lbm::Lattice<3>::cy(i); cz = lbm::Lattice<3>::cz(i);
+        wi = lbm::Lattice<3>::w(i);
+        break;
+    }
+    if (v) {
+      v[3 * i] = cx;
+      v[3 * i + 1] = cy;
+      v[3 * i + 2] = cz;
+    }
+    if (w) w[i] = wi;
+  }
+  return LB_OK;
+}
+
+int lb_path_in_use(const lb_ctx* h) { return h ? h->c.path : fail(LB_EINVAL, "ctx is NULL"); }
+
+void lb_free(lb_ctx* h) {
+  if (!h) return;
+  Ctx& c = h->c;
+  (void)hipStreamSynchronize(c.stream);
+  if (c.owns_ws && c.ws) (void)hipFree(c.ws);
+  delete h;
+}
+
+const char* lb_strerror(int code) {
+  switch (code) {
+    case LB_OK: return "success";
+    case LB_EINVAL: return "invalid argument";
+    case LB_ENOMEM: return "out of memory";
+    case LB_ENOTSUP: return "not supported";
+    case LB_EDEVICE: return "HIP runtime error";
+    case LB_ENUMERIC: return "non-finite or non-positive density";
+    default: return "unknown status";
+  }
+}
+
+const char* lb_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,63 @@
+// Internal interface between the C ABI (lb_capi.hip) and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lb.h"
+#include "physics.hpp"
+
+namespace lbm {
+
+// Context behind the opaque lb_ctx handle.
+struct Ctx {
+  lb_params prm;
+  int Q = 0, D = 0;
+  long long S = 0;
+  size_t real_bytes = 0;   // bytes per stored population
+  hipStream_t stream = nullptr;
+
+  void* ws = nullptr;      // workspace base (device)
+  bool owns_ws = false;
+  size_t ws_bytes = 0;
+
+  void* f[2] = {nullptr, nullptr};  // population copies, pull storage
+  int cur = 0;                      // f[cur] holds the current state
+  void* rho_scratch = nullptr;      // [N][S] working precision (split path)
+  void* h_scratch = nullptr;        // [N][S] working precision (split path)
+  double* diag_partial = nullptr;   // [diag_blocks][K]
+  double* diag_out = nullptr;       // [K]: masses (kMaxComp), momentum (D), flag
+  int* health_flag = nullptr;       // sticky: 1 once a bad density was seen
+  int diag_blocks = 0;
+
+  int64_t t = 0;
+  int path = LB_PATH_SPLIT;
+  int fused_tile = 0;               // tile choice of the fused kernel
+
+  Params<float> pf;
+  Params<double> pd;
+
+  template <typename T>
+  const Params<T>& params() const;
+};
+
+template <>
+inline const Params<float>& Ctx::params<float>() const { return pf; }
+template <>
+inline const Params<double>& Ctx::params<double>() const { return pd; }
+
+struct SplitTable {
+  void (*init)(const Ctx&, const double* rho0_dev, void* f);
+  void (*step)(const Ctx&, const void* fin, void* fout);
+  void (*observe)(const Ctx&, const void* fin, double* rho, double* mu, double* h, double* U, double* P);
+  void (*unpull)(const Ctx&, const void* fin, double* out);
+  void (*diag)(const Ctx&, const void* fin);
+};
+
+const SplitTable& split_table(int lattice, int storage);
+
+// Fused single-kernel step; nullptr when no fused kernel exists for the
+// combination.
+using FusedStepFn = void (*)(const Ctx&, const void* fin, void* fout);
+FusedStepFn fused_step_for(int lattice, int storage, int n_comp);
+
+}  // namespace lbm

@@ -1,0 +1,197 @@
+// Per-site pieces of the method, shared by every kernel of the library.
+//
+//   chemical potential  Eq. (lgf) of Sec. IV, per mer, plus -kappa lap rho
+//   force               Eq. (definef), either line
+//   equilibrium         moments of Sec. III (second-order polynomial)
+//   forcing term        moments Eqs. (ff1)-(ff3)
+//   collision           Eq. (ssLB), BGK
+//
+// Populations live in "pull" storage: slot (sigma, i, r) holds the
+// post-collision value f*_i computed at site r, so the population that sits
+// at site r at the next step is the one stored at r - v_i.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lattice.hpp"
+
+namespace lbm {
+
+constexpr int kMaxComp = 8;
+
+// Arithmetic parameters of one run, in the working precision T.
+template <typename T>
+struct Params {
+  int n;          // number of components N
+  int log_form;   // 1: A = -c rho grad(mu - ln(rho)/3); 0: A = -c (rho grad mu - grad(rho)/3)
+  int nx, ny, nz;
+  long long S;    // nx * ny * nz
+  T inv_tau;      // BGK rate 1/tau
+  T cforce;       // c = w / tau = 1 - 1/(2 tau)
+  T theta;        // temperature of the free energy
+  T kappa;        // square-gradient coefficient
+  T inv_m[kMaxComp];
+  T chi[kMaxComp * kMaxComp];  // leading dimension kMaxComp, symmetric
+};
+
+__device__ __forceinline__ float ln_(float x) { return logf(x); }
+__device__ __forceinline__ double ln_(double x) { return log(x); }
+
+// Potential that the force differentiates, at one site:
+//   mu^s = theta [ -1 + (1 + ln phi^s)/m^s - sum_t phi^t/m^t
+//                  + sum_t chi^{st} phi^t - 1/2 sum_{t,t'} chi^{tt'} phi^t phi^t' ]
+//          - kappa lap^s
+//   h^s  = mu^s - ln(rho^s)/3   (log form)   or   mu^s   (expanded form)
+// NC is the compile-time component count (n <= NC; entries >= n are ignored).
+template <typename T, int NC>
+__device__ __forceinline__ void site_potential(const Params<T>& p, const T (&rho)[NC],
+                                               const T (&lap)[NC], T (&mu)[NC], T (&h)[NC]) {
+  const int n = p.n;
+  T rt = T(0);
+#pragma unroll
+  for (int s = 0; s < NC; ++s)
+    if (s < n) rt += rho[s];
+  const T inv_rt = T(1) / rt;
+  const T ln_rt = ln_(rt);
+  T phi[NC];
+  T sum_phi_m = T(0);
+#pragma unroll
+  for (int s = 0; s < NC; ++s) {
+    phi[s] = s < n ? rho[s] * inv_rt : T(0);
+    sum_phi_m += phi[s] * p.inv_m[s];
+  }
+  T lin[NC];
+  T quad = T(0);
+#pragma unroll
+  for (int s = 0; s < NC; ++s) {
+    T acc = T(0);
+#pragma unroll
+    for (int t = 0; t < NC; ++t) acc += p.chi[s * kMaxComp + t] * phi[t];
+    lin[s] = acc;
+    quad += phi[s] * acc;
+  }
+#pragma unroll
+  for (int s = 0; s < NC; ++s) {
+    if (s < n) {
+      const T ln_rs = ln_(rho[s]);
+      const T ln_phi = ln_rs - ln_rt;
+      const T bulk = T(-1) + (T(1) + ln_phi) * p.inv_m[s] - sum_phi_m + lin[s] - T(0.5) * quad;
+      mu[s] = p.theta * bulk - p.kappa * lap[s];
+      h[s] = p.log_form ? mu[s] - ln_rs * T(1.0 / 3.0) : mu[s];
+    } else {
+      mu[s] = T(0);
+      h[s] = T(0);
+    }
+  }
+}
+
+// Free-energy density psi of Eq. (lgf) at one site (bulk part only), used by
+// the pressure diagnostic.
+template <typename T, int NC>
+__device__ __forceinline__ T site_psi(const Params<T>& p, const T (&rho)[NC]) {
+  const int n = p.n;
+  T rt = T(0);
+#pragma unroll
+  for (int s = 0; s < NC; ++s)
+    if (s < n) rt += rho[s];
+  T psi = T(0);
+#pragma unroll
+  for (int s = 0; s < NC; ++s) {
+    if (s < n) {
+      const T phi = rho[s] / rt;
+      const T num = rho[s] * p.inv_m[s];
+      psi += p.theta * num * (ln_(phi) - T(1) / p.inv_m[s]);
+#pragma unroll
+      for (int t = 0; t < NC; ++t)
+        if (t < n) psi += T(0.5) * p.theta * p.chi[s * kMaxComp + t] * rho[s] * (rho[t] / rt);
+    }
+  }
+  return psi;
+}
+
+// BGK collision of one component at one site, Eq. (ssLB):
+//   f*_i = f_i + (f^e_i - f_i)/tau + F_i
+//   f^e_i = w_i rho [1 + 3 v.u + 9/2 (v.u)^2 - 3/2 u.u]      (barycentric u)
+//   F_i   = w_i [3 v.A + 9 (v.A)(v.us) - 3 A.us]            (us = j / rho)
+// The zeroth moments of f^e and F (rho and 0) fix the rest population:
+//   f*_0 = f_0 + sum_{i>0} (f_i - f*_i).
+// Written this way the stored populations keep their exact sum up to the
+// single rounding of f*_0: each difference f_i - f*_i is exact (the two
+// values lie within a factor two of each other), whereas forming f^e_0 and
+// F_0 separately lets biased roundings of the FP32 density sum drift the
+// mass by ~1e-8 per step.
+template <int LAT, typename T>
+__device__ __forceinline__ void collide(T (&f)[Lattice<LAT>::Q], T rho, T ux, T uy, T uz, T Ax,
+                                        T Ay, T Az, T usx, T usy, T usz, T inv_tau) {
+  using L = Lattice<LAT>;
+  constexpr int Q = L::Q;
+  const T uu = ux * ux + uy * uy + uz * uz;
+  const T Aus = Ax * usx + Ay * usy + Az * usz;
+  const T base = T(1) - T(1.5) * uu;
+  T defect = T(0);
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const T w = T(L::w(i));
+    const T vu = T(L::cx(i)) * ux + T(L::cy(i)) * uy + T(L::cz(i)) * uz;
+    const T vA = T(L::cx(i)) * Ax + T(L::cy(i)) * Ay + T(L::cz(i)) * Az;
+    const T vus = T(L::cx(i)) * usx + T(L::cy(i)) * usy + T(L::cz(i)) * usz;
+    const T feq = w * rho * (base + T(3) * vu + T(4.5) * vu * vu);
+    const T F = w * (T(3) * vA + T(9) * vA * vus - T(3) * Aus);
+    const T post = f[i] + inv_tau * (feq - f[i]) + F;
+    defect += f[i] - post;
+    f[i] = post;
+  }
+  f[0] = f[0] + defect;
+}
+
+// Stencils, written once so that every kernel forms them in the same order.
+// `g(i)` returns the field at r + v_i.
+//   lap g   = 6 sum_{i>0} w_i (g(r + v_i) - g(r))
+//   grad g  = 3 sum_{i>0} w_i v_i g(r + v_i)
+template <int LAT, typename T, typename G>
+__device__ __forceinline__ T lattice_laplacian(const G& g, T g0) {
+  using L = Lattice<LAT>;
+  T acc = T(0);
+#pragma unroll
+  for (int i = 1; i < L::Q; ++i) acc += T(L::w(i)) * (g(i) - g0);
+  return T(6) * acc;
+}
+
+// sum_{i>0} w_i v_i g(r + v_i): one third of the gradient stencil.
+template <int LAT, typename T, typename G>
+__device__ __forceinline__ void lattice_wsum(const G& g, T& sx, T& sy, T& sz) {
+  using L = Lattice<LAT>;
+  sx = sy = sz = T(0);
+#pragma unroll
+  for (int i = 1; i < L::Q; ++i) {
+    const T v = g(i);
+    if (L::cx(i)) sx += T(L::cx(i) * L::w(i)) * v;
+    if (L::cy(i)) sy += T(L::cy(i) * L::w(i)) * v;
+    if (L::cz(i)) sz += T(L::cz(i) * L::w(i)) * v;
+  }
+}
+
+// Force density A = rho^s a^s of Eq. (definef), c = 1 - 1/(2 tau):
+//   log form:      A = -c rho grad h,                 h = mu - ln(rho)/3
+//   expanded form: A = -c (rho grad h - grad(rho)/3), h = mu
+// `h(i)` and `r(i)` give the potential and the density at r + v_i.
+template <int LAT, typename T, typename GH, typename GR>
+__device__ __forceinline__ void lattice_force(const GH& h, const GR& r, T rho_s, const Params<T>& p,
+                                              T& Ax, T& Ay, T& Az) {
+  T hx, hy, hz;
+  lattice_wsum<LAT, T>(h, hx, hy, hz);
+  T qx = T(0), qy = T(0), qz = T(0);
+  if (!p.log_form) lattice_wsum<LAT, T>(r, qx, qy, qz);
+  Ax = -p.cforce * (rho_s * (T(3) * hx) - qx);
+  Ay = -p.cforce * (rho_s * (T(3) * hy) - qy);
+  Az = -p.cforce * (rho_s * (T(3) * hz) - qz);
+}
+
+// Periodic neighbour coordinate: x + d with d in {-1, 0, 1}.
+__device__ __forceinline__ int wrap_add(int x, int d, int n) {
+  int y = x + d;
+  y = y < 0 ? y + n : y;
+  return y >= n ? y - n : y;
+}
+
+}  // namespace lbm

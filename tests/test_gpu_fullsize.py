@@ -1,0 +1,85 @@
+"""The benchmark workload at full size (ternary D2Q9, 2048 x 2048, fused
+kernel) against the oracle on sampled sites, plus properties that hold at any
+size.
+
+After K steps the state at a site depends on the initial densities within
+3K sites (each step reaches one site by streaming and two more through the
+Laplacian in mu and the gradient of mu); U reaches two further sites through
+the force.  So the oracle, run on a periodic window of half-width 3K + 4
+centred on a sample site, reproduces that site exactly: the window's own
+wrap-around contaminates only its rim."""
+import numpy as np
+import pytest
+
+import lbinputs as LI
+from oracle import Oracle, OracleParams
+
+pytestmark = pytest.mark.gpu
+
+N_FULL = 2048
+K = 4
+
+
+def sample_sites(nx, ny, seed=5):
+    rng = np.random.default_rng(seed)
+    fixed = [(0, 0), (nx - 1, ny - 1), (63, 15), (64, 16), (127, 16), (128, 31), (nx // 2 - 1, 100),
+             (nx // 2, 101), (nx // 2 + 1, ny - 1), (nx - 1, 0), (0, ny - 1), (1023, 1024)]
+    rnd = [(int(x), int(y)) for x, y in zip(rng.integers(0, nx, 12), rng.integers(0, ny, 12))]
+    return fixed + rnd
+
+
+def window_oracle(cfg, rho0, nx, ny, x, y, steps):
+    R = 3 * steps + 4
+    W = 2 * R + 1
+    xs = np.arange(x - R, x + R + 1) % nx
+    ys = np.arange(y - R, y + R + 1) % ny
+    n = cfg["n_comp"]
+    g = rho0.reshape(n, ny, nx)[:, ys][:, :, xs].reshape(n, -1)
+    o = Oracle(OracleParams(**dict(cfg, shape=(W, W))), np.ascontiguousarray(g))
+    o.step(steps)
+    ob = o.observe()
+    c = R * W + R
+    return ob["rho"][:, c], ob["mu"][:, c], ob["U"][:, c]
+
+
+@pytest.fixture(scope="module")
+def workload():
+    return LI.ternary_immersion(N_FULL)
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-5), ("f64", 1e-12)])
+def test_fullsize_sampled_sites_match_oracle(workload, storage, tol):
+    from paper_0704_3444_amd import Simulation
+
+    cfg, rho0 = workload
+    print(f"[fullsize] ternary {N_FULL}^2 {storage} fused, {K} steps", flush=True)
+    sim = Simulation(cfg, rho0, storage=storage, path="auto")
+    assert sim.path == "fused"
+    sim.step(K)
+    out = sim.moments()
+    sim.close()
+    cs = 1 / np.sqrt(3)
+    worst = {"rho": 0.0, "mu": 0.0, "U": 0.0}
+    for (x, y) in sample_sites(N_FULL, N_FULL):
+        r, mu, U = window_oracle(cfg, rho0, N_FULL, N_FULL, x, y, K)
+        s = y * N_FULL + x
+        worst["rho"] = max(worst["rho"], float(np.max(np.abs(out["rho"][:, s] - r) / r)))
+        worst["mu"] = max(worst["mu"], float(np.max(np.abs(out["mu"][:, s] - mu) / np.abs(mu).max())))
+        worst["U"] = max(worst["U"], float(np.max(np.abs(out["U"][:, s] - U)) / cs))
+    print(f"[fullsize] {storage} worst errors {worst}", flush=True)
+    for k, v in worst.items():
+        assert v < tol, (k, worst)
+
+
+def test_fullsize_mass_conserved(workload):
+    from paper_0704_3444_amd import Simulation
+
+    cfg, rho0 = workload
+    sim = Simulation(cfg, rho0, storage="f32", path="auto")
+    m0 = rho0.sum(axis=1)
+    sim.step(300)
+    m = sim.moments(fields=False)["mass"]
+    sim.close()
+    drift = np.abs(m / m0 - 1).max()
+    print(f"[fullsize] f32 mass drift over 300 steps {drift:.3e}", flush=True)
+    assert drift < 1e-6

@@ -1,0 +1,140 @@
+"""GPU runtime behaviour of the C ABI: determinism, checkpoint/resume,
+translation equivariance across tile boundaries, conservation, and error
+reporting (all numeric-failure cases produce NaN arithmetic only; no kernel
+is made to fault)."""
+import numpy as np
+import pytest
+
+import lbinputs as LI
+
+pytestmark = pytest.mark.gpu
+
+PATHS = ["split", "fused"]
+
+
+def sim(cfg, rho0, **kw):
+    from paper_0704_3444_amd import Simulation
+
+    return Simulation(cfg, rho0, **kw)
+
+
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_bitwise_deterministic(path, storage):
+    cfg, rho0 = LI.ternary_immersion(70, ny=37)
+    a = sim(cfg, rho0, storage=storage, path=path)
+    b = sim(cfg, rho0, storage=storage, path=path)
+    a.step(60)
+    b.step(60)
+    assert a.get_state() == b.get_state()
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_checkpoint_resume_bitwise(path):
+    cfg, rho0 = LI.binary_spinodal(48)
+    a = sim(cfg, rho0, storage="f32", path=path)
+    a.step(40)
+    snap = a.get_state()
+    a.step(40)
+    ref = a.get_state()
+    b = sim(cfg, rho0, storage="f32", path=path)
+    b.set_state(snap)
+    b.step(40)
+    assert b.get_state() == ref
+    assert b.moments(fields=False)["step"] == 80
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_translation_equivariance_bitwise(path, storage):
+    """Shifting the initial state by (dx, dy) shifts the result exactly;
+    shifts straddle the tiles of the fused kernel."""
+    nx, ny = 150, 77
+    cfg, rho0 = LI.ternary_immersion(nx, ny=ny)
+    g = rho0.reshape(3, ny, nx)
+    for dx, dy in ((37, 11), (64, 16), (1, 76)):
+        rolled = np.roll(g, (dy, dx), axis=(1, 2)).reshape(3, -1)
+        a = sim(cfg, rho0, storage=storage, path=path)
+        b = sim(cfg, rolled, storage=storage, path=path)
+        a.step(25)
+        b.step(25)
+        fa = a.get_f().reshape(3, -1, ny, nx)
+        fb = b.get_f().reshape(3, -1, ny, nx)
+        assert np.array_equal(np.roll(fa, (dy, dx), axis=(2, 3)), fb), (dx, dy)
+        a.close()
+        b.close()
+
+
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("storage,bar", [("f64", 1e-13), ("f32", 1e-6)])
+def test_mass_conserved_long_run(path, storage, bar):
+    cfg, rho0 = LI.binary_spinodal(128, seed=77)
+    s = sim(cfg, rho0, storage=storage, path=path)
+    m0 = rho0.sum(axis=1)
+    s.step(3000)
+    m = s.moments(fields=False)["mass"]
+    assert np.abs(m / m0 - 1).max() < bar, m / m0 - 1
+    s.close()
+
+
+def test_invalid_inputs_rejected():
+    from paper_0704_3444_amd import LBError
+
+    cfg, rho0 = LI.binary_spinodal(16)
+    bad = rho0.copy()
+    bad[1, 5] = 0.0
+    with pytest.raises(LBError) as ei:
+        sim(cfg, bad)
+    assert ei.value.code == -1
+    bad[1, 5] = np.nan
+    with pytest.raises(LBError):
+        sim(cfg, bad)
+    with pytest.raises(LBError):
+        sim(dict(cfg, chi=np.array([[0.0, 2.4], [2.3, 0.0]])), rho0)
+    with pytest.raises(LBError):
+        sim(dict(cfg, chi=np.array([[0.1, 2.4], [2.4, 0.0]])), rho0)
+    with pytest.raises(LBError):
+        sim(dict(cfg, tau=0.5), rho0)
+    with pytest.raises(LBError):
+        sim(dict(cfg, theta=0.0), rho0)
+
+
+def test_workspace_too_small_rejected():
+    import torch
+    from paper_0704_3444_amd import lb
+
+    cfg, rho0 = LI.binary_spinodal(16)
+    p = lb.make_params(cfg, stream=torch.cuda.current_stream().cuda_stream)
+    need = lb.lb_workspace_bytes(p)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    with pytest.raises(lb.LBError) as ei:
+        lb.lb_init(p, rho0, ws.data_ptr(), need - 1024)
+    assert ei.value.code == -2
+
+
+@pytest.mark.parametrize("check_every", [0, 5])
+def test_numeric_failure_reported(check_every):
+    """A quench far beyond the scheme's stability (chi = 8 chi_c) drives a
+    density negative; lb_moments reports LB_ENUMERIC."""
+    from paper_0704_3444_amd import LBError
+
+    cfg, rho0 = LI.binary_spinodal(32, chi=16.0)
+    s = sim(cfg, rho0, check_every=check_every)
+    s.step(300)
+    with pytest.raises(LBError) as ei:
+        s.moments(fields=False)
+    assert ei.value.code == -5
+    s.close()
+
+
+def test_healthy_run_with_checks_reports_ok():
+    cfg, rho0 = LI.binary_spinodal(32)
+    s = sim(cfg, rho0, check_every=10)
+    s.step(100)
+    out = s.moments(fields=False)
+    assert out["status"] == 0 and out["step"] == 100
+    s.close()
