@@ -25,8 +25,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS×components at 2048² ternary, % HBM peak; serving p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ["paper_0704_3444_amd/csrc/k_fused2d.hip", "paper_0704_3444_amd/csrc/physics.hpp",
-                  "paper_0704_3444_amd/csrc/lattice.hpp"]
+KERNEL_SOURCES = ["paper_0704_3444_amd/csrc/k_sweep2d.hip", "paper_0704_3444_amd/csrc/k_fused2d.hip",
+                  "paper_0704_3444_amd/csrc/physics.hpp", "paper_0704_3444_amd/csrc/lattice.hpp"]
 
 
 def kernel_source_hash() -> str:
@@ -50,10 +50,10 @@ def workload(name):
     return table[name]()
 
 
-def measured_traffic(name, storage):
+def measured_traffic(name, storage, kpath):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when the kernel sources changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{name}_{storage}.json")
+    path = os.path.join(ROOT, "profiles", f"traffic_{name}_{storage}_{kpath}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -107,7 +107,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--storage", default="f32", choices=["f32", "f64"])
     ap.add_argument("--workload", default="ternary_d2q9_2048")
-    ap.add_argument("--path", default="auto", choices=["auto", "fused", "split"])
+    ap.add_argument("--path", default="auto", choices=["auto", "sweep", "tile", "split"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
     args = ap.parse_args()
@@ -162,13 +162,13 @@ def main():
     path = sim.path
     sim.close()
 
-    kernels_per_step = 1 if path == "fused" else 3
+    kernels_per_step = 3 if path == "split" else 1
     alg_bytes = 2 * Q * N * S * nbytes
     achieved = alg_bytes / (ms_per_step / 1e3) / 1e9
-    traffic = measured_traffic(args.workload, args.storage) if path == "fused" else None
+    traffic = measured_traffic(args.workload, args.storage, path)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_fused_d2q9" if path == "fused" else "k_density+k_potential+k_collide",
+                "kernel": {"sweep": "k_sweep_d2q9", "tile": "k_fused_d2q9"}.get(path, "k_density+k_potential+k_collide"),
                 "algorithmic_bytes_per_launch": alg_bytes, "launches_per_step": kernels_per_step,
                 "avg_launch_ms": round(ms_per_step / kernels_per_step, 5)}
 

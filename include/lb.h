@@ -67,10 +67,17 @@ typedef enum lb_storage { LB_F64 = 0, LB_F32 = 1 } lb_storage;
  * lap g = 6 sum_i w_i (g(r + v_i) - g(r)). */
 typedef enum lb_force_form { LB_FORCE_LOG = 0, LB_FORCE_EXPANDED = 1 } lb_force_form;
 
-/* Kernel path.  AUTO picks the fused single-kernel step where one exists
- * for the lattice and precision, else the split path (density, potential
- * and collide-stream kernels). */
-typedef enum lb_path { LB_PATH_AUTO = 0, LB_PATH_FUSED = 1, LB_PATH_SPLIT = 2 } lb_path;
+/* Kernel path.
+ *   LB_PATH_AUTO:  the fastest path that supports the run (sweep, then tile,
+ *                  then split).
+ *   LB_PATH_TILE:  fused one-kernel D2Q9 step over 2-D tiles with a two-site
+ *                  density halo (any nx, FP64 and FP32).
+ *   LB_PATH_SPLIT: three kernels per step (density, potential, collide and
+ *                  stream); every lattice.
+ *   LB_PATH_SWEEP: fused one-kernel D2Q9 step that sweeps 64-column strips
+ *                  row by row (FP32, N <= 4, nx a multiple of 64).
+ * Asking for a path that does not support the run gives LB_ENOTSUP. */
+typedef enum lb_path { LB_PATH_AUTO = 0, LB_PATH_TILE = 1, LB_PATH_SPLIT = 2, LB_PATH_SWEEP = 3 } lb_path;
 
 typedef struct lb_params {
   int32_t n_comp;        /* N, 1 .. LB_MAX_COMP                                   */
@@ -153,7 +160,8 @@ int lb_set_state(lb_ctx* c, const void* host, size_t bytes);
 /* Lattice tables: Q, D, velocities v[Q][3] and weights w[Q] (host). */
 int lb_lattice_tables(int32_t lattice, int32_t* Q, int32_t* D, int32_t* v, double* w);
 
-/* Path that lb_step runs for this context (LB_PATH_FUSED or LB_PATH_SPLIT). */
+/* Path that lb_step runs for this context (LB_PATH_TILE, LB_PATH_SPLIT or
+ * LB_PATH_SWEEP). */
 int lb_path_in_use(const lb_ctx* c);
 
 /* Release the context and any memory the library allocated.  NULL is a

@@ -13,7 +13,9 @@
 //   D. force, equilibrium, forcing term, BGK collision, and one coalesced
 //      store per population at the site itself (streaming happens through
 //      the pull of the next step).
-// Populations are read once and written once per step from HBM.  Workgroup
+// Populations are read once and written once per step from HBM; the stores
+// are non-temporal (the next step reads them, long after they would have
+// left the caches, and keeping them out preserves L2 for the halo rows).  Workgroup
 // indices are remapped so that the eight XCDs (dispatched round-robin) each
 // sweep a contiguous band of tiles, keeping halo rows in their own L2.
 // No MFMA: the step is a bandwidth-bound stencil, not a contraction.
@@ -31,32 +33,50 @@ __device__ __forceinline__ int wrap_mod(int v, int n) {
   return r < 0 ? r + n : r;
 }
 
+// 32-bit byte offset of population 0 of site (x, y); population q sits 64 q
+// elements further (the block layout of pop_index).  The host only takes
+// this path when one population copy is smaller than 4 GiB, so that every
+// access is a uniform 64-bit base plus a 32-bit per-lane offset.
+template <typename T>
+__device__ __forceinline__ uint32_t site_offset(int nbx, int nq, int x, int y) {
+  return (((uint32_t(y) * uint32_t(nbx) + uint32_t(x >> 6)) * uint32_t(nq) << 6) + uint32_t(x & 63)) *
+         uint32_t(sizeof(T));
+}
+
+template <typename T>
+__device__ __forceinline__ T load_at(const T* __restrict__ base, uint32_t byte_off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+
 // rho^sigma at (x, y), summing the pulled populations in lattice order (the
 // same order as the split path's density kernel).
 template <typename T, int NC>
-__device__ __forceinline__ void pulled_density(const T* __restrict__ fin, long long S, int nx, int ny, int x,
-                                               int y, int n, T (&rho)[NC]) {
+__device__ __forceinline__ void pulled_density(const T* __restrict__ fin, const Params<T>& p, int x, int y,
+                                               T (&rho)[NC]) {
   using L = Lattice<2>;
-  const int xm = wrap_add(x, -1, nx), xp = wrap_add(x, 1, nx);
-  const int ym = wrap_add(y, -1, ny), yp = wrap_add(y, 1, ny);
+  const int xm = wrap_add(x, -1, p.nx), xp = wrap_add(x, 1, p.nx);
+  const int ym = wrap_add(y, -1, p.ny), yp = wrap_add(y, 1, p.ny);
+  uint32_t off[L::Q];
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) {
+    const int sx = L::cx(i) > 0 ? xm : (L::cx(i) < 0 ? xp : x);
+    const int sy = L::cy(i) > 0 ? ym : (L::cy(i) < 0 ? yp : y);
+    off[i] = site_offset<T>(p.nbx, p.nq, sx, sy) + uint32_t(i * kBlockX * sizeof(T));
+  }
 #pragma unroll
   for (int k = 0; k < NC; ++k) {
     T acc = T(0);
-    if (k < n) {
+    if (k < p.n) {
 #pragma unroll
-      for (int i = 0; i < L::Q; ++i) {
-        const int sx = L::cx(i) > 0 ? xm : (L::cx(i) < 0 ? xp : x);
-        const int sy = L::cy(i) > 0 ? ym : (L::cy(i) < 0 ? yp : y);
-        acc += fin[((long long)k * L::Q + i) * S + (long long)sy * nx + sx];
-      }
+      for (int i = 0; i < L::Q; ++i) acc += load_at(fin, off[i] + uint32_t(k * L::Q * kBlockX * sizeof(T)));
     }
     rho[k] = acc;
   }
 }
 
-template <typename T, int NC, int TX, int TY, int NT>
+template <typename T, int NC, int TX, int TY, int NT, bool NTSTORE>
 __global__ void __launch_bounds__(NT) k_fused_d2q9(const T* __restrict__ fin, T* __restrict__ fout, Params<T> p,
-                                                   int nbx, int ntiles, int tiles_per_xcd) {
+                                                   int nbx, int ntiles, int tiles_per_xcd, int xcd_remap) {
   using L = Lattice<2>;
   constexpr int Q = L::Q;
   constexpr int HX = TX + 4, HY = TY + 4;  // rho region: tile + 2
@@ -71,11 +91,10 @@ __global__ void __launch_bounds__(NT) k_fused_d2q9(const T* __restrict__ fin, T*
   // XCD-aware tile order: workgroup b runs on XCD b % 8; give XCD c the
   // contiguous tile range [c * tiles_per_xcd, (c + 1) * tiles_per_xcd).
   const int b = blockIdx.x;
-  const int t = (b % kXcds) * tiles_per_xcd + b / kXcds;
+  const int t = xcd_remap ? (b % kXcds) * tiles_per_xcd + b / kXcds : b;
   if (t >= ntiles) return;
   const int x0 = (t % nbx) * TX, y0 = (t / nbx) * TY;
   const int nx = p.nx, ny = p.ny, n = p.n;
-  const long long S = p.S;
   const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
 
   // ---- A: the tile's own populations, kept in registers -------------------
@@ -88,14 +107,19 @@ __global__ void __launch_bounds__(NT) k_fused_d2q9(const T* __restrict__ fin, T*
     if (valid[k]) {
       const int xm = wrap_add(x, -1, nx), xp = wrap_add(x, 1, nx);
       const int ym = wrap_add(y, -1, ny), yp = wrap_add(y, 1, ny);
+      uint32_t off[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const int sx = L::cx(i) > 0 ? xm : (L::cx(i) < 0 ? xp : x);
+        const int sy = L::cy(i) > 0 ? ym : (L::cy(i) < 0 ? yp : y);
+        off[i] = site_offset<T>(p.nbx, p.nq, sx, sy) + uint32_t(i * kBlockX * sizeof(T));
+      }
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         T acc = T(0);
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-          const int sx = L::cx(i) > 0 ? xm : (L::cx(i) < 0 ? xp : x);
-          const int sy = L::cy(i) > 0 ? ym : (L::cy(i) < 0 ? yp : y);
-          f[k][c][i] = c < n ? fin[((long long)c * Q + i) * S + (long long)sy * nx + sx] : T(0);
+          f[k][c][i] = c < n ? load_at(fin, off[i] + uint32_t(c * Q * kBlockX * sizeof(T))) : T(0);
           acc += f[k][c][i];
         }
         s_rho[c][ty + k * RS + 2][tx + 2] = acc;
@@ -126,7 +150,7 @@ __global__ void __launch_bounds__(NT) k_fused_d2q9(const T* __restrict__ fin, T*
         px = TX + 2 + j % 2;
       }
       T r[NC];
-      pulled_density<T, NC>(fin, S, nx, ny, wrap_mod(x0 - 2 + px, nx), wrap_mod(y0 - 2 + py, ny), n, r);
+      pulled_density<T, NC>(fin, p, wrap_mod(x0 - 2 + px, nx), wrap_mod(y0 - 2 + py, ny), r);
 #pragma unroll
       for (int c = 0; c < NC; ++c) s_rho[c][py][px] = r[c];
     }
@@ -136,7 +160,7 @@ __global__ void __launch_bounds__(NT) k_fused_d2q9(const T* __restrict__ fin, T*
       const bool inner = px >= 2 && px < TX + 2 && py >= 2 && py < TY + 2 && x0 + px - 2 < nx && y0 + py - 2 < ny;
       if (inner) continue;  // filled in phase A
       T r[NC];
-      pulled_density<T, NC>(fin, S, nx, ny, wrap_mod(x0 - 2 + px, nx), wrap_mod(y0 - 2 + py, ny), n, r);
+      pulled_density<T, NC>(fin, p, wrap_mod(x0 - 2 + px, nx), wrap_mod(y0 - 2 + py, ny), r);
 #pragma unroll
       for (int c = 0; c < NC; ++c) s_rho[c][py][px] = r[c];
     }
@@ -186,10 +210,10 @@ __global__ void __launch_bounds__(NT) k_fused_d2q9(const T* __restrict__ fin, T*
         rt += rs[c];
       }
     }
-    const T inv_rt = T(1) / rt;
+    const T inv_rt = rcp_(rt);
     ux *= inv_rt;
     uy *= inv_rt;
-    const long long s = (long long)y * nx + x;
+    const uint32_t own = site_offset<T>(p.nbx, p.nq, x, y);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       if (c >= n) continue;
@@ -197,24 +221,35 @@ __global__ void __launch_bounds__(NT) k_fused_d2q9(const T* __restrict__ fin, T*
       lattice_force<2, T>([&](int i) { return s_h[c][ly + 1 + L::cy(i)][tx + 1 + L::cx(i)]; },
                           [&](int i) { return s_rho[c][ly + 2 + L::cy(i)][tx + 2 + L::cx(i)]; }, rs[c], p, Ax,
                           Ay, Az);
-      const T inv_rs = T(1) / rs[c];
+      const T inv_rs = rcp_(rs[c]);
       collide<2, T>(f[k][c], rs[c], ux, uy, T(0), Ax, Ay, Az, jx[c] * inv_rs, jy[c] * inv_rs, T(0), p.inv_tau);
 #pragma unroll
-      for (int i = 0; i < Q; ++i) fout[((long long)c * Q + i) * S + s] = f[k][c][i];
+      for (int i = 0; i < Q; ++i) {
+        T* dst = reinterpret_cast<T*>(reinterpret_cast<char*>(fout) + own +
+                                      uint32_t((c * Q + i) * kBlockX * sizeof(T)));
+        if constexpr (NTSTORE)
+          __builtin_nontemporal_store(f[k][c][i], dst);
+        else
+          *dst = f[k][c][i];
+      }
     }
   }
 }
 
 // ------------------------------------------------------------ dispatch ----
-template <typename T, int NC, int TX, int TY>
-static void launch_fused(const Ctx& c, const void* fin, void* fout) {
-  constexpr int NT = 256;
-  const int nbx = int((c.prm.nx + TX - 1) / TX);
-  const int nby = int((c.prm.ny + TY - 1) / TY);
+template <typename T, int NC, int TX, int TY, int NT = 256, bool NTSTORE = true>
+static void launch_tile(const Params<T>& p, const T* fin, T* fout, hipStream_t stream, bool remap = true) {
+  const int nbx = (p.nx + TX - 1) / TX;
+  const int nby = (p.ny + TY - 1) / TY;
   const int ntiles = nbx * nby;
   const int per_xcd = (ntiles + kXcds - 1) / kXcds;
-  k_fused_d2q9<T, NC, TX, TY, NT><<<per_xcd * kXcds, NT, 0, c.stream>>>(
-      static_cast<const T*>(fin), static_cast<T*>(fout), c.params<T>(), nbx, ntiles, per_xcd);
+  const int grid = remap ? per_xcd * kXcds : ntiles;
+  k_fused_d2q9<T, NC, TX, TY, NT, NTSTORE><<<grid, NT, 0, stream>>>(fin, fout, p, nbx, ntiles, per_xcd, remap);
+}
+
+template <typename T, int NC, int TX, int TY>
+static void launch_fused(const Ctx& c, const void* fin, void* fout) {
+  launch_tile<T, NC, TX, TY>(c.params<T>(), static_cast<const T*>(fin), static_cast<T*>(fout), c.stream);
 }
 
 // Tile per precision and component count: registers hold SPT * N * 9
@@ -247,7 +282,7 @@ static FusedStepFn pick_n(int n) {
 }
 
 FusedStepFn fused_step_for(int lattice, int storage, int n_comp) {
-  if (lattice != 2) return nullptr;
+  if (lattice != 2) return nullptr;  // slot-count limit checked by the caller
   return storage == 0 ? pick_n<double>(n_comp) : pick_n<float>(n_comp);
 }
 

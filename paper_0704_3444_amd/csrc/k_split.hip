@@ -46,6 +46,22 @@ __device__ __forceinline__ long long neighbour(const SiteCoord& c, int i, int si
 template <typename S>
 __device__ __forceinline__ double to_d(S v) { return double(v); }
 
+// Storage index of population q at the site r - v_i (the slot pulled into r).
+template <int LAT, typename T>
+__device__ __forceinline__ long long pull_index(const SiteCoord& c, int q, int i, const Params<T>& p) {
+  using L = Lattice<LAT>;
+  const int sx = wrap_add(c.x, -L::cx(i), p.nx);
+  const int sy = wrap_add(c.y, -L::cy(i), p.ny);
+  const int sz = wrap_add(c.z, -L::cz(i), p.nz);
+  return pop_index(p.nbx, p.nq, q, sx, (long long)sy + (long long)p.ny * sz);
+}
+
+// Storage index of population q at the site itself.
+template <typename T>
+__device__ __forceinline__ long long own_index(const SiteCoord& c, int q, const Params<T>& p) {
+  return pop_index(p.nbx, p.nq, q, c.x, (long long)c.y + (long long)p.ny * c.z);
+}
+
 // ---------------------------------------------------------------- init ----
 // Rest equilibrium f_i(r, 0) = w_i rho0(r), written in pull storage: slot
 // (i, r) holds the value that arrives at r + v_i.
@@ -60,7 +76,7 @@ __global__ void __launch_bounds__(kBlock) k_init(const double* __restrict__ rho0
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
       const long long src = neighbour<LAT>(c, i, +1, p);
-      f[((long long)k * L::Q + i) * p.S + s] = T(L::w(i) * rho0[(long long)k * p.S + src]);
+      f[own_index(c, k * L::Q + i, p)] = T(L::w(i) * rho0[(long long)k * p.S + src]);
     }
   }
 }
@@ -76,13 +92,10 @@ __global__ void __launch_bounds__(kBlock) k_density(const T* __restrict__ f, TO*
   const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= p.S) return;
   const SiteCoord c = coord_of(s, p);
-  long long src[L::Q];
-#pragma unroll
-  for (int i = 0; i < L::Q; ++i) src[i] = neighbour<LAT>(c, i, -1, p);
   for (int k = 0; k < p.n; ++k) {
     TO acc = TO(0);
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) acc += TO(f[((long long)k * L::Q + i) * p.S + src[i]]);
+    for (int i = 0; i < L::Q; ++i) acc += TO(f[pull_index<LAT>(c, k * L::Q + i, i, p)]);
     rho[(long long)k * p.S + s] = acc;
   }
 }
@@ -128,21 +141,17 @@ __global__ void __launch_bounds__(kBlock) k_collide(const T* __restrict__ fin, T
   const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= p.S) return;
   const SiteCoord c = coord_of(s, p);
-  long long src[Q], nb[Q];
+  long long nb[Q];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    src[i] = neighbour<LAT>(c, i, -1, p);
-    nb[i] = neighbour<LAT>(c, i, +1, p);
-  }
+  for (int i = 0; i < Q; ++i) nb[i] = neighbour<LAT>(c, i, +1, p);
   // barycentric velocity u = sum_sigma j^sigma / sum_sigma rho^sigma
   T jx[kMaxComp], jy[kMaxComp], jz[kMaxComp];
   T rt = T(0), ux = T(0), uy = T(0), uz = T(0);
   for (int k = 0; k < p.n; ++k) {
-    const T* fk = fin + (long long)k * Q * p.S;
     T ax = T(0), ay = T(0), az = T(0);
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-      const T fi = fk[(long long)i * p.S + src[i]];
+      const T fi = fin[pull_index<LAT>(c, k * Q + i, i, p)];
       if (L::cx(i)) ax += T(L::cx(i)) * fi;
       if (L::cy(i)) ay += T(L::cy(i)) * fi;
       if (L::cz(i)) az += T(L::cz(i)) * fi;
@@ -155,27 +164,25 @@ __global__ void __launch_bounds__(kBlock) k_collide(const T* __restrict__ fin, T
     uz += az;
     rt += rho[(long long)k * p.S + s];
   }
-  const T inv_rt = T(1) / rt;
+  const T inv_rt = rcp_(rt);
   ux *= inv_rt;
   uy *= inv_rt;
   uz *= inv_rt;
   for (int k = 0; k < p.n; ++k) {
-    const T* fk = fin + (long long)k * Q * p.S;
     const T rs = rho[(long long)k * p.S + s];
     T f[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) f[i] = fk[(long long)i * p.S + src[i]];
+    for (int i = 0; i < Q; ++i) f[i] = fin[pull_index<LAT>(c, k * Q + i, i, p)];
     const T* hk = h + (long long)k * p.S;
     const T* rk = rho + (long long)k * p.S;
     T Ax, Ay, Az;
     lattice_force<LAT, T>([&](int i) { return hk[nb[i]]; }, [&](int i) { return rk[nb[i]]; }, rs, p, Ax, Ay,
                           Az);
-    const T inv_rs = T(1) / rs;
+    const T inv_rs = rcp_(rs);
     collide<LAT, T>(f, rs, ux, uy, uz, Ax, Ay, Az, jx[k] * inv_rs, jy[k] * inv_rs, jz[k] * inv_rs,
                     p.inv_tau);
-    T* ok = fout + (long long)k * Q * p.S;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) ok[(long long)i * p.S + s] = f[i];
+    for (int i = 0; i < Q; ++i) fout[own_index(c, k * Q + i, p)] = f[i];
   }
 }
 
@@ -193,12 +200,9 @@ __global__ void __launch_bounds__(kBlock) k_observe(const T* __restrict__ fin, c
   const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= p.S) return;
   const SiteCoord c = coord_of(s, p);
-  long long src[Q], nb[Q];
+  long long nb[Q];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    src[i] = neighbour<LAT>(c, i, -1, p);
-    nb[i] = neighbour<LAT>(c, i, +1, p);
-  }
+  for (int i = 0; i < Q; ++i) nb[i] = neighbour<LAT>(c, i, +1, p);
   double rt = 0, jt[3] = {0, 0, 0}, At[3] = {0, 0, 0};
   double r[kMaxComp], lap[kMaxComp], g[kMaxComp][3];
   for (int k = 0; k < kMaxComp; ++k) {
@@ -207,10 +211,9 @@ __global__ void __launch_bounds__(kBlock) k_observe(const T* __restrict__ fin, c
     g[k][0] = g[k][1] = g[k][2] = 0.0;
   }
   for (int k = 0; k < p.n; ++k) {
-    const T* fk = fin + (long long)k * Q * p.S;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-      const double fi = to_d(fk[(long long)i * p.S + src[i]]);
+      const double fi = to_d(fin[pull_index<LAT>(c, k * Q + i, i, p)]);
       jt[0] += L::cx(i) * fi;
       jt[1] += L::cy(i) * fi;
       jt[2] += L::cz(i) * fi;
@@ -270,10 +273,8 @@ __global__ void __launch_bounds__(kBlock) k_unpull(const T* __restrict__ fin, do
   const SiteCoord c = coord_of(s, p);
   for (int k = 0; k < p.n; ++k)
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-      const long long idx = ((long long)k * L::Q + i) * p.S;
-      out[idx + s] = to_d(fin[idx + neighbour<LAT>(c, i, -1, p)]);
-    }
+    for (int i = 0; i < L::Q; ++i)
+      out[((long long)k * L::Q + i) * p.S + s] = to_d(fin[pull_index<LAT>(c, k * L::Q + i, i, p)]);
 }
 
 // ---------------------------------------------------------- diagnostics ----
@@ -298,17 +299,13 @@ __global__ void __launch_bounds__(kBlock) k_diag(const T* __restrict__ fin, doub
   for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < p.S;
        s += (long long)gridDim.x * blockDim.x) {
     const SiteCoord c = coord_of(s, p);
-    long long src[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) src[i] = neighbour<LAT>(c, i, -1, p);
 #pragma unroll
     for (int k = 0; k < kMaxComp; ++k) {
       if (k < p.n) {
-        const T* fk = fin + (long long)k * Q * p.S;
         double r = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-          const double fi = to_d(fk[(long long)i * p.S + src[i]]);
+          const double fi = to_d(fin[pull_index<LAT>(c, k * Q + i, i, p)]);
           r += fi;
           jx += L::cx(i) * fi;
           jy += L::cy(i) * fi;
@@ -316,8 +313,8 @@ __global__ void __launch_bounds__(kBlock) k_diag(const T* __restrict__ fin, doub
         }
         acc[k] += r;
         acc[kMaxComp] += jx;
-        if (D > 1) acc[kMaxComp + 1] += jy;
-        if (D > 2) acc[kMaxComp + 2] += jz;
+        if constexpr (D > 1) acc[kMaxComp + 1] += jy;
+        if constexpr (D > 2) acc[kMaxComp + 2] += jz;
         if (!(r > 0.0) || !(r < 1e300)) acc[K - 1] = 1.0;
       }
     }

@@ -1,0 +1,302 @@
+// Strip-sweep D2Q9 step: one launch per time step, every population read
+// once and written once, with almost no halo re-reads.
+//
+// A workgroup of four waves owns a strip of 64 columns (one 64-site block of
+// the population layout) and a segment of rows, which it sweeps from top to
+// bottom.  Wave w handles the rows y = w (mod 4) of the segment.  One round
+// advances four rows:
+//   1. density rho^sigma of the rows one round ahead, from populations the
+//      waves already hold in registers (plus four halo columns formed by 12
+//      lanes), into an LDS ring of rows;
+//   2. chemical potentials and the potential h of four rows into an LDS ring
+//      (the Laplacian in mu and the gradient of mu reach two rows ahead);
+//   3. prefetch of the populations two rounds ahead;
+//   4. force, equilibrium, forcing term and collision of the current row,
+//      stored in place (streaming happens through the next step's pull).
+// Each wave keeps three rows of populations in registers (current, one round
+// ahead, in flight).  Rows are re-read only at the two ends of a segment
+// (4 rows per segment) and the strip edges (4 columns per 64), instead of a
+// two-site ring around every tile.  Workgroups are banded per XCD so that
+// neighbouring strips share L2.
+#include <hip/hip_runtime.h>
+
+#include "lbm_internal.hpp"
+#include "physics.hpp"
+
+namespace lbm {
+namespace sweep {
+
+constexpr int kXcds = 8;
+constexpr int kRhoRing = 16;  // rows of rho kept in LDS (live span is 9)
+constexpr int kHRing = 8;     // rows of h kept in LDS (live span is 8)
+constexpr int kW = 64;        // strip width = block width = wave size
+constexpr int kRW = kW + 4;   // rho row: columns x0 - 2 .. x0 + 65
+constexpr int kHW = kW + 2;   // h row:   columns x0 - 1 .. x0 + 64
+
+__device__ __forceinline__ int wrap_mod(int v, int n) {
+  int r = v % n;
+  return r < 0 ? r + n : r;
+}
+
+// Byte offset of population 0 of site (x, y) in the block layout (see
+// pop_index); the caller guarantees one copy is below 4 GiB.
+template <typename T>
+__device__ __forceinline__ uint32_t site_off(int nbx, int nq, int x, int y) {
+  return (((uint32_t(y) * uint32_t(nbx) + uint32_t(x >> 6)) * uint32_t(nq) << 6) + uint32_t(x & 63)) *
+         uint32_t(sizeof(T));
+}
+
+template <typename T>
+__device__ __forceinline__ T ld(const T* __restrict__ base, uint32_t byte_off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+
+// The populations pulled into site (x, prow): f_i comes from (x - v_i).
+template <typename T, int NC>
+__device__ __forceinline__ void load_row(const T* __restrict__ fin, const Params<T>& p, int x, int prow,
+                                         T (&F)[NC][9]) {
+  using L = Lattice<2>;
+  const int xm = wrap_add(x, -1, p.nx), xp = wrap_add(x, 1, p.nx);
+  const int ym = wrap_add(prow, -1, p.ny), yp = wrap_add(prow, 1, p.ny);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const int sx = L::cx(i) > 0 ? xm : (L::cx(i) < 0 ? xp : x);
+    const int sy = L::cy(i) > 0 ? ym : (L::cy(i) < 0 ? yp : prow);
+    const uint32_t off = site_off<T>(p.nbx, p.nq, sx, sy) + uint32_t(i * kW * sizeof(T));
+#pragma unroll
+    for (int c = 0; c < NC; ++c) F[c][i] = ld(fin, off + uint32_t(c * 9 * kW * sizeof(T)));
+  }
+}
+
+// Halo columns x0-2, x0-1, x0+64, x0+65 of the four rows r0 .. r0+3: lane
+// L < 16 NC pulls the nine populations of (row r0 + L / (4 NC), halo column,
+// component).  One wave loads them for the whole workgroup.
+template <typename T, int NC>
+__device__ __forceinline__ void load_halo4(const T* __restrict__ fin, const Params<T>& p, int lane, int x0,
+                                           int r0, T (&Hv)[9]) {
+  using L = Lattice<2>;
+  if (lane < 16 * NC) {
+    const int wr = lane / (4 * NC), hc = (lane % (4 * NC)) / NC, c = lane % NC;
+    const int prow = wrap_mod(r0 + wr, p.ny);
+    const int hx = wrap_mod(x0 + (hc < 2 ? hc - 2 : kW + hc - 2), p.nx);
+    const int xm = wrap_add(hx, -1, p.nx), xp = wrap_add(hx, 1, p.nx);
+    const int ym = wrap_add(prow, -1, p.ny), yp = wrap_add(prow, 1, p.ny);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const int sx = L::cx(i) > 0 ? xm : (L::cx(i) < 0 ? xp : hx);
+      const int sy = L::cy(i) > 0 ? ym : (L::cy(i) < 0 ? yp : prow);
+      Hv[i] = ld(fin, site_off<T>(p.nbx, p.nq, sx, sy) + uint32_t((c * 9 + i) * kW * sizeof(T)));
+    }
+  }
+}
+
+template <typename T, int NC>
+__global__ void __launch_bounds__(256) k_sweep_d2q9(const T* __restrict__ fin, T* __restrict__ fout, Params<T> p,
+                                                    int strips, int seg_rows, int ntiles, int tiles_per_xcd) {
+  using L = Lattice<2>;
+  __shared__ T s_rho[kRhoRing][NC][kRW];
+  __shared__ T s_h[kHRing][NC][kHW];
+
+  const int b = blockIdx.x;
+  const int t = (b % kXcds) * tiles_per_xcd + b / kXcds;
+  if (t >= ntiles) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int x0 = (t % strips) * kW;
+  const int ya = (t / strips) * seg_rows;
+  const int yb = min(ya + seg_rows, p.ny);
+  const int rounds = (yb - ya + 3) / 4;
+  const int x = x0 + lane;  // nx is a multiple of 64: every lane is a site
+  const int ny = p.ny;
+  constexpr int kHaloWave = 1, kEdgeWave = 0;
+
+  // ring slots of virtual row r (r >= ya - 8 always)
+  auto rslot = [&](int r) { return (r - ya + 8 * kRhoRing) & (kRhoRing - 1); };
+  auto hslot = [&](int r) { return (r - ya + 8 * kHRing) & (kHRing - 1); };
+
+  // density of virtual row r from the wave's populations
+  auto put_rho = [&](int r, const T (&F)[NC][9]) {
+    const int sr = rslot(r);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      T acc = T(0);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) acc += F[c][i];
+      s_rho[sr][c][lane + 2] = acc;
+    }
+  };
+  // halo densities of rows r0 .. r0+3 from the halo wave's values
+  auto put_rho_halo = [&](int r0, const T (&Hv)[9]) {
+    if (lane < 16 * NC) {
+      const int wr = lane / (4 * NC), hc = (lane % (4 * NC)) / NC, c = lane % NC;
+      T acc = T(0);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) acc += Hv[i];
+      s_rho[rslot(r0 + wr)][c][hc < 2 ? hc : kW + hc] = acc;
+    }
+  };
+
+  // potential h of virtual row r at h position q (column x0 - 1 + q)
+  auto put_h = [&](int r, int q) {
+    const int s0 = rslot(r - 1), s1 = rslot(r), s2 = rslot(r + 1);
+    const int pc = q + 1;  // rho position of the column
+    T rr[NC], lap[NC], mu[NC], hh[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      rr[c] = s_rho[s1][c][pc];
+      lap[c] = lattice_laplacian<2, T>(
+          [&](int i) {
+            const int sy = L::cy(i) > 0 ? s2 : (L::cy(i) < 0 ? s0 : s1);
+            return s_rho[sy][c][pc + L::cx(i)];
+          },
+          rr[c]);
+    }
+    site_potential<T, NC>(p, rr, lap, mu, hh);
+    const int sh = hslot(r);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) s_h[sh][c][q] = hh[c];
+  };
+  // h of rows r0 .. r0+3: each wave its own row's 64 interior columns, the
+  // edge wave the eight edge columns (q = 0 and 65) of all four rows
+  auto put_h4 = [&](int r0) {
+    put_h(r0 + w, lane + 1);
+    if (w == kEdgeWave && lane < 8) put_h(r0 + (lane >> 1), (lane & 1) ? kHW - 1 : 0);
+  };
+
+  T F0[NC][9], F1[NC][9], F2[NC][9], Hv[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Hv[i] = T(0);
+
+  // ---- prologue --------------------------------------------------------
+  // rho of rows ya-2, ya-1 (waves 2, 3) and ya .. ya+3 (all waves); h of rows
+  // ya-1 .. ya+2; populations of rows ya + w (collided in round 0) in F1 and
+  // ya + 4 + w in flight in F2.
+  if (w >= 2) load_row<T, NC>(fin, p, x, wrap_mod(ya - 4 + w, ny), F0);
+  if (w == kHaloWave) load_halo4<T, NC>(fin, p, lane, x0, ya - 4, Hv);
+  if (w >= 2) put_rho(ya - 4 + w, F0);
+  if (w == kHaloWave) put_rho_halo(ya - 4, Hv);
+  load_row<T, NC>(fin, p, x, wrap_mod(ya + w, ny), F1);
+  if (w == kHaloWave) load_halo4<T, NC>(fin, p, lane, x0, ya, Hv);
+  put_rho(ya + w, F1);
+  if (w == kHaloWave) put_rho_halo(ya, Hv);
+  __syncthreads();
+  put_h4(ya - 1);
+  __syncthreads();
+  load_row<T, NC>(fin, p, x, wrap_mod(ya + 4 + w, ny), F2);
+  if (w == kHaloWave) load_halo4<T, NC>(fin, p, lane, x0, ya + 4, Hv);
+
+  // ---- rounds ------------------------------------------------------------
+  // Entering round k: Fc holds row ya+4k+w (rho already in LDS), Fa holds
+  // row ya+4k+4+w (in flight), Hv the halo values of rows ya+4k+4 .. +7;
+  // the round prefetches row ya+4k+8+w into Fn.
+  auto round = [&](int k, T (&Fc)[NC][9], T (&Fa)[NC][9], T (&Fn)[NC][9]) __attribute__((always_inline)) {
+    const int rc = ya + 4 * k + w;  // row collided by this wave
+    const int ra = rc + 4;          // row whose density is formed this round
+    put_rho(ra, Fa);
+    if (w == kHaloWave) put_rho_halo(ya + 4 * k + 4, Hv);
+    __syncthreads();
+    put_h4(ya + 4 * k + 3);
+    __syncthreads();
+    if (k + 1 < rounds) {
+      load_row<T, NC>(fin, p, x, wrap_mod(ra + 4, ny), Fn);
+      if (w == kHaloWave) load_halo4<T, NC>(fin, p, lane, x0, ya + 4 * k + 8, Hv);
+    }
+    if (rc < yb) {
+      const int sr = rslot(rc);
+      T rs[NC], jx[NC], jy[NC];
+      T rt = T(0), ux = T(0), uy = T(0);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        T ax = T(0), ay = T(0);
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+          if (L::cx(i)) ax += T(L::cx(i)) * Fc[c][i];
+          if (L::cy(i)) ay += T(L::cy(i)) * Fc[c][i];
+        }
+        jx[c] = ax;
+        jy[c] = ay;
+        rs[c] = s_rho[sr][c][lane + 2];
+        ux += ax;
+        uy += ay;
+        rt += rs[c];
+      }
+      const T inv_rt = rcp_(rt);
+      ux *= inv_rt;
+      uy *= inv_rt;
+      const int h0 = hslot(rc - 1), h1 = hslot(rc), h2 = hslot(rc + 1);
+      const int r0 = rslot(rc - 1), r2 = rslot(rc + 1);
+      const uint32_t own = site_off<T>(p.nbx, p.nq, x, rc);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        T Ax, Ay, Az;
+        lattice_force<2, T>(
+            [&](int i) {
+              const int sy = L::cy(i) > 0 ? h2 : (L::cy(i) < 0 ? h0 : h1);
+              return s_h[sy][c][lane + 1 + L::cx(i)];
+            },
+            [&](int i) {
+              const int sy = L::cy(i) > 0 ? r2 : (L::cy(i) < 0 ? r0 : sr);
+              return s_rho[sy][c][lane + 2 + L::cx(i)];
+            },
+            rs[c], p, Ax, Ay, Az);
+        const T inv_rs = rcp_(rs[c]);
+        collide<2, T>(Fc[c], rs[c], ux, uy, T(0), Ax, Ay, Az, jx[c] * inv_rs, jy[c] * inv_rs, T(0), p.inv_tau);
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+          __builtin_nontemporal_store(
+              Fc[c][i], reinterpret_cast<T*>(reinterpret_cast<char*>(fout) + own +
+                                             uint32_t((c * 9 + i) * kW * sizeof(T))));
+      }
+    }
+  };
+  for (int k = 0; k < rounds; ++k) {
+    round(k, F1, F2, F0);
+    // rotate: F1 <- row ya+4k+4+w, F2 <- row ya+4k+8+w (register moves; an
+    // unrolled renaming needs more registers than one occupancy step allows)
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        F1[c][i] = F2[c][i];
+        F2[c][i] = F0[c][i];
+      }
+  }
+}
+
+}  // namespace sweep
+
+// Rows per segment: about one workgroup per resident slot (three per CU on
+// 256 CUs), rounded up to whole rounds of four rows, so the grid runs in one
+// wave of workgroups and the four rows re-read per segment stay a small
+// fraction of it.
+static int sweep_rows(int nx, int ny) {
+  const int strips = nx / 64;
+  const int slots = 3 * 256;
+  const int segs = (slots + strips - 1) / strips;
+  int rows = (ny + segs - 1) / segs;
+  rows = (rows + 3) / 4 * 4;
+  return rows < 4 ? 4 : rows;
+}
+
+template <typename T, int NC>
+static void launch_sweep(const Ctx& c, const void* fin, void* fout) {
+  const Params<T>& p = c.params<T>();
+  const int strips = p.nx / 64;
+  const int rows = sweep_rows(p.nx, p.ny);
+  const int ntiles = strips * ((p.ny + rows - 1) / rows);
+  const int per_xcd = (ntiles + sweep::kXcds - 1) / sweep::kXcds;
+  sweep::k_sweep_d2q9<T, NC><<<per_xcd * sweep::kXcds, 256, 0, c.stream>>>(
+      static_cast<const T*>(fin), static_cast<T*>(fout), p, strips, rows, ntiles, per_xcd);
+}
+
+FusedStepFn sweep_step_for(int storage, int n_comp) {
+  if (storage != 1) return nullptr;  // FP32 only: three rows of FP64 populations exceed the register budget
+  switch (n_comp) {
+    case 1: return launch_sweep<float, 1>;
+    case 2: return launch_sweep<float, 2>;
+    case 3: return launch_sweep<float, 3>;
+    case 4: return launch_sweep<float, 4>;
+    default: return nullptr;
+  }
+}
+
+}  // namespace lbm

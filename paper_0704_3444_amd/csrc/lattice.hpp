@@ -1,7 +1,8 @@
 // Velocity sets for the device code.  D1Q3 is the set of Sec. IV; D2Q9 and
 // D3Q19 are the standard second-order sets (sum_i w_i v_i v_i = I/3, fourth
 // moment isotropic).  Every table is a constexpr function so that fully
-// unrolled loops fold each velocity component and weight into an immediate.
+// unrolled loops fold each velocity component and weight into an immediate;
+// opp(i) is the index of -v_i.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -18,6 +19,7 @@ struct Lattice<1> {  // D1Q3
   __host__ __device__ static constexpr int cy(int) { return 0; }
   __host__ __device__ static constexpr int cz(int) { return 0; }
   __host__ __device__ static constexpr double w(int i) { return i == 0 ? 2.0 / 3.0 : 1.0 / 6.0; }
+  __host__ __device__ static constexpr int opp(int i) { return i == 0 ? 0 : 3 - i; }
 };
 
 template <>
@@ -32,6 +34,9 @@ struct Lattice<2> {  // D2Q9: rest, 4 axis, 4 diagonal
   __host__ __device__ static constexpr int cz(int) { return 0; }
   __host__ __device__ static constexpr double w(int i) {
     return i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+  }
+  __host__ __device__ static constexpr int opp(int i) {
+    return i == 0 ? 0 : (i == 1 || i == 2 || i == 5 || i == 6 ? i + 2 : i - 2);
   }
 };
 
@@ -53,6 +58,23 @@ struct Lattice<3> {  // D3Q19: rest, 6 axis, 12 edge
   __host__ __device__ static constexpr double w(int i) {
     return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
   }
+  __host__ __device__ static constexpr int opp(int i) { return i == 0 ? 0 : (i % 2 ? i + 1 : i - 1); }
 };
+
+// Compile-time checks of the tables: weights sum to one, opp(i) is -v_i.
+template <typename L>
+constexpr bool tables_consistent() {
+  double ws = 0.0;
+  for (int i = 0; i < L::Q; ++i) {
+    ws += L::w(i);
+    const int j = L::opp(i);
+    if (L::cx(j) != -L::cx(i) || L::cy(j) != -L::cy(i) || L::cz(j) != -L::cz(i)) return false;
+    if (L::w(j) != L::w(i)) return false;
+  }
+  return ws > 1.0 - 1e-15 && ws < 1.0 + 1e-15;
+}
+static_assert(tables_consistent<Lattice<1>>(), "D1Q3 table");
+static_assert(tables_consistent<Lattice<2>>(), "D2Q9 table");
+static_assert(tables_consistent<Lattice<3>>(), "D3Q19 table");
 
 }  // namespace lbm

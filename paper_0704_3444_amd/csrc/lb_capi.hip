@@ -57,7 +57,7 @@ int validate(const lb_params* p, std::string* why) {
   if (p->n_comp < 1 || p->n_comp > LB_MAX_COMP) return bad("n_comp must be in 1..8");
   if (p->storage != LB_F64 && p->storage != LB_F32) return bad("unknown storage");
   if (p->force_form != LB_FORCE_LOG && p->force_form != LB_FORCE_EXPANDED) return bad("unknown force_form");
-  if (p->path < LB_PATH_AUTO || p->path > LB_PATH_SPLIT) return bad("unknown path");
+  if (p->path < LB_PATH_AUTO || p->path > LB_PATH_SWEEP) return bad("unknown path");
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) return bad("box sides must be >= 1");
   if (p->nx > (1 << 30) || p->ny > (1 << 30) || p->nz > (1 << 30)) return bad("box side too large");
   if (p->lattice == LB_D1Q3 && (p->ny != 1 || p->nz != 1)) return bad("D1Q3 needs ny = nz = 1");
@@ -89,13 +89,22 @@ struct Layout {
   int diag_blocks;
 };
 
+// Population slots of one copy: rows * (64-site blocks per row) * 64 * N * Q
+// (the x extent is padded to a multiple of 64; padded slots are never used).
+size_t population_slots(const lb_params* p) {
+  int Q, D;
+  lattice_dims(p->lattice, &Q, &D);
+  const size_t nbx = (size_t(p->nx) + 63) / 64;
+  return size_t(p->ny) * size_t(p->nz) * nbx * 64 * size_t(p->n_comp) * Q;
+}
+
 Layout layout_of(const lb_params* p) {
   int Q, D;
   lattice_dims(p->lattice, &Q, &D);
   const size_t S = size_t(p->nx) * size_t(p->ny) * size_t(p->nz);
   const size_t rb = p->storage == LB_F64 ? 8 : 4;
   Layout L;
-  const size_t fbytes = align_up(size_t(p->n_comp) * Q * S * rb);
+  const size_t fbytes = align_up(population_slots(p) * rb);
   const size_t rbytes = align_up(size_t(p->n_comp) * S * rb);
   const size_t blocks = (S + 255) / 256;
   L.diag_blocks = int(blocks < 1024 ? blocks : 1024);
@@ -119,6 +128,10 @@ void fill_params(const lb_params* p, lbm::Params<T>* q) {
   q->ny = int(p->ny);
   q->nz = int(p->nz);
   q->S = (long long)p->nx * p->ny * p->nz;
+  q->nbx = int((p->nx + 63) / 64);
+  int Q, D;
+  lattice_dims(p->lattice, &Q, &D);
+  q->nq = p->n_comp * Q;
   q->inv_tau = T(1.0 / p->tau[0]);
   q->cforce = T(1.0 - 0.5 / p->tau[0]);
   q->theta = T(p->theta);
@@ -133,8 +146,7 @@ void fill_params(const lb_params* p, lbm::Params<T>* q) {
 // Step the context's state n times on its stream.
 int advance(Ctx& c, int64_t n) {
   const lbm::SplitTable& st = lbm::split_table(c.prm.lattice, c.prm.storage);
-  lbm::FusedStepFn fused =
-      c.path == LB_PATH_FUSED ? lbm::fused_step_for(c.prm.lattice, c.prm.storage, c.prm.n_comp) : nullptr;
+  lbm::FusedStepFn fused = c.path == LB_PATH_SPLIT ? nullptr : c.fused;
   for (int64_t k = 0; k < n; ++k) {
     void* fin = c.f[c.cur];
     void* fout = c.f[1 - c.cur];
@@ -202,7 +214,7 @@ int lb_init(const lb_params* p, const double* rho0, void* workspace, size_t work
     c.ws_bytes = L.total;
   }
   char* base = static_cast<char*>(c.ws);
-  const size_t fbytes = size_t(p->n_comp) * c.Q * S * c.real_bytes;
+  const size_t fbytes = population_slots(p) * c.real_bytes;
   c.f[0] = base + L.f;
   c.f[1] = base + L.f + align_up(fbytes);
   c.rho_scratch = base + L.rho;
@@ -214,12 +226,33 @@ int lb_init(const lb_params* p, const double* rho0, void* workspace, size_t work
   fill_params(p, &c.pf);
   fill_params(p, &c.pd);
 
-  lbm::FusedStepFn fused = lbm::fused_step_for(p->lattice, p->storage, p->n_comp);
-  if (p->path == LB_PATH_FUSED && !fused) {
-    lb_free(h);
-    return fail(LB_ENOTSUP, "no fused kernel for this lattice / storage / N");
+  // the fused kernels address one population copy with 32-bit byte offsets
+  const bool small = fbytes < (size_t(1) << 32);
+  lbm::FusedStepFn tile = small ? lbm::fused_step_for(p->lattice, p->storage, p->n_comp) : nullptr;
+  lbm::FusedStepFn sweep =
+      small && p->lattice == LB_D2Q9 && p->nx % 64 == 0 ? lbm::sweep_step_for(p->storage, p->n_comp) : nullptr;
+  switch (p->path) {
+    case LB_PATH_AUTO:
+      c.path = sweep ? LB_PATH_SWEEP : (tile ? LB_PATH_TILE : LB_PATH_SPLIT);
+      break;
+    case LB_PATH_TILE:
+      c.path = LB_PATH_TILE;
+      if (!tile) {
+        lb_free(h);
+        return fail(LB_ENOTSUP, "no tile kernel for this lattice / N / size");
+      }
+      break;
+    case LB_PATH_SWEEP:
+      c.path = LB_PATH_SWEEP;
+      if (!sweep) {
+        lb_free(h);
+        return fail(LB_ENOTSUP, "the sweep kernel needs D2Q9, FP32, N <= 4 and nx a multiple of 64");
+      }
+      break;
+    default:
+      c.path = LB_PATH_SPLIT;
   }
-  c.path = (p->path == LB_PATH_SPLIT || !fused) ? LB_PATH_SPLIT : LB_PATH_FUSED;
+  c.fused = c.path == LB_PATH_SWEEP ? sweep : (c.path == LB_PATH_TILE ? tile : nullptr);
 
   double* rho_dev = nullptr;
   hipError_t e = hipMalloc(&rho_dev, size_t(p->n_comp) * S * sizeof(double));
@@ -229,6 +262,10 @@ int lb_init(const lb_params* p, const double* rho0, void* workspace, size_t work
   }
   e = hipMemcpyAsync(rho_dev, rho0, size_t(p->n_comp) * S * sizeof(double), hipMemcpyHostToDevice, c.stream);
   if (e == hipSuccess) e = hipMemsetAsync(c.health_flag, 0, sizeof(int), c.stream);
+  // padded slots (x >= nx in the last block of a row) are never written by
+  // the step; clear both copies so that checkpoints are deterministic
+  if (e == hipSuccess) e = hipMemsetAsync(c.f[0], 0, fbytes, c.stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c.f[1], 0, fbytes, c.stream);
   if (e == hipSuccess) {
     lbm::split_table(p->lattice, p->storage).init(c, rho_dev, c.f[0]);
     e = hipGetLastError();
@@ -326,7 +363,7 @@ int lb_get_f(lb_ctx* h, double* f) {
 size_t lb_state_bytes(const lb_ctx* h) {
   if (!h) return 0;
   const Ctx& c = h->c;
-  return size_t(c.prm.n_comp) * c.Q * size_t(c.S) * c.real_bytes + sizeof(int64_t);
+  return population_slots(&c.prm) * c.real_bytes + sizeof(int64_t);
 }
 
 int lb_get_state(lb_ctx* h, void* host, size_t bytes) {

@@ -8,6 +8,13 @@
 
 namespace lbm {
 
+struct Ctx;
+// Fused single-kernel steps; nullptr when no such kernel exists for the
+// combination.
+using FusedStepFn = void (*)(const Ctx&, const void* fin, void* fout);
+FusedStepFn fused_step_for(int lattice, int storage, int n_comp);  // tile kernel, D2Q9
+FusedStepFn sweep_step_for(int storage, int n_comp);               // strip sweep, D2Q9, nx % 64 == 0
+
 // Context behind the opaque lb_ctx handle.
 struct Ctx {
   lb_params prm;
@@ -31,7 +38,7 @@ struct Ctx {
 
   int64_t t = 0;
   int path = LB_PATH_SPLIT;
-  int fused_tile = 0;               // tile choice of the fused kernel
+  FusedStepFn fused = nullptr;      // kernel of LB_PATH_TILE / LB_PATH_SWEEP
 
   Params<float> pf;
   Params<double> pd;
@@ -54,10 +61,5 @@ struct SplitTable {
 };
 
 const SplitTable& split_table(int lattice, int storage);
-
-// Fused single-kernel step; nullptr when no fused kernel exists for the
-// combination.
-using FusedStepFn = void (*)(const Ctx&, const void* fin, void* fout);
-FusedStepFn fused_step_for(int lattice, int storage, int n_comp);
 
 }  // namespace lbm

@@ -9,6 +9,13 @@
 // Populations live in "pull" storage: slot (sigma, i, r) holds the
 // post-collision value f*_i computed at site r, so the population that sits
 // at site r at the next step is the one stored at r - v_i.
+//
+// Layout in HBM (pop_index): sites are grouped in blocks of 64 consecutive x
+// on one row (row = y + ny z); a block stores the N*Q populations of its 64
+// sites as N*Q contiguous runs of 64 values.  A wavefront that owns one
+// block reads and writes one contiguous N*Q*64-value region per step, so the
+// N*Q population streams do not land on the same HBM channels at the same
+// time (a plain structure of arrays puts them a power-of-two apart).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -26,6 +33,8 @@ struct Params {
   int log_form;   // 1: A = -c rho grad(mu - ln(rho)/3); 0: A = -c (rho grad mu - grad(rho)/3)
   int nx, ny, nz;
   long long S;    // nx * ny * nz
+  int nbx;        // 64-site blocks per row, ceil(nx / 64)
+  int nq;         // populations per site, N * Q
   T inv_tau;      // BGK rate 1/tau
   T cforce;       // c = w / tau = 1 - 1/(2 tau)
   T theta;        // temperature of the free energy
@@ -34,8 +43,15 @@ struct Params {
   T chi[kMaxComp * kMaxComp];  // leading dimension kMaxComp, symmetric
 };
 
-__device__ __forceinline__ float ln_(float x) { return logf(x); }
+// Natural logarithm and reciprocal in the working precision.  FP32 uses the
+// hardware v_log_f32 (log2, about 1 ulp) and v_rcp_f32 (1 ulp): each costs one
+// instruction instead of a correctly rounded library sequence, and their
+// error is far below the FP32 storage rounding that dominates that path.
+// FP64 uses the correctly rounded library functions.
+__device__ __forceinline__ float ln_(float x) { return __builtin_amdgcn_logf(x) * 0.693147180559945309f; }
 __device__ __forceinline__ double ln_(double x) { return log(x); }
+__device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_(double x) { return 1.0 / x; }
 
 // Potential that the force differentiates, at one site:
 //   mu^s = theta [ -1 + (1 + ln phi^s)/m^s - sum_t phi^t/m^t
@@ -51,7 +67,7 @@ __device__ __forceinline__ void site_potential(const Params<T>& p, const T (&rho
 #pragma unroll
   for (int s = 0; s < NC; ++s)
     if (s < n) rt += rho[s];
-  const T inv_rt = T(1) / rt;
+  const T inv_rt = rcp_(rt);
   const T ln_rt = ln_(rt);
   T phi[NC];
   T sum_phi_m = T(0);
@@ -113,6 +129,8 @@ __device__ __forceinline__ T site_psi(const Params<T>& p, const T (&rho)[NC]) {
 //   f*_i = f_i + (f^e_i - f_i)/tau + F_i
 //   f^e_i = w_i rho [1 + 3 v.u + 9/2 (v.u)^2 - 3/2 u.u]      (barycentric u)
 //   F_i   = w_i [3 v.A + 9 (v.A)(v.us) - 3 A.us]            (us = j / rho)
+// Opposite velocities share the even parts of f^e and F and flip the odd
+// ones, so each pair (i, opp(i)) is formed together.
 // The zeroth moments of f^e and F (rho and 0) fix the rest population:
 //   f*_0 = f_0 + sum_{i>0} (f_i - f*_i).
 // Written this way the stored populations keep their exact sum up to the
@@ -131,15 +149,23 @@ __device__ __forceinline__ void collide(T (&f)[Lattice<LAT>::Q], T rho, T ux, T 
   T defect = T(0);
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
+    if (L::opp(i) < i) continue;
+    const int j = L::opp(i);
     const T w = T(L::w(i));
+    const T wr = w * rho;
     const T vu = T(L::cx(i)) * ux + T(L::cy(i)) * uy + T(L::cz(i)) * uz;
     const T vA = T(L::cx(i)) * Ax + T(L::cy(i)) * Ay + T(L::cz(i)) * Az;
     const T vus = T(L::cx(i)) * usx + T(L::cy(i)) * usy + T(L::cz(i)) * usz;
-    const T feq = w * rho * (base + T(3) * vu + T(4.5) * vu * vu);
-    const T F = w * (T(3) * vA + T(9) * vA * vus - T(3) * Aus);
-    const T post = f[i] + inv_tau * (feq - f[i]) + F;
-    defect += f[i] - post;
-    f[i] = post;
+    const T e_even = wr * (base + T(4.5) * vu * vu);
+    const T e_odd = wr * (T(3) * vu);
+    const T F_even = w * (T(9) * vA * vus - T(3) * Aus);
+    const T F_odd = w * (T(3) * vA);
+    const T post_i = f[i] + inv_tau * ((e_even + e_odd) - f[i]) + (F_even + F_odd);
+    const T post_j = f[j] + inv_tau * ((e_even - e_odd) - f[j]) + (F_even - F_odd);
+    defect += f[i] - post_i;
+    defect += f[j] - post_j;
+    f[i] = post_i;
+    f[j] = post_j;
   }
   f[0] = f[0] + defect;
 }
@@ -185,6 +211,13 @@ __device__ __forceinline__ void lattice_force(const GH& h, const GR& r, T rho_s,
   Ax = -p.cforce * (rho_s * (T(3) * hx) - qx);
   Ay = -p.cforce * (rho_s * (T(3) * hy) - qy);
   Az = -p.cforce * (rho_s * (T(3) * hz) - qz);
+}
+
+constexpr int kBlockX = 64;
+
+// Storage index of population q = sigma * Q + i of site (x, row).
+__device__ __forceinline__ long long pop_index(int nbx, int nq, int q, int x, long long row) {
+  return ((row * nbx + (x >> 6)) * nq + q) * kBlockX + (x & (kBlockX - 1));
 }
 
 // Periodic neighbour coordinate: x + d with d in {-1, 0, 1}.

@@ -21,7 +21,7 @@ LB_OK, LB_EINVAL, LB_ENOMEM, LB_ENOTSUP, LB_EDEVICE, LB_ENUMERIC = 0, -1, -2, -3
 LATTICE = {"D1Q3": 1, "D2Q9": 2, "D3Q19": 3}
 STORAGE = {"f64": 0, "f32": 1}
 FORCE_FORM = {"log": 0, "expanded": 1}
-PATH = {"auto": 0, "fused": 1, "split": 2}
+PATH = {"auto": 0, "tile": 1, "split": 2, "sweep": 3}
 
 EXPORTS = [
     "lb_workspace_bytes", "lb_init", "lb_step", "lb_moments", "lb_get_f", "lb_state_bytes",
@@ -189,7 +189,7 @@ def lb_lattice_tables(lattice: str):
 
 def lb_path_in_use(ctx: int) -> str:
     r = _check(load().lb_path_in_use(C.c_void_p(ctx)))
-    return {1: "fused", 2: "split"}[r]
+    return {1: "tile", 2: "split", 3: "sweep"}[r]
 
 
 def lb_free(ctx: int) -> None:

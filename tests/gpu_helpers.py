@@ -9,6 +9,17 @@ from oracle import Oracle, OracleParams
 TOL = {"f64": 1e-12, "f32": 1e-5}
 
 
+def paths_for(cfg, storage):
+    """Kernel paths that support a run: split always; the tile kernel for
+    D2Q9; the strip sweep for D2Q9 in FP32 with nx a multiple of 64, N <= 4."""
+    paths = ["split"]
+    if cfg["lattice"] == "D2Q9":
+        paths.append("tile")
+        if storage == "f32" and cfg["shape"][0] % 64 == 0 and cfg["n_comp"] <= 4:
+            paths.append("sweep")
+    return paths
+
+
 def run_gpu(cfg, rho0, steps, storage="f64", path="auto", fields=True):
     from paper_0704_3444_amd import Simulation
 

@@ -52,9 +52,9 @@ def test_fullsize_sampled_sites_match_oracle(workload, storage, tol):
     from paper_0704_3444_amd import Simulation
 
     cfg, rho0 = workload
-    print(f"[fullsize] ternary {N_FULL}^2 {storage} fused, {K} steps", flush=True)
     sim = Simulation(cfg, rho0, storage=storage, path="auto")
-    assert sim.path == "fused"
+    print(f"[fullsize] ternary {N_FULL}^2 {storage} path={sim.path}, {K} steps", flush=True)
+    assert sim.path == ("sweep" if storage == "f32" else "tile")
     sim.step(K)
     out = sim.moments()
     sim.close()

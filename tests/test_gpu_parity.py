@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import lbinputs as LI
-from gpu_helpers import TOL, errors, run_gpu, run_oracle
+from gpu_helpers import TOL, errors, paths_for, run_gpu, run_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -22,6 +22,8 @@ def _cases():
     cases.append(("binary64_stable", p, r, 200))
     p, r = LI.ternary_immersion(96, ny=80)
     cases.append(("ternary_immersion_96x80", p, r, 200))
+    p, r = LI.ternary_immersion(128, ny=77)
+    cases.append(("ternary_immersion_128x77", p, r, 200))
     p, r = LI.binary_spinodal(130, lattice="D1Q3", chi=0.94, kappa=0.0)
     p["m"] = [10.0, 1.0]
     r = LI.sine_profile(p, [0.24, 0.76], amp=0.1)
@@ -41,10 +43,9 @@ CASES = _cases()
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 @pytest.mark.parametrize("name,cfg,rho0,steps", CASES, ids=[c[0] for c in CASES])
 def test_gpu_matches_oracle(name, cfg, rho0, steps, storage):
-    """Both kernel paths (the fused one exists for D2Q9) against the oracle."""
+    """Every kernel path that supports the run against the oracle."""
     o = run_oracle(cfg, rho0, steps)
-    paths = ["split", "fused"] if cfg["lattice"] == "D2Q9" else ["split"]
-    for path in paths:
+    for path in paths_for(cfg, storage):
         print(f"[parity] {name} storage={storage} path={path} steps={steps} shape={cfg['shape']}", flush=True)
         g = run_gpu(cfg, rho0, steps, storage=storage, path=path)
         assert g["path"] == path
@@ -57,58 +58,66 @@ def test_gpu_matches_oracle(name, cfg, rho0, steps, storage):
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])
-def test_fused_equals_split(storage):
-    """The two paths perform the same operations in the same order."""
-    cfg, rho0 = LI.ternary_immersion(150, ny=70)
+def test_fused_paths_equal_split(storage):
+    """The fused kernels perform the split path's operations in the same
+    order, so all paths agree bit for bit."""
+    cfg, rho0 = LI.ternary_immersion(192, ny=70)
     a = run_gpu(cfg, rho0, 40, storage=storage, path="split")
-    b = run_gpu(cfg, rho0, 40, storage=storage, path="fused")
-    d = np.abs(a["f"] - b["f"]).max() / np.abs(a["f"]).max()
-    print(f"[fused-vs-split] {storage} max rel diff {d:.3e}", flush=True)
-    assert d < (1e-14 if storage == "f64" else 1e-6)
+    for path in paths_for(cfg, storage)[1:]:
+        b = run_gpu(cfg, rho0, 40, storage=storage, path=path)
+        d = np.abs(a["f"] - b["f"]).max() / np.abs(a["f"]).max()
+        print(f"[fused-vs-split] {storage} {path} max rel diff {d:.3e}", flush=True)
+        assert d == 0.0, (path, d)
 
 
-@pytest.mark.parametrize("path", ["split", "fused"])
-def test_expanded_force_form_matches_oracle(path):
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_expanded_force_form_matches_oracle(storage):
     cfg, rho0 = LI.binary_spinodal(64)
     cfg["force_form"] = "expanded"
-    g = run_gpu(cfg, rho0, 200, path=path)
     o = run_oracle(cfg, rho0, 200)
-    e = errors(g, o)
-    assert e["rho"] < 1e-12 and e["f"] < 1e-12 and e["mu"] < 1e-12, e
+    for path in paths_for(cfg, storage):
+        g = run_gpu(cfg, rho0, 200, storage=storage, path=path)
+        e = errors(g, o)
+        tol = TOL[storage]
+        assert e["rho"] < tol and e["f"] < tol and e["mu"] < tol, (path, e)
 
 
-@pytest.mark.parametrize("path", ["split", "fused"])
-@pytest.mark.parametrize("shape", [(1, 1), (2, 3), (3, 1), (5, 2), (65, 17), (130, 33)])
-def test_degenerate_and_ragged_boxes(shape, path):
-    """Boxes smaller than the stencil (every neighbour wraps onto itself)
-    and boxes that leave partial tiles on both axes."""
+@pytest.mark.parametrize("shape", [(1, 1), (2, 3), (3, 1), (5, 2), (65, 17), (130, 33), (64, 1), (64, 3),
+                                   (128, 5), (192, 77)])
+def test_degenerate_and_ragged_boxes(shape):
+    """Boxes smaller than the stencil (every neighbour wraps onto itself),
+    boxes that leave partial tiles on both axes, and strips with ragged
+    segments for the sweep kernel."""
     p, _ = LI.binary_spinodal(4)
     p["shape"] = shape
     S = shape[0] * shape[1]
     r = LI.noisy_uniform(p, [0.5, 0.5], 0.01, 7)
+    o = run_oracle(p, r, 20)
     for storage in ("f64", "f32"):
-        g = run_gpu(p, r, 20, storage=storage, path=path)
-        o = run_oracle(p, r, 20)
-        e = errors(g, o)
-        assert e["rho"] < TOL[storage] and e["f"] < TOL[storage], (shape, S, storage, e)
+        for path in paths_for(p, storage):
+            g = run_gpu(p, r, 20, storage=storage, path=path)
+            e = errors(g, o)
+            assert e["rho"] < TOL[storage] and e["f"] < TOL[storage], (shape, S, storage, path, e)
 
 
-@pytest.mark.parametrize("n", [1, 4, 6, 8])
+@pytest.mark.parametrize("n", [1, 2, 4, 6, 8])
 def test_component_counts(n):
-    """N = 1 (pure fluid) up to the maximum N = 8, both paths, FP64."""
-    p = LI.params("D2Q9", n, (70, 20), kappa=0.01, m=[1.0 + (k % 3 == 1) for k in range(n)])
+    """N = 1 (pure fluid) up to the maximum N = 8, every path, both precisions."""
+    p = LI.params("D2Q9", n, (128, 20), kappa=0.01, m=[1.0 + (k % 3 == 1) for k in range(n)])
     chi = np.full((n, n), 1.0)
     np.fill_diagonal(chi, 0.0)
     p["chi"] = chi
     r = LI.noisy_uniform(p, [1.0 / n] * n, 0.005 / n, 11)
     o = run_oracle(p, r, 50)
-    for path in ("split", "fused"):
-        g = run_gpu(p, r, 50, path=path)
-        e = errors(g, o)
-        assert e["rho"] < 1e-12 and e["f"] < 1e-12 and e["mu"] < 1e-12, (n, path, e)
+    for storage in ("f64", "f32"):
+        for path in paths_for(p, storage):
+            g = run_gpu(p, r, 50, storage=storage, path=path)
+            e = errors(g, o)
+            tol = TOL[storage]
+            assert e["rho"] < tol and e["f"] < tol and e["mu"] < tol, (n, storage, path, e)
 
 
-@pytest.mark.parametrize("path", ["split", "fused"])
+@pytest.mark.parametrize("path", ["split", "tile"])
 def test_zero_steps_is_rest_equilibrium(path):
     cfg, rho0 = LI.ternary_immersion(40, ny=33)
     g = run_gpu(cfg, rho0, 0, path=path)

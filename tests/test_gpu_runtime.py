@@ -9,7 +9,11 @@ import lbinputs as LI
 
 pytestmark = pytest.mark.gpu
 
-PATHS = ["split", "fused"]
+PATHS = ["split", "tile", "sweep"]
+
+
+def storages(path):
+    return ["f32"] if path == "sweep" else ["f64", "f32"]
 
 
 def sim(cfg, rho0, **kw):
@@ -19,21 +23,21 @@ def sim(cfg, rho0, **kw):
 
 
 @pytest.mark.parametrize("path", PATHS)
-@pytest.mark.parametrize("storage", ["f64", "f32"])
-def test_bitwise_deterministic(path, storage):
-    cfg, rho0 = LI.ternary_immersion(70, ny=37)
-    a = sim(cfg, rho0, storage=storage, path=path)
-    b = sim(cfg, rho0, storage=storage, path=path)
-    a.step(60)
-    b.step(60)
-    assert a.get_state() == b.get_state()
-    a.close()
-    b.close()
+def test_bitwise_deterministic(path):
+    for storage in storages(path):
+        cfg, rho0 = LI.ternary_immersion(128 if path == "sweep" else 70, ny=37)
+        a = sim(cfg, rho0, storage=storage, path=path)
+        b = sim(cfg, rho0, storage=storage, path=path)
+        a.step(60)
+        b.step(60)
+        assert a.get_state() == b.get_state(), storage
+        a.close()
+        b.close()
 
 
 @pytest.mark.parametrize("path", PATHS)
 def test_checkpoint_resume_bitwise(path):
-    cfg, rho0 = LI.binary_spinodal(48)
+    cfg, rho0 = LI.binary_spinodal(64 if path == "sweep" else 48)
     a = sim(cfg, rho0, storage="f32", path=path)
     a.step(40)
     snap = a.get_state()
@@ -52,8 +56,10 @@ def test_checkpoint_resume_bitwise(path):
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_translation_equivariance_bitwise(path, storage):
     """Shifting the initial state by (dx, dy) shifts the result exactly;
-    shifts straddle the tiles of the fused kernel."""
-    nx, ny = 150, 77
+    shifts straddle the tiles, strips and segments of the fused kernels."""
+    if storage not in storages(path):
+        pytest.skip("the sweep kernel is FP32 only")
+    nx, ny = (128 if path == "sweep" else 150), 77
     cfg, rho0 = LI.ternary_immersion(nx, ny=ny)
     g = rho0.reshape(3, ny, nx)
     for dx, dy in ((37, 11), (64, 16), (1, 76)):
@@ -72,6 +78,8 @@ def test_translation_equivariance_bitwise(path, storage):
 @pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("storage,bar", [("f64", 1e-13), ("f32", 1e-6)])
 def test_mass_conserved_long_run(path, storage, bar):
+    if storage not in storages(path):
+        pytest.skip("the sweep kernel is FP32 only")
     cfg, rho0 = LI.binary_spinodal(128, seed=77)
     s = sim(cfg, rho0, storage=storage, path=path)
     m0 = rho0.sum(axis=1)
