@@ -90,10 +90,11 @@ __device__ __forceinline__ void load_halo4(const T* __restrict__ fin, const Para
   }
 }
 
-template <typename T, int NC>
+template <typename T, int NC, int PF>
 __global__ void __launch_bounds__(256) k_sweep_d2q9(const T* __restrict__ fin, T* __restrict__ fout, Params<T> p,
                                                     int strips, int seg_rows, int ntiles, int tiles_per_xcd) {
   using L = Lattice<2>;
+  static_assert(PF == 1 || PF == 2, "prefetch depth in rounds");
   __shared__ T s_rho[kRhoRing][NC][kRW];
   __shared__ T s_h[kHRing][NC][kHW];
 
@@ -162,43 +163,48 @@ __global__ void __launch_bounds__(256) k_sweep_d2q9(const T* __restrict__ fin, T
     if (w == kEdgeWave && lane < 8) put_h(r0 + (lane >> 1), (lane & 1) ? kHW - 1 : 0);
   };
 
-  T F0[NC][9], F1[NC][9], F2[NC][9], Hv[9];
+  // F[0]: row collided this round; F[1 .. PF]: rows whose density is formed
+  // in the next rounds (in flight); F[PF + 1]: the row prefetched this round.
+  // Hv[0 .. PF - 1]: halo values of the rows of F[1 .. PF]; Hv[PF] prefetched.
+  T F[PF + 2][NC][9], Hv[PF + 1][9];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) Hv[i] = T(0);
+  for (int s = 0; s <= PF; ++s)
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Hv[s][i] = T(0);
 
   // ---- prologue --------------------------------------------------------
   // rho of rows ya-2, ya-1 (waves 2, 3) and ya .. ya+3 (all waves); h of rows
-  // ya-1 .. ya+2; populations of rows ya + w (collided in round 0) in F1 and
-  // ya + 4 + w in flight in F2.
-  if (w >= 2) load_row<T, NC>(fin, p, x, wrap_mod(ya - 4 + w, ny), F0);
-  if (w == kHaloWave) load_halo4<T, NC>(fin, p, lane, x0, ya - 4, Hv);
-  if (w >= 2) put_rho(ya - 4 + w, F0);
-  if (w == kHaloWave) put_rho_halo(ya - 4, Hv);
-  load_row<T, NC>(fin, p, x, wrap_mod(ya + w, ny), F1);
-  if (w == kHaloWave) load_halo4<T, NC>(fin, p, lane, x0, ya, Hv);
-  put_rho(ya + w, F1);
-  if (w == kHaloWave) put_rho_halo(ya, Hv);
+  // ya-1 .. ya+2; populations of row ya + w (collided in round 0) in F[0] and
+  // of rows ya + 4j + w, j = 1 .. PF, in flight.
+  if (w >= 2) load_row<T, NC>(fin, p, x, wrap_mod(ya - 4 + w, ny), F[1]);
+  if (w == kHaloWave) load_halo4<T, NC>(fin, p, lane, x0, ya - 4, Hv[0]);
+  if (w >= 2) put_rho(ya - 4 + w, F[1]);
+  if (w == kHaloWave) put_rho_halo(ya - 4, Hv[0]);
+  load_row<T, NC>(fin, p, x, wrap_mod(ya + w, ny), F[0]);
+  if (w == kHaloWave) load_halo4<T, NC>(fin, p, lane, x0, ya, Hv[0]);
+  put_rho(ya + w, F[0]);
+  if (w == kHaloWave) put_rho_halo(ya, Hv[0]);
   __syncthreads();
   put_h4(ya - 1);
   __syncthreads();
-  load_row<T, NC>(fin, p, x, wrap_mod(ya + 4 + w, ny), F2);
-  if (w == kHaloWave) load_halo4<T, NC>(fin, p, lane, x0, ya + 4, Hv);
+#pragma unroll
+  for (int j = 1; j <= PF; ++j) {
+    load_row<T, NC>(fin, p, x, wrap_mod(ya + 4 * j + w, ny), F[j]);
+    if (w == kHaloWave) load_halo4<T, NC>(fin, p, lane, x0, ya + 4 * j, Hv[j - 1]);
+  }
 
   // ---- rounds ------------------------------------------------------------
-  // Entering round k: Fc holds row ya+4k+w (rho already in LDS), Fa holds
-  // row ya+4k+4+w (in flight), Hv the halo values of rows ya+4k+4 .. +7;
-  // the round prefetches row ya+4k+8+w into Fn.
-  auto round = [&](int k, T (&Fc)[NC][9], T (&Fa)[NC][9], T (&Fn)[NC][9]) __attribute__((always_inline)) {
+  for (int k = 0; k < rounds; ++k) {
     const int rc = ya + 4 * k + w;  // row collided by this wave
     const int ra = rc + 4;          // row whose density is formed this round
-    put_rho(ra, Fa);
-    if (w == kHaloWave) put_rho_halo(ya + 4 * k + 4, Hv);
+    put_rho(ra, F[1]);
+    if (w == kHaloWave) put_rho_halo(ya + 4 * k + 4, Hv[0]);
     __syncthreads();
     put_h4(ya + 4 * k + 3);
     __syncthreads();
-    if (k + 1 < rounds) {
-      load_row<T, NC>(fin, p, x, wrap_mod(ra + 4, ny), Fn);
-      if (w == kHaloWave) load_halo4<T, NC>(fin, p, lane, x0, ya + 4 * k + 8, Hv);
+    if (k + PF < rounds) {
+      load_row<T, NC>(fin, p, x, wrap_mod(ra + 4 * PF, ny), F[PF + 1]);
+      if (w == kHaloWave) load_halo4<T, NC>(fin, p, lane, x0, ya + 4 * k + 4 + 4 * PF, Hv[PF]);
     }
     if (rc < yb) {
       const int sr = rslot(rc);
@@ -209,8 +215,8 @@ __global__ void __launch_bounds__(256) k_sweep_d2q9(const T* __restrict__ fin, T
         T ax = T(0), ay = T(0);
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
-          if (L::cx(i)) ax += T(L::cx(i)) * Fc[c][i];
-          if (L::cy(i)) ay += T(L::cy(i)) * Fc[c][i];
+          if (L::cx(i)) ax += T(L::cx(i)) * F[0][c][i];
+          if (L::cy(i)) ay += T(L::cy(i)) * F[0][c][i];
         }
         jx[c] = ax;
         jy[c] = ay;
@@ -239,26 +245,27 @@ __global__ void __launch_bounds__(256) k_sweep_d2q9(const T* __restrict__ fin, T
             },
             rs[c], p, Ax, Ay, Az);
         const T inv_rs = rcp_(rs[c]);
-        collide<2, T>(Fc[c], rs[c], ux, uy, T(0), Ax, Ay, Az, jx[c] * inv_rs, jy[c] * inv_rs, T(0), p.inv_tau);
+        collide<2, T>(F[0][c], rs[c], ux, uy, T(0), Ax, Ay, Az, jx[c] * inv_rs, jy[c] * inv_rs, T(0),
+                      p.inv_tau);
 #pragma unroll
         for (int i = 0; i < 9; ++i)
           __builtin_nontemporal_store(
-              Fc[c][i], reinterpret_cast<T*>(reinterpret_cast<char*>(fout) + own +
-                                             uint32_t((c * 9 + i) * kW * sizeof(T))));
+              F[0][c][i], reinterpret_cast<T*>(reinterpret_cast<char*>(fout) + own +
+                                               uint32_t((c * 9 + i) * kW * sizeof(T))));
       }
     }
-  };
-  for (int k = 0; k < rounds; ++k) {
-    round(k, F1, F2, F0);
-    // rotate: F1 <- row ya+4k+4+w, F2 <- row ya+4k+8+w (register moves; an
-    // unrolled renaming needs more registers than one occupancy step allows)
+    // rotate the register sets (moves; the rotation is not renamed by unrolling
+    // because that needs more registers than one occupancy step allows)
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
+    for (int s = 0; s <= PF; ++s)
 #pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        F1[c][i] = F2[c][i];
-        F2[c][i] = F0[c][i];
-      }
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int i = 0; i < 9; ++i) F[s][c][i] = F[s + 1][c][i];
+#pragma unroll
+    for (int s = 0; s < PF; ++s)
+#pragma unroll
+      for (int i = 0; i < 9; ++i) Hv[s][i] = Hv[s + 1][i];
   }
 }
 
@@ -284,7 +291,7 @@ static void launch_sweep(const Ctx& c, const void* fin, void* fout) {
   const int rows = sweep_rows(p.nx, p.ny);
   const int ntiles = strips * ((p.ny + rows - 1) / rows);
   const int per_xcd = (ntiles + sweep::kXcds - 1) / sweep::kXcds;
-  sweep::k_sweep_d2q9<T, NC><<<per_xcd * sweep::kXcds, 256, 0, c.stream>>>(
+  sweep::k_sweep_d2q9<T, NC, 1><<<per_xcd * sweep::kXcds, 256, 0, c.stream>>>(
       static_cast<const T*>(fin), static_cast<T*>(fout), p, strips, rows, ntiles, per_xcd);
 }
 
