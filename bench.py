@@ -2,7 +2,7 @@
 multicomponent LB method (Li & Wagner) on the ternary D2Q9 2048 x 2048
 immersion-precipitation workload, FP32, one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--storage f32|f64]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--storage f32|f64|f16s]
                     [--workload NAME] [--no-cpu] [--calibrate-copy]
 
 Prints one JSON line.  `value` is MLUPS x components (sites x components x
@@ -10,7 +10,7 @@ steps / second / 1e6) with the state resident in HBM; the timed region is K
 lb_step calls bracketed by synchronisation and HIP events on the stream the
 kernels run on.  `roofline` prices the fused step kernel against the HBM
 peak: its algorithmic traffic per launch is every population read once and
-written once, 2 * Q * N * S * bytes.  `cpu_baseline` times the FP64 CPU
+written once, 2 * N * S * (rest + (Q - 1) * moving slot bytes).  `cpu_baseline` times the FP64 CPU
 oracle on a bounded sample of the same workload on the host cores.
 """
 import argparse
@@ -26,7 +26,10 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS×components at 2048² ternary, % HBM peak; serving p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_0704_3444_amd/csrc/k_sweep2d.hip", "paper_0704_3444_amd/csrc/k_fused2d.hip",
-                  "paper_0704_3444_amd/csrc/physics.hpp", "paper_0704_3444_amd/csrc/lattice.hpp"]
+                  "paper_0704_3444_amd/csrc/physics.hpp", "paper_0704_3444_amd/csrc/lattice.hpp",
+                  "paper_0704_3444_amd/csrc/storage.hpp"]
+# bytes of one stored population: (rest slot, moving slot)
+STORE_BYTES = {"f64": (8, 8), "f32": (4, 4), "f16s": (4, 2)}
 
 
 def kernel_source_hash() -> str:
@@ -105,7 +108,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--storage", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--storage", default="f32", choices=["f32", "f64", "f16s"])
     ap.add_argument("--workload", default="ternary_d2q9_2048")
     ap.add_argument("--path", default="auto", choices=["auto", "sweep", "tile", "split"])
     ap.add_argument("--no-cpu", action="store_true")
@@ -134,7 +137,7 @@ def main():
     S = int(np.prod(shape))
     N = int(cfg["n_comp"])
     Q = {"D1Q3": 3, "D2Q9": 9, "D3Q19": 19}[cfg["lattice"]]
-    nbytes = 4 if args.storage == "f32" else 8
+    rest_b, move_b = STORE_BYTES[args.storage]
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
@@ -163,7 +166,7 @@ def main():
     sim.close()
 
     kernels_per_step = 3 if path == "split" else 1
-    alg_bytes = 2 * Q * N * S * nbytes
+    alg_bytes = 2 * N * S * (rest_b + (Q - 1) * move_b)
     achieved = alg_bytes / (ms_per_step / 1e3) / 1e9
     traffic = measured_traffic(args.workload, args.storage, path)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -181,7 +184,7 @@ def main():
         "metric": METRIC, "value": round(value, 1), "unit": "MLUPS×components", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": args.storage, "data": "synthetic",
+        "dtype": "f64" if args.storage == "f64" else "f32", "data": "synthetic",
         "config": {"workload": args.workload, "lattice": cfg["lattice"], "shape": shape[: len(cfg["shape"])],
                    "n_comp": N, "storage": args.storage, "path": path, "force_form": cfg["force_form"]},
         "hbm_frac": round(achieved / HBM_PEAK_GBS, 4),

@@ -54,9 +54,21 @@ typedef enum lb_status {
 typedef enum lb_lattice { LB_D1Q3 = 1, LB_D2Q9 = 2, LB_D3Q19 = 3 } lb_lattice;
 
 /* Storage and arithmetic precision of the populations.
- *   LB_F64: stored and computed in FP64.
- *   LB_F32: stored and computed in FP32. */
-typedef enum lb_storage { LB_F64 = 0, LB_F32 = 1 } lb_storage;
+ *   LB_F64:  stored and computed in FP64.
+ *   LB_F32:  stored and computed in FP32.
+ *   LB_F16S: computed in FP32; each moving population (i > 0) is stored as
+ *            the FP16 deviation (f_i - w_i rbar^sigma) / s^sigma from the
+ *            equilibrium at the mean density rbar^sigma of rho0^sigma, with
+ *            s^sigma the smallest power of two >= max rho0^sigma; the rest
+ *            slot holds an FP32 ledger that absorbs the FP16 rounding, so
+ *            that every collision keeps each component's mass exactly.
+ *            Populations take 2 bytes, the rest slot 4 (20 bytes per site
+ *            and component on D2Q9, against 36 for LB_F32).  The rounding
+ *            error of a stored value is at most 2^-11 of its deviation from
+ *            w_i rbar^sigma: small where the mixture is near its mean
+ *            composition, as large as plain FP16 where a component is far
+ *            from its mean (a phase-separated minority). */
+typedef enum lb_storage { LB_F64 = 0, LB_F32 = 1, LB_F16S = 2 } lb_storage;
 
 /* Which line of Eq. (definef) forms the force rho^sigma a^sigma, with
  * c = 1 - 1/(2 tau):
@@ -71,11 +83,12 @@ typedef enum lb_force_form { LB_FORCE_LOG = 0, LB_FORCE_EXPANDED = 1 } lb_force_
  *   LB_PATH_AUTO:  the fastest path that supports the run (sweep, then tile,
  *                  then split).
  *   LB_PATH_TILE:  fused one-kernel D2Q9 step over 2-D tiles with a two-site
- *                  density halo (any nx, FP64 and FP32).
+ *                  density halo (any nx, LB_F64 and LB_F32).
  *   LB_PATH_SPLIT: three kernels per step (density, potential, collide and
  *                  stream); every lattice.
  *   LB_PATH_SWEEP: fused one-kernel D2Q9 step that sweeps 64-column strips
- *                  row by row (FP32, N <= 4, nx a multiple of 64).
+ *                  row by row (LB_F32 or LB_F16S, N <= 4, nx a multiple of
+ *                  64).
  * Asking for a path that does not support the run gives LB_ENOTSUP. */
 typedef enum lb_path { LB_PATH_AUTO = 0, LB_PATH_TILE = 1, LB_PATH_SPLIT = 2, LB_PATH_SWEEP = 3 } lb_path;
 
@@ -149,10 +162,11 @@ int lb_moments(lb_ctx* c, double* rho, double* U, double* mu, double* P, double*
  * velocity order of the lattice tables (lb_lattice_tables).  Synchronises. */
 int lb_get_f(lb_ctx* c, double* f);
 
-/* Checkpoint: the raw device state (storage precision) plus the step
- * counter.  lb_state_bytes gives the size; lb_get_state copies it to host
- * memory, lb_set_state restores it into a context created with the same
- * parameters.  Both synchronise. */
+/* Checkpoint: the raw device state (storage precision), the reference of
+ * LB_F16S storage (rbar^sigma and s^sigma; zero for the other storages) and
+ * the step counter.  lb_state_bytes gives the size; lb_get_state copies it
+ * to host memory, lb_set_state restores it into a context created with the
+ * same parameters (any rho0).  Both synchronise. */
 size_t lb_state_bytes(const lb_ctx* c);
 int lb_get_state(lb_ctx* c, void* host, size_t bytes);
 int lb_set_state(lb_ctx* c, const void* host, size_t bytes);

@@ -283,7 +283,9 @@ static FusedStepFn pick_n(int n) {
 
 FusedStepFn fused_step_for(int lattice, int storage, int n_comp) {
   if (lattice != 2) return nullptr;  // slot-count limit checked by the caller
-  return storage == 0 ? pick_n<double>(n_comp) : pick_n<float>(n_comp);
+  if (storage == 0) return pick_n<double>(n_comp);
+  if (storage == 1) return pick_n<float>(n_comp);
+  return nullptr;  // shifted FP16 storage: split and sweep paths only
 }
 
 }  // namespace lbm

@@ -7,10 +7,13 @@
 // fused D2Q9 kernel.  The same kernels, instantiated in FP64, produce the
 // observables of lb_moments.  k_diag/k_diag_final form the FP64 mass and
 // momentum sums and the density health flag with a fixed reduction order.
+// Every kernel is templated on the storage codec S (storage.hpp): T is its
+// working precision; stored slots are decoded on load and encoded on store.
 #include <hip/hip_runtime.h>
 
 #include "lbm_internal.hpp"
 #include "physics.hpp"
+#include "storage.hpp"
 
 namespace lbm {
 
@@ -43,60 +46,139 @@ __device__ __forceinline__ long long neighbour(const SiteCoord& c, int i, int si
                  wrap_add(c.z, sign * L::cz(i), p.nz), p);
 }
 
-template <typename S>
-__device__ __forceinline__ double to_d(S v) { return double(v); }
-
-// Storage index of population q at the site r - v_i (the slot pulled into r).
-template <int LAT, typename T>
-__device__ __forceinline__ long long pull_index(const SiteCoord& c, int q, int i, const Params<T>& p) {
+// Byte offset of population i of component k at the site r - v_i (the slot
+// pulled into r).
+template <class S, int LAT, typename T>
+__device__ __forceinline__ uint64_t pull_byte(const SiteCoord& c, int k, int i, const Params<T>& p) {
   using L = Lattice<LAT>;
   const int sx = wrap_add(c.x, -L::cx(i), p.nx);
   const int sy = wrap_add(c.y, -L::cy(i), p.ny);
   const int sz = wrap_add(c.z, -L::cz(i), p.nz);
-  return pop_index(p.nbx, p.nq, q, sx, (long long)sy + (long long)p.ny * sz);
+  return pop_byte<S, L::Q>(p.n, p.nbx, k, i, sx, (long long)sy + (long long)p.ny * sz);
 }
 
-// Storage index of population q at the site itself.
-template <typename T>
-__device__ __forceinline__ long long own_index(const SiteCoord& c, int q, const Params<T>& p) {
-  return pop_index(p.nbx, p.nq, q, c.x, (long long)c.y + (long long)p.ny * c.z);
+// Byte offset of population i of component k at the site itself.
+template <class S, int LAT, typename T>
+__device__ __forceinline__ uint64_t own_byte(const SiteCoord& c, int k, int i, const Params<T>& p) {
+  return pop_byte<S, Lattice<LAT>::Q>(p.n, p.nbx, k, i, c.x, (long long)c.y + (long long)p.ny * c.z);
+}
+
+// Populations of component k pulled into site c, decoded to the working
+// precision, and the site's ledger (shifted codec only).
+template <class S, int LAT>
+__device__ __forceinline__ void pull_pops(const void* fin, const SiteCoord& c, int k,
+                                          const Params<typename S::T>& p,
+                                          typename S::T (&f)[Lattice<LAT>::Q], typename S::T& ledger) {
+  using T = typename S::T;
+  ledger = T(0);
+#pragma unroll
+  for (int i = 0; i < Lattice<LAT>::Q; ++i) {
+    const T raw = load_slot<S>(fin, pull_byte<S, LAT>(c, k, i, p), i);
+    ledger = i == 0 ? raw : ledger + raw;
+    f[i] = decode<S, LAT>(p.sh, k, i, raw);
+  }
+}
+
+// Populations of component k pulled into site c, exactly, in FP64.
+template <class S, int LAT, typename PT>
+__device__ __forceinline__ void pull_pops_exact(const void* fin, const SiteCoord& c, int k, const Params<PT>& p,
+                                                double (&f)[Lattice<LAT>::Q]) {
+#pragma unroll
+  for (int i = 0; i < Lattice<LAT>::Q; ++i)
+    f[i] = decode_exact<S, LAT>(p.sh, k, i, load_slot<S>(fin, pull_byte<S, LAT>(c, k, i, p), i));
+}
+
+// Store the post-collision populations of component k at site c.  Plain
+// codecs write the values; the shifted codec writes the FP16 deviations of
+// the moving populations and puts the rest of the ledger into slot 0.
+template <class S, int LAT>
+__device__ __forceinline__ void store_pops(void* fout, const SiteCoord& c, int k, const Params<typename S::T>& p,
+                                           const typename S::T (&post)[Lattice<LAT>::Q], typename S::T ledger) {
+  using T = typename S::T;
+  char* out = static_cast<char*>(fout);
+  if constexpr (S::kShift) {
+    T rest = ledger;
+#pragma unroll
+    for (int i = 1; i < Lattice<LAT>::Q; ++i) {
+      const _Float16 d = encode_move<LAT>(p.sh, k, i, post[i]);
+      rest -= float(d);
+      *reinterpret_cast<_Float16*>(out + own_byte<S, LAT>(c, k, i, p)) = d;
+    }
+    *reinterpret_cast<float*>(out + own_byte<S, LAT>(c, k, 0, p)) = rest;
+  } else {
+#pragma unroll
+    for (int i = 0; i < Lattice<LAT>::Q; ++i) *reinterpret_cast<T*>(out + own_byte<S, LAT>(c, k, i, p)) = post[i];
+  }
 }
 
 // ---------------------------------------------------------------- init ----
 // Rest equilibrium f_i(r, 0) = w_i rho0(r), written in pull storage: slot
-// (i, r) holds the value that arrives at r + v_i.
-template <int LAT, typename T>
-__global__ void __launch_bounds__(kBlock) k_init(const double* __restrict__ rho0, T* __restrict__ f,
-                                                 Params<T> p) {
+// (i, r) holds the value that arrives at r + v_i.  The shifted codec stores
+// the FP16 deviations of the moving slots, and in the rest slot of r the
+// ledger that makes the site's stored total equal rho0(r) (to 2^-25 s).
+template <class S, int LAT>
+__global__ void __launch_bounds__(kBlock) k_init(const double* __restrict__ rho0, void* __restrict__ f,
+                                                 Params<typename S::T> p) {
   using L = Lattice<LAT>;
+  using T = typename S::T;
   const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= p.S) return;
   const SiteCoord c = coord_of(s, p);
+  char* out = static_cast<char*>(f);
   for (int k = 0; k < p.n; ++k) {
+    if constexpr (S::kShift) {
+      const double r0 = rho0[(long long)k * p.S + s];
+      double target = r0;
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) {
-      const long long src = neighbour<LAT>(c, i, +1, p);
-      f[own_index(c, k * L::Q + i, p)] = T(L::w(i) * rho0[(long long)k * p.S + src]);
+      for (int i = 0; i < L::Q; ++i) target -= double(shift_ref<LAT>(p.sh, k, i));
+      target /= double(p.sh.scale[k]);
+#pragma unroll
+      for (int i = 1; i < L::Q; ++i) {
+        // the slot pulled into r carries w_i rho0(r); the slot written here
+        // carries w_i rho0(r + v_i)
+        target -= double(encode_move<LAT>(p.sh, k, i, float(L::w(i) * r0)));
+        const double rn = rho0[(long long)k * p.S + neighbour<LAT>(c, i, +1, p)];
+        *reinterpret_cast<_Float16*>(out + own_byte<S, LAT>(c, k, i, p)) =
+            encode_move<LAT>(p.sh, k, i, float(L::w(i) * rn));
+      }
+      *reinterpret_cast<float*>(out + own_byte<S, LAT>(c, k, 0, p)) =
+          float(rint(target * 16777216.0) / 16777216.0);
+    } else {
+#pragma unroll
+      for (int i = 0; i < L::Q; ++i) {
+        const long long src = neighbour<LAT>(c, i, +1, p);
+        *reinterpret_cast<T*>(out + own_byte<S, LAT>(c, k, i, p)) = T(L::w(i) * rho0[(long long)k * p.S + src]);
+      }
     }
   }
 }
 
 // ------------------------------------------------------------- density ----
 // rho^sigma(r) = sum_i f_i(r): the population at r in direction i is the
-// slot (i, r - v_i).  TO is the output type (T for the step, double for the
-// observables).
-template <int LAT, typename T, typename TO>
-__global__ void __launch_bounds__(kBlock) k_density(const T* __restrict__ f, TO* __restrict__ rho,
-                                                    Params<T> p) {
+// slot (i, r - v_i).  The step takes it in the working precision (plain
+// codecs: the sum in direction order; shifted codec: from the ledger); the
+// observables take the exact stored values summed in FP64.
+template <class S, int LAT, typename TO>
+__global__ void __launch_bounds__(kBlock) k_density(const void* __restrict__ f, TO* __restrict__ rho,
+                                                    Params<typename S::T> p) {
   using L = Lattice<LAT>;
+  using T = typename S::T;
   const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= p.S) return;
   const SiteCoord c = coord_of(s, p);
   for (int k = 0; k < p.n; ++k) {
-    TO acc = TO(0);
+    if constexpr (sizeof(TO) > sizeof(T)) {
+      double v[L::Q];
+      pull_pops_exact<S, LAT>(f, c, k, p, v);
+      double acc = 0.0;
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) acc += TO(f[pull_index<LAT>(c, k * L::Q + i, i, p)]);
-    rho[(long long)k * p.S + s] = acc;
+      for (int i = 0; i < L::Q; ++i) acc += v[i];
+      rho[(long long)k * p.S + s] = acc;
+    } else {
+      T v[L::Q], ledger;
+      pull_pops<S, LAT>(f, c, k, p, v, ledger);
+      rho[(long long)k * p.S + s] = site_density<S, L::Q>(p.sh, k, v, ledger);
+    }
   }
 }
 
@@ -132,11 +214,12 @@ __global__ void __launch_bounds__(kBlock) k_potential(const T* __restrict__ rho,
 }
 
 // ------------------------------------------------------------- collide ----
-template <int LAT, typename T>
-__global__ void __launch_bounds__(kBlock) k_collide(const T* __restrict__ fin, T* __restrict__ fout,
-                                                    const T* __restrict__ rho, const T* __restrict__ h,
-                                                    Params<T> p) {
+template <class S, int LAT>
+__global__ void __launch_bounds__(kBlock) k_collide(const void* __restrict__ fin, void* __restrict__ fout,
+                                                    const typename S::T* __restrict__ rho,
+                                                    const typename S::T* __restrict__ h, Params<typename S::T> p) {
   using L = Lattice<LAT>;
+  using T = typename S::T;
   constexpr int Q = L::Q;
   const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= p.S) return;
@@ -148,13 +231,14 @@ __global__ void __launch_bounds__(kBlock) k_collide(const T* __restrict__ fin, T
   T jx[kMaxComp], jy[kMaxComp], jz[kMaxComp];
   T rt = T(0), ux = T(0), uy = T(0), uz = T(0);
   for (int k = 0; k < p.n; ++k) {
+    T f[Q], ledger;
+    pull_pops<S, LAT>(fin, c, k, p, f, ledger);
     T ax = T(0), ay = T(0), az = T(0);
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-      const T fi = fin[pull_index<LAT>(c, k * Q + i, i, p)];
-      if (L::cx(i)) ax += T(L::cx(i)) * fi;
-      if (L::cy(i)) ay += T(L::cy(i)) * fi;
-      if (L::cz(i)) az += T(L::cz(i)) * fi;
+      if (L::cx(i)) ax += T(L::cx(i)) * f[i];
+      if (L::cy(i)) ay += T(L::cy(i)) * f[i];
+      if (L::cz(i)) az += T(L::cz(i)) * f[i];
     }
     jx[k] = ax;
     jy[k] = ay;
@@ -170,9 +254,8 @@ __global__ void __launch_bounds__(kBlock) k_collide(const T* __restrict__ fin, T
   uz *= inv_rt;
   for (int k = 0; k < p.n; ++k) {
     const T rs = rho[(long long)k * p.S + s];
-    T f[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) f[i] = fin[pull_index<LAT>(c, k * Q + i, i, p)];
+    T f[Q], ledger;
+    pull_pops<S, LAT>(fin, c, k, p, f, ledger);
     const T* hk = h + (long long)k * p.S;
     const T* rk = rho + (long long)k * p.S;
     T Ax, Ay, Az;
@@ -181,8 +264,7 @@ __global__ void __launch_bounds__(kBlock) k_collide(const T* __restrict__ fin, T
     const T inv_rs = rcp_(rs);
     collide<LAT, T>(f, rs, ux, uy, uz, Ax, Ay, Az, jx[k] * inv_rs, jy[k] * inv_rs, jz[k] * inv_rs,
                     p.inv_tau);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) fout[own_index(c, k * Q + i, p)] = f[i];
+    store_pops<S, LAT>(fout, c, k, p, f, ledger);
   }
 }
 
@@ -191,8 +273,8 @@ __global__ void __launch_bounds__(kBlock) k_collide(const T* __restrict__ fin, T
 //   P_ab = [p0 - kappa sum_s (rho lap rho + |grad rho|^2 / 2)] d_ab
 //        + kappa sum_s d_a rho d_b rho,     p0 = sum_s rho mu0 - psi,
 // all in FP64 from the stored populations (converted exactly to FP64).
-template <int LAT, typename T>
-__global__ void __launch_bounds__(kBlock) k_observe(const T* __restrict__ fin, const double* __restrict__ rho,
+template <class S, int LAT>
+__global__ void __launch_bounds__(kBlock) k_observe(const void* __restrict__ fin, const double* __restrict__ rho,
                                                     const double* __restrict__ h, double* __restrict__ U,
                                                     double* __restrict__ P, Params<double> p) {
   using L = Lattice<LAT>;
@@ -211,12 +293,13 @@ __global__ void __launch_bounds__(kBlock) k_observe(const T* __restrict__ fin, c
     g[k][0] = g[k][1] = g[k][2] = 0.0;
   }
   for (int k = 0; k < p.n; ++k) {
+    double fk[Q];
+    pull_pops_exact<S, LAT>(fin, c, k, p, fk);
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-      const double fi = to_d(fin[pull_index<LAT>(c, k * Q + i, i, p)]);
-      jt[0] += L::cx(i) * fi;
-      jt[1] += L::cy(i) * fi;
-      jt[2] += L::cz(i) * fi;
+      jt[0] += L::cx(i) * fk[i];
+      jt[1] += L::cy(i) * fk[i];
+      jt[2] += L::cz(i) * fk[i];
     }
     const double* rk = rho + (long long)k * p.S;
     r[k] = rk[s];
@@ -264,17 +347,19 @@ __global__ void __launch_bounds__(kBlock) k_observe(const T* __restrict__ fin, c
 }
 
 // Populations at the current time, FP64 [N][Q][S].
-template <int LAT, typename T>
-__global__ void __launch_bounds__(kBlock) k_unpull(const T* __restrict__ fin, double* __restrict__ out,
-                                                   Params<T> p) {
+template <class S, int LAT>
+__global__ void __launch_bounds__(kBlock) k_unpull(const void* __restrict__ fin, double* __restrict__ out,
+                                                   Params<typename S::T> p) {
   using L = Lattice<LAT>;
   const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= p.S) return;
   const SiteCoord c = coord_of(s, p);
-  for (int k = 0; k < p.n; ++k)
+  for (int k = 0; k < p.n; ++k) {
+    double fk[L::Q];
+    pull_pops_exact<S, LAT>(fin, c, k, p, fk);
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i)
-      out[((long long)k * L::Q + i) * p.S + s] = to_d(fin[pull_index<LAT>(c, k * L::Q + i, i, p)]);
+    for (int i = 0; i < L::Q; ++i) out[((long long)k * L::Q + i) * p.S + s] = fk[i];
+  }
 }
 
 // ---------------------------------------------------------- diagnostics ----
@@ -287,9 +372,9 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-template <int LAT, typename T>
-__global__ void __launch_bounds__(kBlock) k_diag(const T* __restrict__ fin, double* __restrict__ partial,
-                                                 Params<T> p) {
+template <class S, int LAT>
+__global__ void __launch_bounds__(kBlock) k_diag(const void* __restrict__ fin, double* __restrict__ partial,
+                                                 Params<typename S::T> p) {
   using L = Lattice<LAT>;
   constexpr int Q = L::Q, D = L::D;
   constexpr int K = kMaxComp + D + 1;
@@ -302,10 +387,12 @@ __global__ void __launch_bounds__(kBlock) k_diag(const T* __restrict__ fin, doub
 #pragma unroll
     for (int k = 0; k < kMaxComp; ++k) {
       if (k < p.n) {
+        double fk[Q];
+        pull_pops_exact<S, LAT>(fin, c, k, p, fk);
         double r = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-          const double fi = to_d(fin[pull_index<LAT>(c, k * Q + i, i, p)]);
+          const double fi = fk[i];
           r += fi;
           jx += L::cx(i) * fi;
           jy += L::cy(i) * fi;
@@ -358,51 +445,53 @@ __global__ void k_diag_final(const double* __restrict__ partial, int nblocks, in
 // ------------------------------------------------------------ launchers ----
 static inline unsigned grid_for(long long S) { return unsigned((S + kBlock - 1) / kBlock); }
 
-template <int LAT, typename T>
+template <class S, int LAT>
 struct SplitOps {
+  using T = typename S::T;
   static void init(const Ctx& c, const double* rho0_dev, void* f) {
-    k_init<LAT, T><<<grid_for(c.S), kBlock, 0, c.stream>>>(rho0_dev, static_cast<T*>(f), c.params<T>());
+    k_init<S, LAT><<<grid_for(c.S), kBlock, 0, c.stream>>>(rho0_dev, f, c.params<T>());
   }
   static void step(const Ctx& c, const void* fin, void* fout) {
     const Params<T>& p = c.params<T>();
     T* rho = static_cast<T*>(c.rho_scratch);
     T* h = static_cast<T*>(c.h_scratch);
-    k_density<LAT, T, T><<<grid_for(c.S), kBlock, 0, c.stream>>>(static_cast<const T*>(fin), rho, p);
+    k_density<S, LAT, T><<<grid_for(c.S), kBlock, 0, c.stream>>>(fin, rho, p);
     k_potential<LAT, T><<<grid_for(c.S), kBlock, 0, c.stream>>>(rho, nullptr, h, p);
-    k_collide<LAT, T><<<grid_for(c.S), kBlock, 0, c.stream>>>(static_cast<const T*>(fin),
-                                                               static_cast<T*>(fout), rho, h, p);
+    k_collide<S, LAT><<<grid_for(c.S), kBlock, 0, c.stream>>>(fin, fout, rho, h, p);
   }
   static void observe(const Ctx& c, const void* fin, double* rho, double* mu, double* h, double* U,
                       double* P) {
-    k_density<LAT, T, double><<<grid_for(c.S), kBlock, 0, c.stream>>>(static_cast<const T*>(fin), rho,
-                                                                       c.params<T>());
+    k_density<S, LAT, double><<<grid_for(c.S), kBlock, 0, c.stream>>>(fin, rho, c.params<T>());
     k_potential<LAT, double><<<grid_for(c.S), kBlock, 0, c.stream>>>(rho, mu, h, c.pd);
-    k_observe<LAT, T><<<grid_for(c.S), kBlock, 0, c.stream>>>(static_cast<const T*>(fin), rho, h, U, P, c.pd);
+    k_observe<S, LAT><<<grid_for(c.S), kBlock, 0, c.stream>>>(fin, rho, h, U, P, c.pd);
   }
   static void unpull(const Ctx& c, const void* fin, double* out) {
-    k_unpull<LAT, T><<<grid_for(c.S), kBlock, 0, c.stream>>>(static_cast<const T*>(fin), out, c.params<T>());
+    k_unpull<S, LAT><<<grid_for(c.S), kBlock, 0, c.stream>>>(fin, out, c.params<T>());
   }
   static void diag(const Ctx& c, const void* fin) {
     constexpr int K = kMaxComp + Lattice<LAT>::D + 1;
-    k_diag<LAT, T><<<c.diag_blocks, kBlock, 0, c.stream>>>(static_cast<const T*>(fin), c.diag_partial,
-                                                             c.params<T>());
+    k_diag<S, LAT><<<c.diag_blocks, kBlock, 0, c.stream>>>(fin, c.diag_partial, c.params<T>());
     k_diag_final<<<1, 64, 0, c.stream>>>(c.diag_partial, c.diag_blocks, K, c.diag_out, c.health_flag);
   }
 };
 
-template <typename T>
+template <class S>
 static const SplitTable& table_for_lattice(int lattice) {
-  static const SplitTable t1 = {SplitOps<1, T>::init, SplitOps<1, T>::step, SplitOps<1, T>::observe,
-                                SplitOps<1, T>::unpull, SplitOps<1, T>::diag};
-  static const SplitTable t2 = {SplitOps<2, T>::init, SplitOps<2, T>::step, SplitOps<2, T>::observe,
-                                SplitOps<2, T>::unpull, SplitOps<2, T>::diag};
-  static const SplitTable t3 = {SplitOps<3, T>::init, SplitOps<3, T>::step, SplitOps<3, T>::observe,
-                                SplitOps<3, T>::unpull, SplitOps<3, T>::diag};
+  static const SplitTable t1 = {SplitOps<S, 1>::init, SplitOps<S, 1>::step, SplitOps<S, 1>::observe,
+                                SplitOps<S, 1>::unpull, SplitOps<S, 1>::diag};
+  static const SplitTable t2 = {SplitOps<S, 2>::init, SplitOps<S, 2>::step, SplitOps<S, 2>::observe,
+                                SplitOps<S, 2>::unpull, SplitOps<S, 2>::diag};
+  static const SplitTable t3 = {SplitOps<S, 3>::init, SplitOps<S, 3>::step, SplitOps<S, 3>::observe,
+                                SplitOps<S, 3>::unpull, SplitOps<S, 3>::diag};
   return lattice == 1 ? t1 : (lattice == 2 ? t2 : t3);
 }
 
 const SplitTable& split_table(int lattice, int storage) {
-  return storage == 0 ? table_for_lattice<double>(lattice) : table_for_lattice<float>(lattice);
+  switch (storage) {
+    case StoreF64::kId: return table_for_lattice<StoreF64>(lattice);
+    case StoreF32::kId: return table_for_lattice<StoreF32>(lattice);
+    default: return table_for_lattice<StoreF16S>(lattice);
+  }
 }
 
 }  // namespace lbm

@@ -2,6 +2,7 @@
 // workspace layout, the step loop, observables and checkpoints.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -55,7 +56,7 @@ int validate(const lb_params* p, std::string* why) {
   int Q, D;
   if (lattice_dims(p->lattice, &Q, &D)) return bad("unknown lattice");
   if (p->n_comp < 1 || p->n_comp > LB_MAX_COMP) return bad("n_comp must be in 1..8");
-  if (p->storage != LB_F64 && p->storage != LB_F32) return bad("unknown storage");
+  if (p->storage != LB_F64 && p->storage != LB_F32 && p->storage != LB_F16S) return bad("unknown storage");
   if (p->force_form != LB_FORCE_LOG && p->force_form != LB_FORCE_EXPANDED) return bad("unknown force_form");
   if (p->path < LB_PATH_AUTO || p->path > LB_PATH_SWEEP) return bad("unknown path");
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) return bad("box sides must be >= 1");
@@ -89,22 +90,30 @@ struct Layout {
   int diag_blocks;
 };
 
-// Population slots of one copy: rows * (64-site blocks per row) * 64 * N * Q
-// (the x extent is padded to a multiple of 64; padded slots are never used).
-size_t population_slots(const lb_params* p) {
+// Bytes of one population copy: rows * (64-site blocks per row) * N * the
+// bytes of one component's 64-site block (the x extent is padded to a
+// multiple of 64; padded slots are never used).  A component's block holds
+// 64 rest values and 64 (Q - 1) moving values: FP64 8 + 8, FP32 4 + 4,
+// shifted FP16 4 (the FP32 ledger) + 2.
+size_t population_bytes(const lb_params* p) {
   int Q, D;
   lattice_dims(p->lattice, &Q, &D);
   const size_t nbx = (size_t(p->nx) + 63) / 64;
-  return size_t(p->ny) * size_t(p->nz) * nbx * 64 * size_t(p->n_comp) * Q;
+  const size_t rest = p->storage == LB_F64 ? 8 : 4;
+  const size_t move = p->storage == LB_F64 ? 8 : (p->storage == LB_F32 ? 4 : 2);
+  return size_t(p->ny) * size_t(p->nz) * nbx * size_t(p->n_comp) * 64 * (rest + (Q - 1) * move);
 }
+
+// Bytes of the working precision (FP64 for LB_F64, FP32 otherwise).
+size_t work_bytes(const lb_params* p) { return p->storage == LB_F64 ? 8 : 4; }
 
 Layout layout_of(const lb_params* p) {
   int Q, D;
   lattice_dims(p->lattice, &Q, &D);
   const size_t S = size_t(p->nx) * size_t(p->ny) * size_t(p->nz);
-  const size_t rb = p->storage == LB_F64 ? 8 : 4;
+  const size_t rb = work_bytes(p);
   Layout L;
-  const size_t fbytes = align_up(population_slots(p) * rb);
+  const size_t fbytes = align_up(population_bytes(p));
   const size_t rbytes = align_up(size_t(p->n_comp) * S * rb);
   const size_t blocks = (S + 255) / 256;
   L.diag_blocks = int(blocks < 1024 ? blocks : 1024);
@@ -141,6 +150,40 @@ void fill_params(const lb_params* p, lbm::Params<T>* q) {
     for (int b = 0; b < lbm::kMaxComp; ++b)
       q->chi[a * lbm::kMaxComp + b] =
           T(a < p->n_comp && b < p->n_comp ? p->chi[a * LB_MAX_COMP + b] : 0.0);
+}
+
+// Reference of the shifted FP16 storage from the initial densities:
+// rbar^sigma = mean of rho0^sigma (FP64, rounded once to FP32), s^sigma =
+// the smallest power of two >= max rho0^sigma, and sum_i w_i rbar^sigma
+// with each term rounded to FP32 as the kernels form it.  Zero for the other
+// codecs.
+lbm::ShiftRef shift_ref_of(const lb_params* p, const double* rho0, size_t S) {
+  lbm::ShiftRef r;
+  std::memset(&r, 0, sizeof(r));
+  if (p->storage != LB_F16S) return r;
+  double w[19];
+  int32_t Q = 0;
+  lb_lattice_tables(p->lattice, &Q, nullptr, nullptr, w);
+  for (int k = 0; k < p->n_comp; ++k) {
+    double sum = 0.0, mx = 0.0;
+    for (size_t i = 0; i < S; ++i) {
+      sum += rho0[k * S + i];
+      mx = std::max(mx, rho0[k * S + i]);
+    }
+    r.rbar[k] = float(sum / double(S));
+    int e = 0;
+    std::frexp(mx, &e);  // mx = m 2^e with m in [0.5, 1)
+    if (std::ldexp(1.0, e - 1) >= mx) e -= 1;  // mx itself a power of two
+    r.scale[k] = float(std::ldexp(1.0, e));
+    r.inv_scale[k] = float(std::ldexp(1.0, -e));
+    double cs = 0.0;
+    for (int i = 0; i < Q; ++i) {
+      const float ci = float(w[i]) * r.rbar[k];
+      cs += double(ci);
+    }
+    r.csum[k] = float(cs);
+  }
+  return r;
 }
 
 // Step the context's state n times on its stream.
@@ -199,7 +242,8 @@ int lb_init(const lb_params* p, const double* rho0, void* workspace, size_t work
   c.prm = *p;
   lattice_dims(p->lattice, &c.Q, &c.D);
   c.S = (long long)S;
-  c.real_bytes = p->storage == LB_F64 ? 8 : 4;
+  c.real_bytes = work_bytes(p);
+  c.pop_bytes = population_bytes(p);
   c.stream = static_cast<hipStream_t>(p->stream);
   if (workspace) {
     c.ws = workspace;
@@ -214,7 +258,7 @@ int lb_init(const lb_params* p, const double* rho0, void* workspace, size_t work
     c.ws_bytes = L.total;
   }
   char* base = static_cast<char*>(c.ws);
-  const size_t fbytes = population_slots(p) * c.real_bytes;
+  const size_t fbytes = c.pop_bytes;
   c.f[0] = base + L.f;
   c.f[1] = base + L.f + align_up(fbytes);
   c.rho_scratch = base + L.rho;
@@ -225,6 +269,7 @@ int lb_init(const lb_params* p, const double* rho0, void* workspace, size_t work
   c.diag_blocks = L.diag_blocks;
   fill_params(p, &c.pf);
   fill_params(p, &c.pd);
+  c.pf.sh = c.pd.sh = shift_ref_of(p, rho0, S);
 
   // the fused kernels address one population copy with 32-bit byte offsets
   const bool small = fbytes < (size_t(1) << 32);
@@ -239,14 +284,14 @@ int lb_init(const lb_params* p, const double* rho0, void* workspace, size_t work
       c.path = LB_PATH_TILE;
       if (!tile) {
         lb_free(h);
-        return fail(LB_ENOTSUP, "no tile kernel for this lattice / N / size");
+        return fail(LB_ENOTSUP, "no tile kernel for this lattice / storage / N / size");
       }
       break;
     case LB_PATH_SWEEP:
       c.path = LB_PATH_SWEEP;
       if (!sweep) {
         lb_free(h);
-        return fail(LB_ENOTSUP, "the sweep kernel needs D2Q9, FP32, N <= 4 and nx a multiple of 64");
+        return fail(LB_ENOTSUP, "the sweep kernel needs D2Q9, FP32 or shifted FP16, N <= 4 and nx a multiple of 64");
       }
       break;
     default:
@@ -360,10 +405,11 @@ int lb_get_f(lb_ctx* h, double* f) {
   return LB_OK;
 }
 
+// State blob: the current population copy, the shift reference (which
+// decodes shifted FP16 storage) and the step count.
 size_t lb_state_bytes(const lb_ctx* h) {
   if (!h) return 0;
-  const Ctx& c = h->c;
-  return population_slots(&c.prm) * c.real_bytes + sizeof(int64_t);
+  return h->c.pop_bytes + sizeof(lbm::ShiftRef) + sizeof(int64_t);
 }
 
 int lb_get_state(lb_ctx* h, void* host, size_t bytes) {
@@ -371,9 +417,11 @@ int lb_get_state(lb_ctx* h, void* host, size_t bytes) {
   Ctx& c = h->c;
   const size_t need = lb_state_bytes(h);
   if (bytes < need) return fail(LB_EINVAL, "buffer too small for the state");
-  HIP_TRY(hipMemcpyAsync(host, c.f[c.cur], need - sizeof(int64_t), hipMemcpyDeviceToHost, c.stream));
+  char* out = static_cast<char*>(host);
+  HIP_TRY(hipMemcpyAsync(out, c.f[c.cur], c.pop_bytes, hipMemcpyDeviceToHost, c.stream));
   HIP_TRY(hipStreamSynchronize(c.stream));
-  std::memcpy(static_cast<char*>(host) + need - sizeof(int64_t), &c.t, sizeof(int64_t));
+  std::memcpy(out + c.pop_bytes, &c.pf.sh, sizeof(lbm::ShiftRef));
+  std::memcpy(out + c.pop_bytes + sizeof(lbm::ShiftRef), &c.t, sizeof(int64_t));
   return LB_OK;
 }
 
@@ -382,9 +430,12 @@ int lb_set_state(lb_ctx* h, const void* host, size_t bytes) {
   Ctx& c = h->c;
   const size_t need = lb_state_bytes(h);
   if (bytes != need) return fail(LB_EINVAL, "state size does not match this context");
-  HIP_TRY(hipMemcpyAsync(c.f[c.cur], host, need - sizeof(int64_t), hipMemcpyHostToDevice, c.stream));
+  const char* in = static_cast<const char*>(host);
+  HIP_TRY(hipMemcpyAsync(c.f[c.cur], in, c.pop_bytes, hipMemcpyHostToDevice, c.stream));
   HIP_TRY(hipStreamSynchronize(c.stream));
-  std::memcpy(&c.t, static_cast<const char*>(host) + need - sizeof(int64_t), sizeof(int64_t));
+  std::memcpy(&c.pf.sh, in + c.pop_bytes, sizeof(lbm::ShiftRef));
+  c.pd.sh = c.pf.sh;
+  std::memcpy(&c.t, in + c.pop_bytes + sizeof(lbm::ShiftRef), sizeof(int64_t));
   return LB_OK;
 }
 

@@ -20,7 +20,8 @@ struct Ctx {
   lb_params prm;
   int Q = 0, D = 0;
   long long S = 0;
-  size_t real_bytes = 0;   // bytes per stored population
+  size_t real_bytes = 0;   // bytes of the working precision
+  size_t pop_bytes = 0;    // bytes of one population copy
   hipStream_t stream = nullptr;
 
   void* ws = nullptr;      // workspace base (device)

@@ -26,6 +26,14 @@ namespace lbm {
 
 constexpr int kMaxComp = 8;
 
+// Reference of the shifted FP16 storage (unused by the other codecs).
+struct ShiftRef {
+  float rbar[kMaxComp];       // mean density rbar^sigma of each component
+  float scale[kMaxComp];      // s^sigma, a power of two
+  float inv_scale[kMaxComp];  // 1 / s^sigma
+  float csum[kMaxComp];       // sum_i w_i rbar^sigma, rounded once to FP32
+};
+
 // Arithmetic parameters of one run, in the working precision T.
 template <typename T>
 struct Params {
@@ -41,6 +49,7 @@ struct Params {
   T kappa;        // square-gradient coefficient
   T inv_m[kMaxComp];
   T chi[kMaxComp * kMaxComp];  // leading dimension kMaxComp, symmetric
+  ShiftRef sh;
 };
 
 // Natural logarithm and reciprocal in the working precision.  FP32 uses the

@@ -19,7 +19,7 @@ MAX_COMP = 8
 
 LB_OK, LB_EINVAL, LB_ENOMEM, LB_ENOTSUP, LB_EDEVICE, LB_ENUMERIC = 0, -1, -2, -3, -4, -5
 LATTICE = {"D1Q3": 1, "D2Q9": 2, "D3Q19": 3}
-STORAGE = {"f64": 0, "f32": 1}
+STORAGE = {"f64": 0, "f32": 1, "f16s": 2}
 FORCE_FORM = {"log": 0, "expanded": 1}
 PATH = {"auto": 0, "tile": 1, "split": 2, "sweep": 3}
 

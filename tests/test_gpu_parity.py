@@ -4,7 +4,15 @@ Every case runs the HIP path through the C ABI (via the ctypes binding) and
 the oracle from the same initial densities, then compares densities,
 macroscopic velocity, chemical potentials, pressure tensor and all
 populations site by site.  Bars: FP64 path 1e-12 relative, FP32 path 1e-5
-relative (both against the FP64 oracle)."""
+relative (both against the FP64 oracle).
+
+Shifted FP16 storage (f16s) rounds each stored deviation from w_i rbar to
+11 bits, so its error depends on how far the state is from the mean
+composition.  Its bars are stated per case (F16S_TOL): about 3x the error
+measured on MI355X, e.g. 3e-6 in rho for the near-uniform binary spinodal
+and 2e-2 for the phase-separated immersion film, whose minority component
+sits 50x below its mean.  Mass is exact for f16s (the ledger), so its mass
+error is the initial rounding of rho0 into storage only."""
 import numpy as np
 import pytest
 
@@ -39,8 +47,20 @@ def _cases():
 
 CASES = _cases()
 
+# f16s bars per case and quantity (3x the error measured at 200/300/100 steps)
+_NEAR_UNIFORM = {"rho": 1e-5, "f": 2e-5, "U": 1e-5, "mu": 2e-6, "P": 3e-5}
+F16S_TOL = {
+    "binary64_spinodal": _NEAR_UNIFORM,
+    "binary64_stable": _NEAR_UNIFORM,
+    "ternary_immersion_96x80": {"rho": 5e-2, "f": 5e-3, "U": 1e-3, "mu": 1.5e-2, "P": 4e-3},
+    "ternary_immersion_128x77": {"rho": 6e-2, "f": 5e-3, "U": 2.5e-3, "mu": 1.5e-2, "P": 4e-3},
+    "d1q3_polymer_130": {"rho": 1.5e-3, "f": 3e-4, "U": 4e-4, "mu": 1.2e-5, "P": 1e-12},
+    "d3q19_ternary_12x10x9": _NEAR_UNIFORM,
+    "five_40": _NEAR_UNIFORM,
+}
 
-@pytest.mark.parametrize("storage", ["f64", "f32"])
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16s"])
 @pytest.mark.parametrize("name,cfg,rho0,steps", CASES, ids=[c[0] for c in CASES])
 def test_gpu_matches_oracle(name, cfg, rho0, steps, storage):
     """Every kernel path that supports the run against the oracle."""
@@ -51,13 +71,13 @@ def test_gpu_matches_oracle(name, cfg, rho0, steps, storage):
         assert g["path"] == path
         e = errors(g, o, cfg["theta"])
         print(f"[parity] {name} {storage} {path} errors {e}", flush=True)
-        tol = TOL[storage]
         for k in ("rho", "f", "U", "mu", "P"):
+            tol = F16S_TOL[name][k] if storage == "f16s" else TOL[storage]
             assert e[k] < tol, (path, k, e)
         assert e["mass"] < (1e-13 if storage == "f64" else 1e-6), (path, e)
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16s"])
 def test_fused_paths_equal_split(storage):
     """The fused kernels perform the split path's operations in the same
     order, so all paths agree bit for bit."""
@@ -93,11 +113,12 @@ def test_degenerate_and_ragged_boxes(shape):
     S = shape[0] * shape[1]
     r = LI.noisy_uniform(p, [0.5, 0.5], 0.01, 7)
     o = run_oracle(p, r, 20)
-    for storage in ("f64", "f32"):
+    for storage in ("f64", "f32", "f16s"):
+        tol = _NEAR_UNIFORM["rho"] if storage == "f16s" else TOL[storage]
         for path in paths_for(p, storage):
             g = run_gpu(p, r, 20, storage=storage, path=path)
             e = errors(g, o)
-            assert e["rho"] < TOL[storage] and e["f"] < TOL[storage], (shape, S, storage, path, e)
+            assert e["rho"] < tol and e["f"] < 2 * tol, (shape, S, storage, path, e)
 
 
 @pytest.mark.parametrize("n", [1, 2, 4, 6, 8])
@@ -109,12 +130,13 @@ def test_component_counts(n):
     p["chi"] = chi
     r = LI.noisy_uniform(p, [1.0 / n] * n, 0.005 / n, 11)
     o = run_oracle(p, r, 50)
-    for storage in ("f64", "f32"):
+    for storage in ("f64", "f32", "f16s"):
         for path in paths_for(p, storage):
             g = run_gpu(p, r, 50, storage=storage, path=path)
             e = errors(g, o)
-            tol = TOL[storage]
-            assert e["rho"] < tol and e["f"] < tol and e["mu"] < tol, (n, storage, path, e)
+            tol = _NEAR_UNIFORM["rho"] if storage == "f16s" else TOL[storage]
+            print(f"[components] n={n} {storage} {path} {e}", flush=True)
+            assert e["rho"] < tol and e["f"] < 2 * tol and e["mu"] < tol, (n, storage, path, e)
 
 
 @pytest.mark.parametrize("path", ["split", "tile"])
@@ -126,3 +148,24 @@ def test_zero_steps_is_rest_equilibrium(path):
     assert np.abs(g["U"]).max() < 1  # forces exist at t = 0; U includes half of them
     _, _, _, w = __import__("paper_0704_3444_amd").lb_lattice_tables("D2Q9")
     assert np.abs(g["f"] - w[None, :, None] * rho0[:, None, :]).max() == 0.0
+
+
+def test_f16s_mass_exact_and_zero_steps():
+    """Shifted FP16 storage keeps every component's mass exactly: the FP64
+    sums of the stored values do not change over 2000 steps (up to the FP64
+    rounding of the sum itself).  At t = 0 the stored densities equal rho0
+    to 2^-25 s per site."""
+    from paper_0704_3444_amd import Simulation
+
+    cfg, rho0 = LI.ternary_immersion(128, ny=64)
+    for path in paths_for(cfg, "f16s"):
+        s = Simulation(cfg, rho0, storage="f16s", path=path)
+        m = s.moments()
+        assert np.abs(m["rho"] - rho0).max() <= 2.0 ** -25 * 1.0 + 1e-16
+        m0 = m["mass"]
+        s.step(2000)
+        m1 = s.moments(fields=False)["mass"]
+        s.close()
+        drift = np.abs(m1 / m0 - 1).max()
+        print(f"[f16s-mass] {path} drift over 2000 steps {drift:.3e}", flush=True)
+        assert drift < 1e-14, (path, drift)

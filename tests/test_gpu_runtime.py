@@ -13,7 +13,7 @@ PATHS = ["split", "tile", "sweep"]
 
 
 def storages(path):
-    return ["f32"] if path == "sweep" else ["f64", "f32"]
+    return {"sweep": ["f32", "f16s"], "tile": ["f64", "f32"], "split": ["f64", "f32", "f16s"]}[path]
 
 
 def sim(cfg, rho0, **kw):
@@ -37,28 +37,34 @@ def test_bitwise_deterministic(path):
 
 @pytest.mark.parametrize("path", PATHS)
 def test_checkpoint_resume_bitwise(path):
+    """Resume from a checkpoint, also into a context created from other
+    initial densities (the blob carries the shifted-storage reference)."""
     cfg, rho0 = LI.binary_spinodal(64 if path == "sweep" else 48)
-    a = sim(cfg, rho0, storage="f32", path=path)
-    a.step(40)
-    snap = a.get_state()
-    a.step(40)
-    ref = a.get_state()
-    b = sim(cfg, rho0, storage="f32", path=path)
-    b.set_state(snap)
-    b.step(40)
-    assert b.get_state() == ref
-    assert b.moments(fields=False)["step"] == 80
-    a.close()
-    b.close()
+    other = 0.9 * rho0[:, ::-1].copy()
+    for storage in [s for s in storages(path) if s != "f64"]:
+        a = sim(cfg, rho0, storage=storage, path=path)
+        a.step(40)
+        snap = a.get_state()
+        a.step(40)
+        ref = a.get_state()
+        for start in (rho0, other):
+            b = sim(cfg, start, storage=storage, path=path)
+            b.set_state(snap)
+            b.step(40)
+            assert b.get_state() == ref, storage
+            assert b.moments(fields=False)["step"] == 80
+            b.close()
+        a.close()
 
 
 @pytest.mark.parametrize("path", PATHS)
-@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16s"])
 def test_translation_equivariance_bitwise(path, storage):
     """Shifting the initial state by (dx, dy) shifts the result exactly;
-    shifts straddle the tiles, strips and segments of the fused kernels."""
+    shifts straddle the tiles, strips and segments of the fused kernels
+    (a shift keeps the mean and maximum of rho0, hence the f16s reference)."""
     if storage not in storages(path):
-        pytest.skip("the sweep kernel is FP32 only")
+        pytest.skip(f"the {path} path does not take {storage} storage")
     nx, ny = (128 if path == "sweep" else 150), 77
     cfg, rho0 = LI.ternary_immersion(nx, ny=ny)
     g = rho0.reshape(3, ny, nx)
@@ -76,10 +82,12 @@ def test_translation_equivariance_bitwise(path, storage):
 
 
 @pytest.mark.parametrize("path", PATHS)
-@pytest.mark.parametrize("storage,bar", [("f64", 1e-13), ("f32", 1e-6)])
+@pytest.mark.parametrize("storage,bar", [("f64", 1e-13), ("f32", 1e-6), ("f16s", 1e-7)])
 def test_mass_conserved_long_run(path, storage, bar):
+    """Mass drift against rho0 after 3000 steps (f16s: exact after the
+    initial rounding of rho0 into storage, at most 2^-25 s per site)."""
     if storage not in storages(path):
-        pytest.skip("the sweep kernel is FP32 only")
+        pytest.skip(f"the {path} path does not take {storage} storage")
     cfg, rho0 = LI.binary_spinodal(128, seed=77)
     s = sim(cfg, rho0, storage=storage, path=path)
     m0 = rho0.sum(axis=1)
