@@ -12,6 +12,13 @@ kernels run on.  `roofline` prices the fused step kernel against the HBM
 peak: its algorithmic traffic per launch is every population read once and
 written once, 2 * N * S * (rest + (Q - 1) * moving slot bytes).  `cpu_baseline` times the FP64 CPU
 oracle on a bounded sample of the same workload on the host cores.
+
+Two more objects on the same line (skipped with --no-f16s / --no-serving):
+`f16s` times the same workload with shifted FP16 storage; `serving` runs a
+Poisson mix of 256 phase-separation requests (N 2 or 3, square boxes of
+side 64..512, 5000 steps each) through the continuous-batching loop and,
+for comparison, one request at a time, and reports p50/p99 latency and
+throughput of both.
 """
 import argparse
 import hashlib
@@ -103,6 +110,62 @@ def calibrate_copy(gib=1.0, reps=5):
     print(json.dumps({"calibrate_copy_bytes": n, "reps": reps}), flush=True)
 
 
+def alg_bytes_per_step(N, S, Q, storage):
+    rest_b, move_b = STORE_BYTES[storage]
+    return 2 * N * S * (rest_b + (Q - 1) * move_b)
+
+
+def time_steps(cfg, rho0, storage, kpath, steps, warmup, stream):
+    """HIP-event time of `steps` lb_step calls after `warmup` untimed ones."""
+    import numpy as np
+    import torch
+
+    from paper_0704_3444_amd import Simulation
+
+    S = int(np.prod(cfg["shape"]))
+    N = int(cfg["n_comp"])
+    sim = Simulation(cfg, rho0, storage=storage, path=kpath, stream=stream)
+    print(f"bench: {cfg['shape']} N={N} {storage} path={sim.path}; warmup {warmup}", file=sys.stderr, flush=True)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record(stream)
+    sim.step(steps)
+    end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = start.elapsed_time(end)
+    # the state must still be physical after the timed steps
+    health = sim.moments(fields=False)
+    out = {"ms_per_step": ms / steps, "value": S * N * steps / (ms / 1e3) / 1e6, "wall": wall, "path": sim.path,
+           "health": health, "mass_drift": float(np.max(np.abs(health["mass"] / rho0.sum(axis=1) - 1)))}
+    sim.close()
+    return out
+
+
+def run_serving(n_req):
+    """The Poisson request mix through the continuous-batching loop (after
+    autotuning the batched kernel on a throwaway batch of the first 48
+    requests) and one request at a time."""
+    import lbinputs as LI
+    from paper_0704_3444_amd import lb, serve
+
+    print(f"bench: serving {n_req} requests", file=sys.stderr, flush=True)
+    reqs = LI.serving_mix(n_req)
+    best, ms = serve.tune_batch(reqs[:48], steps=10)
+    info = lb.lb_batch_config_info("f32", 3, best)
+    batched, bsum = serve.serve_batched(reqs, config=best, chunk=100, graph_steps=50)
+    print(f"bench: serving batched {bsum}", file=sys.stderr, flush=True)
+    serial, ssum = serve.serve_serial(reqs)
+    print(f"bench: serving one at a time {ssum}", file=sys.stderr, flush=True)
+    bad = sum(x["status"] != 0 for x in batched) + sum(x["status"] != 0 for x in serial)
+    return {"workload": f"poisson_mix_{n_req}", "rate_hz": 40.0, "steps_per_request": reqs[0]["nsteps"],
+            "storage": "f32", "tuned_config": dict(info, index=best), "batched": bsum, "one_at_a_time": ssum,
+            "speedup_throughput": round(bsum["mlups_x_comp"] / ssum["mlups_x_comp"], 3),
+            "speedup_p99": round(ssum["p99_ms"] / bsum["p99_ms"], 3), "failed_requests": bad}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,6 +176,9 @@ def main():
     ap.add_argument("--path", default="auto", choices=["auto", "sweep", "tile", "split"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--no-f16s", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=256)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -137,36 +203,15 @@ def main():
     S = int(np.prod(shape))
     N = int(cfg["n_comp"])
     Q = {"D1Q3": 3, "D2Q9": 9, "D3Q19": 19}[cfg["lattice"]]
-    rest_b, move_b = STORE_BYTES[args.storage]
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
-    sim = Simulation(cfg, rho0, storage=args.storage, path=args.path, stream=stream)
-    print(f"bench: {args.workload} {shape} N={N} {args.storage} path={sim.path}; warmup {args.warmup}",
-          file=sys.stderr, flush=True)
-    sim.step(args.warmup)
-    torch.cuda.synchronize()
-
-    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    start.record(stream)
-    sim.step(args.steps)
-    end.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = start.elapsed_time(end)
-    ms_per_step = ms / args.steps
-    value = S * N * args.steps / (ms / 1e3) / 1e6
-
-    # the state must still be physical after the timed steps
-    health = sim.moments(fields=False)
-    mass_drift = float(np.max(np.abs(health["mass"] / rho0.sum(axis=1) - 1)))
-    path = sim.path
-    sim.close()
+    r = time_steps(cfg, rho0, args.storage, args.path, args.steps, args.warmup, stream)
+    ms_per_step, value, wall, path = r["ms_per_step"], r["value"], r["wall"], r["path"]
+    health, mass_drift = r["health"], r["mass_drift"]
 
     kernels_per_step = 3 if path == "split" else 1
-    alg_bytes = 2 * N * S * (rest_b + (Q - 1) * move_b)
+    alg_bytes = alg_bytes_per_step(N, S, Q, args.storage)
     achieved = alg_bytes / (ms_per_step / 1e3) / 1e9
     traffic = measured_traffic(args.workload, args.storage, path)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -174,6 +219,19 @@ def main():
                 "kernel": {"sweep": "k_sweep_d2q9", "tile": "k_fused_d2q9"}.get(path, "k_density+k_potential+k_collide"),
                 "algorithmic_bytes_per_launch": alg_bytes, "launches_per_step": kernels_per_step,
                 "avg_launch_ms": round(ms_per_step / kernels_per_step, 5)}
+
+    f16s = None
+    if not args.no_f16s and args.storage == "f32" and cfg["lattice"] == "D2Q9":
+        h = time_steps(cfg, rho0, "f16s", args.path, args.steps, args.warmup, stream)
+        hb = alg_bytes_per_step(N, S, Q, "f16s")
+        f16s = {"value": round(h["value"], 1), "ms_per_step": round(h["ms_per_step"], 5), "path": h["path"],
+                "speedup_vs_f32": round(h["value"] / value, 3),
+                "hbm_frac": round(hb / (h["ms_per_step"] / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                "algorithmic_bytes_per_launch": hb, "mass_drift": h["mass_drift"], "status": h["health"]["status"]}
+
+    serving = None
+    if not args.no_serving:
+        serving = run_serving(args.serving_requests)
 
     cpu = None
     if not args.no_cpu:
@@ -189,7 +247,7 @@ def main():
                    "n_comp": N, "storage": args.storage, "path": path, "force_form": cfg["force_form"]},
         "hbm_frac": round(achieved / HBM_PEAK_GBS, 4),
         "wall_s": round(wall, 4), "mass_drift": mass_drift, "status": health["status"],
-        "roofline": roofline, "cpu_baseline": cpu,
+        "roofline": roofline, "cpu_baseline": cpu, "f16s": f16s, "serving": serving,
     }
     print(json.dumps(line), flush=True)
 

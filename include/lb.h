@@ -182,6 +182,103 @@ int lb_path_in_use(const lb_ctx* c);
  * no-op.  Waits for the context's stream. */
 void lb_free(lb_ctx* c);
 
+/* ------------------------------------------------------------------------
+ * Batches: many independent runs stepped together.
+ *
+ * A batch holds up to max_slots D2Q9 runs ("slots") of one storage
+ * precision, each with its own box, N <= max_comp and parameters of
+ * Eq. (ssLB) / Eq. (lgf), and steps all of them with one persistent kernel
+ * launch per time step: the launch walks the tiles of every live slot (the
+ * tile step is the one of LB_PATH_TILE, so a slot's result is bit for bit
+ * the one of the same run alone).  Runs of graph_steps steps are replayed
+ * from a captured hipGraph.  Each slot stops at its own target step; slots
+ * join (lb_batch_add) and leave (lb_batch_remove) between calls without
+ * re-capturing the graph, since the kernel reads the slot table and the
+ * per-slot step counters from device memory.
+ *
+ * Memory: one device arena of arena_bytes, allocated at creation, holds the
+ * slots; lb_batch_add admits a run only if its footprint
+ * (lb_batch_footprint) fits in a free range (first fit), and returns
+ * LB_ENOMEM otherwise, so a caller can queue the run and retry after a
+ * removal.  Admission (lb_init's work) and observables run on a second,
+ * library-owned stream, overlapping the stepping of the other slots.
+ * Calls on one batch are not thread-safe.
+ * ------------------------------------------------------------------------ */
+typedef struct lb_batch lb_batch;
+
+typedef struct lb_batch_params {
+  int32_t storage;      /* LB_F32 or LB_F64, for every slot                      */
+  int32_t max_comp;     /* bound on N of the slots, 1 .. 4                        */
+  int32_t max_slots;    /* slot capacity, 1 .. 4096                               */
+  int32_t config;       /* kernel configuration (tile shape and grid), index
+                           below lb_batch_config_count; -1 for the default       */
+  int32_t graph_steps;  /* steps per captured graph, >= 1 (0: 16)                 */
+  int32_t reserved;
+  size_t arena_bytes;   /* device memory for the slots                           */
+  void* stream;         /* hipStream_t of the stepping (NULL: null stream)       */
+} lb_batch_params;
+
+/* Create a batch (allocates the arena, the slot table and a second stream).
+ * Errors: LB_EINVAL, LB_ENOTSUP (storage / max_comp), LB_ENOMEM, LB_EDEVICE. */
+int lb_batch_create(const lb_batch_params* bp, lb_batch** out);
+
+/* Arena bytes that a run with params p takes in batch b (0 if p is invalid
+ * or not admissible to b). */
+size_t lb_batch_footprint(const lb_batch* b, const lb_params* p);
+
+/* Admit a run: validate p (D2Q9, the batch's storage, N <= max_comp; path,
+ * check_every and stream are ignored), carve its workspace from the arena,
+ * set rest equilibrium from rho0 (host FP64 [N][S], as lb_init) and make it
+ * a live slot that lb_batch_step advances until it has taken nsteps steps.
+ * Writes the slot id to *slot.  Synchronises the library's second stream
+ * only.  Errors: LB_EINVAL, LB_ENOTSUP, LB_ENOMEM (no free slot or no arena
+ * range large enough: retry after lb_batch_remove), LB_EDEVICE. */
+int lb_batch_add(lb_batch* b, const lb_params* p, const double* rho0, int64_t nsteps, int32_t* slot);
+
+/* Advance every live slot by up to nsteps steps (a slot stops at its
+ * target), asynchronously on the batch stream, and queue a snapshot of the
+ * step counters. */
+int lb_batch_step(lb_batch* b, int64_t nsteps);
+
+/* Step counters of all max_slots slots (-1 for a free slot) into
+ * steps_done, from the snapshot queued `lag` lb_batch_step calls before the
+ * latest one (lag 0: the latest), waiting for it to complete; lag must be
+ * below 4.  A slot whose counter equals its target is finished: its state
+ * no longer changes. */
+int lb_batch_poll(lb_batch* b, int32_t lag, int64_t* steps_done);
+
+/* Observables of a finished slot (as lb_moments; finished in the last
+ * snapshot lb_batch_poll returned).  Runs on the library's second stream and
+ * waits for it; the batch stream keeps going.  Errors: LB_EINVAL (slot not
+ * live or not finished), LB_ENUMERIC, LB_EDEVICE. */
+int lb_batch_moments(lb_batch* b, int32_t slot, double* rho, double* U, double* mu, double* P, double* mass,
+                     double* mom, int64_t* step);
+
+/* Release a slot and its arena range (a slot still running is stopped). */
+int lb_batch_remove(lb_batch* b, int32_t slot);
+
+/* Kernel configurations of the batched kernel for (storage, max_comp):
+ * their number, and the tile shape, threads per workgroup and workgroups
+ * per compute unit of the persistent grid of configuration `config`. */
+int lb_batch_config_count(int32_t storage, int32_t max_comp);
+int lb_batch_config_info(int32_t storage, int32_t max_comp, int32_t config, int32_t* tile_x, int32_t* tile_y,
+                         int32_t* threads, int32_t* groups_per_cu);
+
+/* Switch the batch to configuration `config` (re-captures the graph). */
+int lb_batch_set_config(lb_batch* b, int32_t config);
+
+/* Autotuner: time every configuration on the batch's live slots for `steps`
+ * steps each (after one warm-up step), with HIP events on the batch stream,
+ * and switch to the fastest.  The slots advance by (steps + 1) times the
+ * number of configurations (every configuration gives the same results bit
+ * for bit, so this is ordinary progress).  ms_per_step receives the timings
+ * (lb_batch_config_count entries, may be NULL); *best the chosen index.
+ * Waits for the batch stream. */
+int lb_batch_tune(lb_batch* b, int32_t steps, double* ms_per_step, int32_t* best);
+
+/* Free the batch, its slots and its arena (waits for both streams). */
+void lb_batch_free(lb_batch* b);
+
 /* Static description of a status code. */
 const char* lb_strerror(int code);
 

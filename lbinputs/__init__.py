@@ -171,6 +171,48 @@ def sine_profile(p: dict, phi0, amp=0.1, rho_total=1.0, axis=0) -> np.ndarray:
     return rho * rho_total
 
 
+def serving_mix(n_req=256, *, seed=1005, rate_hz=40.0, side=(64, 512), steps=5000,
+                binary_chi=(2.2, 2.7), ternary_chi=(2.6, 2.9), solvent_chi=(0.3, 1.0), kappa=(0.005, 0.02),
+                tau=(0.8, 1.0)):
+    """Phase-separation requests arriving as a Poisson process: request k
+    arrives at the sum of k + 1 exponential gaps of mean 1 / rate_hz
+    seconds; N is 2 or 3 with equal odds; the box is square with side
+    uniform in [side[0], side[1]]; tau, kappa and the interactions are
+    uniform in the given ranges.
+      binary:  rho0 = 1/2 + 0.01 (2U - 1) each, chi^{AB} 1.1 to 1.35 times
+               the critical value 2;
+      ternary: two demixing components and a compatible third,
+               rho0 = (0.4, 0.4, 0.2) + 0.01 (2U - 1), chi^{AB} 1.04 to 1.16
+               times 2.5 (where the A-B exchange mode of Eq. (lgf) loses
+               stability at this composition), chi^{AC}, chi^{BC} in
+               solvent_chi.
+    Every pair stays below 1.5 times the binary critical value, beyond which
+    the scheme's segregated interfaces are unstable.  Returns a list of
+    dicts with keys arrival (s), cfg, rho0, nsteps, id."""
+    u = uniform(seed, 99, 8 * n_req).reshape(n_req, 8)
+    t = 0.0
+    out = []
+    for k in range(n_req):
+        t += -np.log1p(-u[k, 0]) / rate_hz
+        n = 2 if u[k, 1] < 0.5 else 3
+        L = min(int(side[0] + np.floor(u[k, 2] * (side[1] - side[0] + 1))), side[1])
+        ta = tau[0] + (tau[1] - tau[0]) * u[k, 3]
+        ka = kappa[0] + (kappa[1] - kappa[0]) * u[k, 4]
+        if n == 2:
+            chi = _chi(2, {(0, 1): binary_chi[0] + (binary_chi[1] - binary_chi[0]) * u[k, 5]})
+            base = [0.5, 0.5]
+        else:
+            v = uniform(seed + 1, k, 3)
+            lo, hi = solvent_chi
+            chi = _chi(3, {(0, 1): ternary_chi[0] + (ternary_chi[1] - ternary_chi[0]) * v[0],
+                           (0, 2): lo + (hi - lo) * v[1], (1, 2): lo + (hi - lo) * v[2]})
+            base = [0.4, 0.4, 0.2]
+        p = params("D2Q9", n, (L, L), tau=ta, kappa=ka, chi=chi)
+        rho0 = noisy_uniform(p, base, 0.01, seed + 10 + k)
+        out.append({"arrival": t, "cfg": p, "rho0": rho0, "nsteps": int(steps), "id": k})
+    return out
+
+
 WORKLOADS = {
     "binary_d2q9_64": lambda: binary_spinodal(64),
     "binary_d2q9_64_stable": lambda: binary_spinodal(64, chi=1.6),

@@ -74,9 +74,18 @@ __device__ __forceinline__ void pulled_density(const T* __restrict__ fin, const 
   }
 }
 
+// LDS of one tile step.
+template <typename T, int NC, int TX, int TY>
+struct TileLds {
+  T rho[NC][TY + 4][TX + 4];  // rho region: tile + 2
+  T h[NC][TY + 2][TX + 2];    // h region:   tile + 1
+};
+
+// The whole step for the tile with corner (x0, y0).  Every thread of the
+// workgroup calls it (it contains workgroup barriers).
 template <typename T, int NC, int TX, int TY, int NT, bool NTSTORE>
-__global__ void __launch_bounds__(NT) k_fused_d2q9(const T* __restrict__ fin, T* __restrict__ fout, Params<T> p,
-                                                   int nbx, int ntiles, int tiles_per_xcd, int xcd_remap) {
+__device__ __forceinline__ void tile_step(const T* __restrict__ fin, T* __restrict__ fout, const Params<T>& p,
+                                          int x0, int y0, TileLds<T, NC, TX, TY>& lds) {
   using L = Lattice<2>;
   constexpr int Q = L::Q;
   constexpr int HX = TX + 4, HY = TY + 4;  // rho region: tile + 2
@@ -84,16 +93,8 @@ __global__ void __launch_bounds__(NT) k_fused_d2q9(const T* __restrict__ fin, T*
   constexpr int RS = NT / TX;              // row stride between a thread's sites
   constexpr int SPT = TY / RS;             // sites per thread
   static_assert(NT % TX == 0 && TY % RS == 0, "tile shape");
-
-  __shared__ T s_rho[NC][HY][HX];
-  __shared__ T s_h[NC][GY][GX];
-
-  // XCD-aware tile order: workgroup b runs on XCD b % 8; give XCD c the
-  // contiguous tile range [c * tiles_per_xcd, (c + 1) * tiles_per_xcd).
-  const int b = blockIdx.x;
-  const int t = xcd_remap ? (b % kXcds) * tiles_per_xcd + b / kXcds : b;
-  if (t >= ntiles) return;
-  const int x0 = (t % nbx) * TX, y0 = (t / nbx) * TY;
+  auto& s_rho = lds.rho;
+  auto& s_h = lds.h;
   const int nx = p.nx, ny = p.ny, n = p.n;
   const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
 
@@ -234,6 +235,123 @@ __global__ void __launch_bounds__(NT) k_fused_d2q9(const T* __restrict__ fin, T*
       }
     }
   }
+}
+
+template <typename T, int NC, int TX, int TY, int NT, bool NTSTORE>
+__global__ void __launch_bounds__(NT) k_fused_d2q9(const T* __restrict__ fin, T* __restrict__ fout, Params<T> p,
+                                                   int nbx, int ntiles, int tiles_per_xcd, int xcd_remap) {
+  __shared__ TileLds<T, NC, TX, TY> lds;
+  // XCD-aware tile order: workgroup b runs on XCD b % 8; give XCD c the
+  // contiguous tile range [c * tiles_per_xcd, (c + 1) * tiles_per_xcd).
+  const int b = blockIdx.x;
+  const int t = xcd_remap ? (b % kXcds) * tiles_per_xcd + b / kXcds : b;
+  if (t >= ntiles) return;
+  tile_step<T, NC, TX, TY, NT, NTSTORE>(fin, fout, p, (t % nbx) * TX, (t / nbx) * TY, lds);
+}
+
+// ---------------------------------------------------------- batched ----
+// Persistent step of many independent lattices in one launch.  The host
+// owns the slot table (parameters, population copies, tile ranges, target
+// step) and the map from work item to table entry; the device owns the step
+// counters.  A slot whose counter has reached its target is skipped, so one
+// captured sequence of launches stays valid while slots join and leave; the
+// population copy read at step t is f[t & 1].  Work items (slot, tile) are
+// numbered consecutively over the live slots; XCD c (dispatch is round
+// robin) takes the contiguous range [c * per_xcd, (c + 1) * per_xcd), its
+// workgroups striding through it, so that the halo rows of neighbouring
+// tiles stay in that XCD's L2.
+template <typename T, int NC, int TX, int TY, int NT>
+__global__ void __launch_bounds__(NT) k_batch_d2q9(const BatchSlot<T>* __restrict__ slots,
+                                                   const long long* __restrict__ t_now,
+                                                   const BatchHeader* __restrict__ hdr,
+                                                   const int* __restrict__ item_slot) {
+  __shared__ TileLds<T, NC, TX, TY> lds;
+  const int items = hdr->items;
+  const int groups = gridDim.x / kXcds;  // workgroups per XCD (the grid is a multiple of 8)
+  const int per_xcd = (items + kXcds - 1) / kXcds;
+  const int xcd = blockIdx.x % kXcds, g = blockIdx.x / kXcds;
+  for (int j = g; j < per_xcd; j += groups) {
+    const int w = xcd * per_xcd + j;
+    if (w >= items) break;
+    const BatchSlot<T>& sl = slots[item_slot[w]];
+    const long long t = t_now[sl.id];
+    if (t >= sl.t_end) continue;  // uniform: the whole workgroup skips
+    const int tile = w - sl.first_item;
+    const int x0 = (tile % sl.tiles_x) * TX, y0 = (tile / sl.tiles_x) * TY;
+    tile_step<T, NC, TX, TY, NT, true>(static_cast<const T*>(sl.f[t & 1]), static_cast<T*>(sl.f[(t + 1) & 1]),
+                                       sl.p, x0, y0, lds);
+    __syncthreads();  // the next tile reuses the LDS
+  }
+}
+
+// Counters of the slots the step launch before stepped: t += 1 below target.
+template <typename T>
+__global__ void k_batch_advance(const BatchSlot<T>* __restrict__ slots, long long* __restrict__ t_now,
+                                const BatchHeader* __restrict__ hdr) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= hdr->nslots) return;
+  const int id = slots[s].id;
+  if (t_now[id] < slots[s].t_end) t_now[id] += 1;
+}
+
+template <typename T, int NC, int TX, int TY, int NT>
+static void batch_step_launch(const void* slots, const long long* t_now, const BatchHeader* hdr,
+                              const int* item_slot, int grid, hipStream_t s) {
+  k_batch_d2q9<T, NC, TX, TY, NT><<<grid, NT, 0, s>>>(static_cast<const BatchSlot<T>*>(slots), t_now, hdr,
+                                                       item_slot);
+}
+
+template <typename T>
+static void batch_advance_launch(const void* slots, long long* t_now, const BatchHeader* hdr, int max_slots,
+                                 hipStream_t s) {
+  k_batch_advance<T><<<(max_slots + 255) / 256, 256, 0, s>>>(static_cast<const BatchSlot<T>*>(slots), t_now, hdr);
+}
+
+template <typename T, int NC, int TX, int TY, int NT>
+static constexpr BatchKernel batch_kernel() {
+  return BatchKernel{TX, TY, NT, batch_step_launch<T, NC, TX, TY, NT>, batch_advance_launch<T>};
+}
+
+// Candidate tile shapes for the autotuner, per precision and component
+// bound: FP32 keeps SPT * NC * 9 populations per thread in registers, FP64
+// twice the bytes, so FP64 and large NC get the shorter tiles.
+template <typename T, int NC>
+static const BatchKernel* batch_list(int* n) {
+  if constexpr (sizeof(T) == 4 && NC <= 3) {
+    static const BatchKernel k[] = {batch_kernel<T, NC, 64, 16, 256>(), batch_kernel<T, NC, 64, 8, 256>(),
+                                    batch_kernel<T, NC, 64, 4, 256>(),  batch_kernel<T, NC, 128, 8, 256>(),
+                                    batch_kernel<T, NC, 32, 16, 256>(), batch_kernel<T, NC, 32, 8, 256>()};
+    *n = int(sizeof(k) / sizeof(k[0]));
+    return k;
+  } else {
+    static const BatchKernel k[] = {batch_kernel<T, NC, 64, 8, 256>(), batch_kernel<T, NC, 64, 4, 256>(),
+                                    batch_kernel<T, NC, 32, 8, 256>()};
+    *n = int(sizeof(k) / sizeof(k[0]));
+    return k;
+  }
+}
+
+const BatchKernel* batch_kernels(int storage, int max_comp, int* n) {
+  *n = 0;
+  if (storage == 1) {
+    switch (max_comp) {
+      case 1: return batch_list<float, 1>(n);
+      case 2: return batch_list<float, 2>(n);
+      case 3: return batch_list<float, 3>(n);
+      case 4: return batch_list<float, 4>(n);
+      default: return nullptr;
+    }
+  }
+  if (storage == 0) {
+    switch (max_comp) {
+      case 1: return batch_list<double, 1>(n);
+      case 2: return batch_list<double, 2>(n);
+      case 3: return batch_list<double, 3>(n);
+      case 4: return batch_list<double, 4>(n);
+      default: return nullptr;
+    }
+  }
+  return nullptr;
 }
 
 // ------------------------------------------------------------ dispatch ----

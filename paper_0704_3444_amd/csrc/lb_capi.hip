@@ -15,10 +15,6 @@
 
 using lbm::Ctx;
 
-struct lb_ctx {
-  Ctx c;
-};
-
 namespace {
 
 thread_local std::string g_last_error;
@@ -219,7 +215,14 @@ size_t lb_workspace_bytes(const lb_params* p) {
   return layout_of(p).total;
 }
 
-int lb_init(const lb_params* p, const double* rho0, void* workspace, size_t workspace_bytes, lb_ctx** out) {
+}  // extern "C"
+
+namespace lbm {
+
+// lb_init with an optional device staging buffer for rho0 (at least
+// N * S doubles); without one, a buffer is allocated and freed here.
+int init_impl(const lb_params* p, const double* rho0, void* workspace, size_t workspace_bytes, double* staging,
+              lb_ctx** out) {
   std::string why;
   if (!out) return fail(LB_EINVAL, "out is NULL");
   *out = nullptr;
@@ -299,11 +302,14 @@ int lb_init(const lb_params* p, const double* rho0, void* workspace, size_t work
   }
   c.fused = c.path == LB_PATH_SWEEP ? sweep : (c.path == LB_PATH_TILE ? tile : nullptr);
 
-  double* rho_dev = nullptr;
-  hipError_t e = hipMalloc(&rho_dev, size_t(p->n_comp) * S * sizeof(double));
-  if (e != hipSuccess) {
-    lb_free(h);
-    return fail(LB_ENOMEM, std::string("hipMalloc of rho0 staging: ") + hipGetErrorString(e));
+  double* rho_dev = staging;
+  hipError_t e = hipSuccess;
+  if (!rho_dev) {
+    e = hipMalloc(&rho_dev, size_t(p->n_comp) * S * sizeof(double));
+    if (e != hipSuccess) {
+      lb_free(h);
+      return fail(LB_ENOMEM, std::string("hipMalloc of rho0 staging: ") + hipGetErrorString(e));
+    }
   }
   e = hipMemcpyAsync(rho_dev, rho0, size_t(p->n_comp) * S * sizeof(double), hipMemcpyHostToDevice, c.stream);
   if (e == hipSuccess) e = hipMemsetAsync(c.health_flag, 0, sizeof(int), c.stream);
@@ -316,7 +322,7 @@ int lb_init(const lb_params* p, const double* rho0, void* workspace, size_t work
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
-  (void)hipFree(rho_dev);
+  if (!staging) (void)hipFree(rho_dev);
   if (e != hipSuccess) {
     lb_free(h);
     return hip_fail(e, "lb_init");
@@ -327,6 +333,27 @@ int lb_init(const lb_params* p, const double* rho0, void* workspace, size_t work
   return LB_OK;
 }
 
+int fail_with(int code, const char* msg) { return fail(code, msg); }
+
+// Bytes of the lb_moments scratch for a context: rho, mu, h (N*S each), U
+// (D*S) and P (D(D+1)/2 * S) doubles.
+size_t moments_scratch_bytes(const lb_ctx* h) {
+  const Ctx& c = h->c;
+  const size_t S = size_t(c.S), N = size_t(c.prm.n_comp), D = size_t(c.D);
+  return (3 * N + D + D * (D + 1) / 2) * S * sizeof(double);
+}
+
+int moments_impl(lb_ctx* h, void* scratch, double* rho, double* U, double* mu, double* P, double* mass,
+                 double* mom, int64_t* step);
+
+}  // namespace lbm
+
+extern "C" {
+
+int lb_init(const lb_params* p, const double* rho0, void* workspace, size_t workspace_bytes, lb_ctx** out) {
+  return lbm::init_impl(p, rho0, workspace, workspace_bytes, nullptr, out);
+}
+
 int lb_step(lb_ctx* h, int64_t nsteps) {
   if (!h) return fail(LB_EINVAL, "ctx is NULL");
   if (nsteps < 0) return fail(LB_EINVAL, "nsteps must be >= 0");
@@ -335,6 +362,15 @@ int lb_step(lb_ctx* h, int64_t nsteps) {
 
 int lb_moments(lb_ctx* h, double* rho, double* U, double* mu, double* P, double* mass, double* mom,
                int64_t* step) {
+  return lbm::moments_impl(h, nullptr, rho, U, mu, P, mass, mom, step);
+}
+
+}  // extern "C"
+
+// lb_moments with an optional device scratch of moments_scratch_bytes;
+// without one, the field buffers are allocated and freed here.
+int lbm::moments_impl(lb_ctx* h, void* scratch, double* rho, double* U, double* mu, double* P, double* mass,
+                      double* mom, int64_t* step) {
   if (!h) return fail(LB_EINVAL, "ctx is NULL");
   Ctx& c = h->c;
   const int N = c.prm.n_comp, D = c.D;
@@ -345,11 +381,20 @@ int lb_moments(lb_ctx* h, double* rho, double* U, double* mu, double* P, double*
   int rc = LB_OK;
   if (fields) {
     const size_t nP = size_t(D) * (D + 1) / 2;
-    hipError_t e = hipMalloc(&d_rho, N * S * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(&d_mu, N * S * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(&d_h, N * S * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(&d_U, D * S * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(&d_P, nP * S * sizeof(double));
+    hipError_t e = hipSuccess;
+    if (scratch) {
+      d_rho = static_cast<double*>(scratch);
+      d_mu = d_rho + N * S;
+      d_h = d_mu + N * S;
+      d_U = d_h + N * S;
+      d_P = d_U + D * S;
+    } else {
+      e = hipMalloc(&d_rho, N * S * sizeof(double));
+      if (e == hipSuccess) e = hipMalloc(&d_mu, N * S * sizeof(double));
+      if (e == hipSuccess) e = hipMalloc(&d_h, N * S * sizeof(double));
+      if (e == hipSuccess) e = hipMalloc(&d_U, D * S * sizeof(double));
+      if (e == hipSuccess) e = hipMalloc(&d_P, nP * S * sizeof(double));
+    }
     if (e != hipSuccess) {
       rc = fail(LB_ENOMEM, std::string("lb_moments scratch: ") + hipGetErrorString(e));
     } else {
@@ -375,11 +420,13 @@ int lb_moments(lb_ctx* h, double* rho, double* U, double* mu, double* P, double*
   } else {
     (void)hipStreamSynchronize(c.stream);
   }
-  (void)hipFree(d_rho);
-  (void)hipFree(d_mu);
-  (void)hipFree(d_h);
-  (void)hipFree(d_U);
-  (void)hipFree(d_P);
+  if (!scratch) {
+    (void)hipFree(d_rho);
+    (void)hipFree(d_mu);
+    (void)hipFree(d_h);
+    (void)hipFree(d_U);
+    (void)hipFree(d_P);
+  }
   if (rc != LB_OK) return rc;
   if (mass)
     for (int k = 0; k < N; ++k) mass[k] = out[k];
@@ -389,6 +436,8 @@ int lb_moments(lb_ctx* h, double* rho, double* U, double* mu, double* P, double*
   if (flag) return fail(LB_ENUMERIC, "a component density became non-finite or <= 0");
   return LB_OK;
 }
+
+extern "C" {
 
 int lb_get_f(lb_ctx* h, double* f) {
   if (!h || !f) return fail(LB_EINVAL, "NULL argument");

@@ -63,4 +63,49 @@ struct SplitTable {
 
 const SplitTable& split_table(int lattice, int storage);
 
+// ------------------------------------------------------------ batching ----
+// Slot table of the batched kernel (device memory, written by the host).
+struct BatchHeader {
+  int nslots;  // live slots in the table, in order of first_item
+  int items;   // work items (tiles) over all live slots
+};
+
+template <typename T>
+struct BatchSlot {
+  Params<T> p;
+  void* f[2];        // population copies; f[t & 1] is current at step t
+  long long t_end;   // the slot is stepped while its counter is below this
+  int id;            // index of the slot's step counter
+  int first_item;    // first work item of the slot
+  int tiles_x;       // tiles per row
+  int pad;
+};
+
+// One configuration of the batched kernel: tile shape, threads per
+// workgroup and a launcher for a given grid.
+struct BatchKernel {
+  int tx, ty, threads;
+  // step: one launch advancing every live slot by one step
+  void (*step)(const void* slots, const long long* t_now, const BatchHeader* hdr, const int* item_slot, int grid,
+               hipStream_t s);
+  // advance: counters += 1 for the slots below their target
+  void (*advance)(const void* slots, long long* t_now, const BatchHeader* hdr, int max_slots, hipStream_t s);
+};
+
+// Candidate configurations for (storage, max components); count in *n.
+const BatchKernel* batch_kernels(int storage, int max_comp, int* n);
+
+// Entry points of lb_capi.hip shared with the batch runtime.
+int fail_with(int code, const char* msg);  // sets lb_last_error, returns code
+int init_impl(const lb_params* p, const double* rho0, void* workspace, size_t workspace_bytes, double* staging,
+              lb_ctx** out);
+size_t moments_scratch_bytes(const lb_ctx* h);
+int moments_impl(lb_ctx* h, void* scratch, double* rho, double* U, double* mu, double* P, double* mass,
+                 double* mom, int64_t* step);
+
 }  // namespace lbm
+
+// The opaque handle of the C ABI.
+struct lb_ctx {
+  lbm::Ctx c;
+};

@@ -27,6 +27,9 @@ EXPORTS = [
     "lb_workspace_bytes", "lb_init", "lb_step", "lb_moments", "lb_get_f", "lb_state_bytes",
     "lb_get_state", "lb_set_state", "lb_lattice_tables", "lb_path_in_use", "lb_free",
     "lb_strerror", "lb_last_error",
+    "lb_batch_create", "lb_batch_footprint", "lb_batch_add", "lb_batch_step", "lb_batch_poll",
+    "lb_batch_moments", "lb_batch_remove", "lb_batch_config_count", "lb_batch_config_info",
+    "lb_batch_set_config", "lb_batch_tune", "lb_batch_free",
 ]
 
 
@@ -37,6 +40,13 @@ class lb_params(C.Structure):
         ("tau", C.c_double * MAX_COMP), ("theta", C.c_double), ("kappa", C.c_double),
         ("m", C.c_double * MAX_COMP), ("chi", C.c_double * (MAX_COMP * MAX_COMP)),
         ("path", C.c_int32), ("check_every", C.c_int32), ("stream", C.c_void_p),
+    ]
+
+
+class lb_batch_params(C.Structure):
+    _fields_ = [
+        ("storage", C.c_int32), ("max_comp", C.c_int32), ("max_slots", C.c_int32), ("config", C.c_int32),
+        ("graph_steps", C.c_int32), ("reserved", C.c_int32), ("arena_bytes", C.c_size_t), ("stream", C.c_void_p),
     ]
 
 
@@ -56,6 +66,11 @@ def load() -> C.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_0704_3444_amd/build.py")
+    # PyTorch ships its own HIP runtime (soname libamdhip64.so.7).  Loading it
+    # first makes liblbm.so bind to that same runtime; loading liblbm.so first
+    # would bring in a second HIP runtime, after which PyTorch finds no GPU.
+    import torch  # noqa: F401
+
     lib = C.CDLL(LIB_PATH)
     dp, vp = C.POINTER(C.c_double), C.c_void_p
     P = C.POINTER(lb_params)
@@ -78,8 +93,26 @@ def load() -> C.CDLL:
     lib.lb_strerror.restype = C.c_char_p
     lib.lb_last_error.argtypes = []
     lib.lb_last_error.restype = C.c_char_p
+    BP, bp = C.POINTER(lb_batch_params), C.c_void_p
+    i32p, i64p = C.POINTER(C.c_int32), C.POINTER(C.c_int64)
+    lib.lb_batch_create.argtypes = [BP, C.POINTER(bp)]
+    lib.lb_batch_footprint.argtypes = [bp, P]
+    lib.lb_batch_footprint.restype = C.c_size_t
+    lib.lb_batch_add.argtypes = [bp, P, dp, C.c_int64, i32p]
+    lib.lb_batch_step.argtypes = [bp, C.c_int64]
+    lib.lb_batch_poll.argtypes = [bp, C.c_int32, i64p]
+    lib.lb_batch_moments.argtypes = [bp, C.c_int32, dp, dp, dp, dp, dp, dp, i64p]
+    lib.lb_batch_remove.argtypes = [bp, C.c_int32]
+    lib.lb_batch_config_count.argtypes = [C.c_int32, C.c_int32]
+    lib.lb_batch_config_info.argtypes = [C.c_int32, C.c_int32, C.c_int32, i32p, i32p, i32p, i32p]
+    lib.lb_batch_set_config.argtypes = [bp, C.c_int32]
+    lib.lb_batch_tune.argtypes = [bp, C.c_int32, dp, i32p]
+    lib.lb_batch_free.argtypes = [bp]
+    lib.lb_batch_free.restype = None
     for name in ("lb_init", "lb_step", "lb_moments", "lb_get_f", "lb_get_state", "lb_set_state",
-                 "lb_lattice_tables", "lb_path_in_use"):
+                 "lb_lattice_tables", "lb_path_in_use", "lb_batch_create", "lb_batch_add", "lb_batch_step",
+                 "lb_batch_poll", "lb_batch_moments", "lb_batch_remove", "lb_batch_config_count",
+                 "lb_batch_config_info", "lb_batch_set_config", "lb_batch_tune"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -242,6 +275,106 @@ class Simulation:
         if getattr(self, "ctx", None):
             lb_free(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ batches
+def lb_batch_config_count(storage: str, max_comp: int) -> int:
+    return _check(load().lb_batch_config_count(STORAGE[storage], max_comp))
+
+
+def lb_batch_config_info(storage: str, max_comp: int, config: int) -> dict:
+    v = [C.c_int32() for _ in range(4)]
+    _check(load().lb_batch_config_info(STORAGE[storage], max_comp, config, *[C.byref(x) for x in v]))
+    return {"tile": (v[0].value, v[1].value), "threads": v[2].value, "groups_per_cu": v[3].value}
+
+
+class Batch:
+    """Many independent D2Q9 runs stepped together by the persistent batched
+    kernel (lb_batch_* of the C ABI).  Slots join with add() and leave with
+    remove(); step() advances every live slot; poll() returns the step
+    counters; moments() reads a finished slot's observables."""
+
+    def __init__(self, *, storage="f32", max_comp=3, max_slots=64, arena_bytes=4 << 30, config=-1,
+                 graph_steps=16, stream=None):
+        bp = lb_batch_params()
+        bp.storage, bp.max_comp, bp.max_slots = STORAGE[storage], int(max_comp), int(max_slots)
+        bp.config, bp.graph_steps, bp.arena_bytes = int(config), int(graph_steps), int(arena_bytes)
+        bp.stream = stream
+        self.storage, self.max_slots, self.max_comp = storage, int(max_slots), int(max_comp)
+        h = C.c_void_p()
+        _check(load().lb_batch_create(C.byref(bp), C.byref(h)))
+        self.h = h.value
+        self.meta = {}
+
+    def footprint(self, cfg: dict) -> int:
+        p = make_params(cfg, storage=self.storage)
+        return int(load().lb_batch_footprint(C.c_void_p(self.h), C.byref(p)))
+
+    def add(self, cfg: dict, rho0: np.ndarray, nsteps: int) -> int:
+        p = make_params(cfg, storage=self.storage)
+        rho0 = np.ascontiguousarray(rho0, dtype=np.float64)
+        slot = C.c_int32()
+        _check(load().lb_batch_add(C.c_void_p(self.h), C.byref(p), _dptr(rho0), C.c_int64(nsteps), C.byref(slot)))
+        self.meta[slot.value] = (int(cfg["n_comp"]), int(np.prod(cfg["shape"])))
+        return slot.value
+
+    def try_add(self, cfg: dict, rho0: np.ndarray, nsteps: int) -> Optional[int]:
+        """add(), or None when the batch has no free slot or arena range."""
+        try:
+            return self.add(cfg, rho0, nsteps)
+        except LBError as e:
+            if e.code == LB_ENOMEM:
+                return None
+            raise
+
+    def step(self, n: int) -> None:
+        _check(load().lb_batch_step(C.c_void_p(self.h), C.c_int64(n)))
+
+    def poll(self, lag: int = 0) -> np.ndarray:
+        out = np.zeros(self.max_slots, dtype=np.int64)
+        _check(load().lb_batch_poll(C.c_void_p(self.h), lag, out.ctypes.data_as(C.POINTER(C.c_int64))))
+        return out
+
+    def moments(self, slot: int, fields=True) -> dict:
+        n, sites = self.meta[slot]
+        out = {"mass": np.zeros(n), "mom": np.zeros(2)}
+        if fields:
+            out.update(rho=np.zeros((n, sites)), U=np.zeros((2, sites)), mu=np.zeros((n, sites)),
+                       P=np.zeros((3, sites)))
+        step = C.c_int64()
+        rc = load().lb_batch_moments(C.c_void_p(self.h), slot, _dptr(out.get("rho")), _dptr(out.get("U")),
+                                     _dptr(out.get("mu")), _dptr(out.get("P")), _dptr(out["mass"]),
+                                     _dptr(out["mom"]), C.byref(step))
+        out["step"], out["status"] = step.value, rc
+        if rc != LB_ENUMERIC:
+            _check(rc)
+        return out
+
+    def remove(self, slot: int) -> None:
+        _check(load().lb_batch_remove(C.c_void_p(self.h), slot))
+        self.meta.pop(slot, None)
+
+    def set_config(self, config: int) -> None:
+        _check(load().lb_batch_set_config(C.c_void_p(self.h), config))
+
+    def tune(self, steps: int = 20):
+        """Time every kernel configuration on the live slots and keep the
+        fastest: returns (index, ms per step of each configuration)."""
+        ms = np.zeros(lb_batch_config_count(self.storage, self.max_comp))
+        best = C.c_int32()
+        _check(load().lb_batch_tune(C.c_void_p(self.h), steps, _dptr(ms), C.byref(best)))
+        return best.value, ms
+
+    def close(self) -> None:
+        if getattr(self, "h", None):
+            load().lb_batch_free(C.c_void_p(self.h))
+            self.h = None
 
     def __del__(self):
         try:

@@ -66,3 +66,42 @@ def test_lattice_tables_match_isotropy():
         vv = v[:, :D].astype(float)
         assert abs(w.sum() - 1) < 1e-15
         assert np.allclose(np.einsum("i,ia,ib->ab", w, vv, vv), np.eye(D) / 3, atol=1e-16)
+
+
+def test_batch_configurations_host_only():
+    """The batched kernel's configurations are host-side tables."""
+    from paper_0704_3444_amd import lb
+
+    assert lb.lb_batch_config_count("f32", 3) == 18
+    assert lb.lb_batch_config_count("f64", 2) == 9
+    seen = set()
+    for c in range(lb.lb_batch_config_count("f32", 3)):
+        info = lb.lb_batch_config_info("f32", 3, c)
+        tx, ty = info["tile"]
+        assert info["threads"] % tx == 0 and ty % (info["threads"] // tx) == 0
+        assert info["groups_per_cu"] in (2, 4, 8)
+        seen.add((tx, ty, info["groups_per_cu"]))
+    assert len(seen) == 18
+    with pytest.raises(lb.LBError):
+        lb.lb_batch_config_count("f16s", 3)
+    with pytest.raises(lb.LBError):
+        lb.lb_batch_config_info("f32", 3, 18)
+
+
+def test_serving_mix_is_seeded_and_in_range():
+    import numpy as np
+    import lbinputs as LI
+
+    a = LI.serving_mix(40, seed=5)
+    b = LI.serving_mix(40, seed=5)
+    assert [x["arrival"] for x in a] == [x["arrival"] for x in b]
+    assert all(np.array_equal(x["rho0"], y["rho0"]) for x, y in zip(a, b))
+    arr = np.array([x["arrival"] for x in a])
+    assert np.all(np.diff(arr) > 0)
+    for x in a:
+        L = x["cfg"]["shape"][0]
+        assert 64 <= L <= 512 and x["cfg"]["shape"] == (L, L)
+        assert x["cfg"]["n_comp"] in (2, 3) and x["nsteps"] == 5000
+        assert np.all(x["rho0"] > 0) and np.allclose(x["rho0"].sum(0), 1.0, atol=0.03)
+        chi = x["cfg"]["chi"]
+        assert np.array_equal(chi, chi.T) and np.all(np.diag(chi) == 0)
