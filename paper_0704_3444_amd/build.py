@@ -19,6 +19,9 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no automatic mul+add contraction: fused operations are written out, so
+    # every kernel rounds the shared per-site arithmetic identically
+    "-ffp-contract=off",
     "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
 ]
 

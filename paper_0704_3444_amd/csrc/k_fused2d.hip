@@ -23,6 +23,7 @@
 
 #include "lbm_internal.hpp"
 #include "physics.hpp"
+#include "storage.hpp"
 
 namespace lbm {
 
@@ -61,7 +62,7 @@ __device__ __forceinline__ void pulled_density(const T* __restrict__ fin, const 
   for (int i = 0; i < L::Q; ++i) {
     const int sx = L::cx(i) > 0 ? xm : (L::cx(i) < 0 ? xp : x);
     const int sy = L::cy(i) > 0 ? ym : (L::cy(i) < 0 ? yp : y);
-    off[i] = site_offset<T>(p.nbx, p.nq, sx, sy) + uint32_t(i * kBlockX * sizeof(T));
+    off[i] = site_offset<T>(p.nbx, p.nq, sx, sy) + uint32_t(run_slot<L::Q>(i) * kBlockX * sizeof(T));
   }
 #pragma unroll
   for (int k = 0; k < NC; ++k) {
@@ -113,7 +114,7 @@ __device__ __forceinline__ void tile_step(const T* __restrict__ fin, T* __restri
       for (int i = 0; i < Q; ++i) {
         const int sx = L::cx(i) > 0 ? xm : (L::cx(i) < 0 ? xp : x);
         const int sy = L::cy(i) > 0 ? ym : (L::cy(i) < 0 ? yp : y);
-        off[i] = site_offset<T>(p.nbx, p.nq, sx, sy) + uint32_t(i * kBlockX * sizeof(T));
+        off[i] = site_offset<T>(p.nbx, p.nq, sx, sy) + uint32_t(run_slot<Q>(i) * kBlockX * sizeof(T));
       }
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
@@ -227,7 +228,7 @@ __device__ __forceinline__ void tile_step(const T* __restrict__ fin, T* __restri
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
         T* dst = reinterpret_cast<T*>(reinterpret_cast<char*>(fout) + own +
-                                      uint32_t((c * Q + i) * kBlockX * sizeof(T)));
+                                      uint32_t((c * Q + run_slot<Q>(i)) * kBlockX * sizeof(T)));
         if constexpr (NTSTORE)
           __builtin_nontemporal_store(f[k][c][i], dst);
         else

@@ -4,25 +4,31 @@
 // A workgroup of four waves owns a strip of 64 columns (one 64-site block of
 // the population layout) and a segment of rows, which it sweeps from top to
 // bottom.  Wave w handles the rows y = w (mod 4) of the segment.  One round
-// advances four rows:
-//   1. density rho^sigma of the rows one round ahead, from populations the
-//      waves already hold in registers (plus four halo columns formed by 12
-//      lanes), into an LDS ring of rows;
-//   2. chemical potentials and the potential h of four rows into an LDS ring
-//      (the Laplacian in mu and the gradient of mu reach two rows ahead);
-//   3. prefetch of the populations two rounds ahead;
-//   4. force, equilibrium, forcing term and collision of the current row,
-//      stored in place (streaming happens through the next step's pull).
-// Each wave keeps three rows of populations in registers (current, one round
-// ahead, in flight).  Rows are re-read only at the two ends of a segment
-// (4 rows per segment) and the strip edges (4 columns per 64), instead of a
-// two-site ring around every tile.  Workgroups are banded per XCD so that
-// neighbouring strips share L2.
+// advances four rows; per wave:
+//   1. wait for the row it staged one round earlier, take its pulled
+//      populations into registers and write its densities (and the halo
+//      columns') into the LDS ring of densities;
+//   2. stage the populations pulled into its density row of the next round
+//      in the same LDS slot with direct global-to-LDS loads: per component
+//      the three runs that row pulls from each source row are one
+//      contiguous, aligned piece of that row's block (the block layout
+//      groups the runs by v_y), three 16-byte-per-lane loads per component,
+//      plus the few values from the neighbouring strips (the x shift of
+//      lanes 0 and 63 and the four density-halo columns);
+//   3. (barrier) chemical potentials and the potential h of its row into an
+//      LDS ring (wave 0 also the eight edge columns of the four rows);
+//   4. (barrier) force, equilibrium, forcing term and collision of the row
+//      it took one round earlier; non-temporal stores in place (streaming
+//      happens through the next step's pull).
+// Staged rows are private to their wave, so only the two rings need the
+// workgroup barriers; the loads in flight hold no registers.  The compiler
+// does not track direct loads into LDS, so the wave waits for its own
+// staging with an explicit vmcnt(0) (one counter covers loads and stores,
+// which may complete out of order with respect to each other).  Workgroups
+// are banded per XCD so that neighbouring strips share L2.
 //
 // The kernel is templated on the storage codec (storage.hpp): FP32, or
-// shifted FP16 whose rows stay in registers as stored (per component the
-// FP32 ledger and four packed pairs of FP16 deviations, 5 registers instead
-// of 9) and are decoded where the collision needs them.
+// shifted FP16 (decoded when the row is taken from LDS).
 #include <hip/hip_runtime.h>
 
 #include "lbm_internal.hpp"
@@ -33,173 +39,242 @@ namespace lbm {
 namespace sweep {
 
 constexpr int kXcds = 8;
-constexpr int kRhoRing = 16;  // rows of rho kept in LDS (live span is 9)
-constexpr int kHRing = 8;     // rows of h kept in LDS (live span is 8)
+constexpr int kRhoRing = 16;  // rows of rho in LDS: 9 live, and a wave one round ahead writes 12 rows further
+constexpr int kHRing = 8;     // rows of h in LDS (8 live; written only between barriers)
 constexpr int kW = 64;        // strip width = block width = wave size
 constexpr int kRW = kW + 4;   // rho row: columns x0 - 2 .. x0 + 65
 constexpr int kHW = kW + 2;   // h row:   columns x0 - 1 .. x0 + 64
+constexpr int kLdsBytes = 163840;
 
 __device__ __forceinline__ int wrap_mod(int v, int n) {
   int r = v % n;
   return r < 0 ? r + n : r;
 }
 
-// Byte offset of the 64-site block that holds site (x, y); the caller
-// guarantees one copy is below 4 GiB.
-template <class S, int NC>
-__device__ __forceinline__ uint32_t blk_off(int nbx, int x, int y) {
-  return (uint32_t(y) * uint32_t(nbx) + uint32_t(x >> 6)) * uint32_t(NC * BlockLayout<S, 9>::kComp);
+// s_waitcnt vmcnt(N), the other counters untouched, as a compiler memory
+// barrier: the LDS written by the direct loads is read only after it.
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
 }
 
-typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+// Workgroup barrier that publishes this wave's LDS writes without waiting
+// for its global loads in flight.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
-// Populations of one site for J components as stored.
-template <class S, int J>
-struct Pops;
-
-template <int J>
-struct Pops<StoreF32, J> {
-  float v[J][9];
-  __device__ __forceinline__ void set(int j, int i, const char* a) { v[j][i] = *reinterpret_cast<const float*>(a); }
-  __device__ __forceinline__ void zero() {
-#pragma unroll
-    for (int j = 0; j < J; ++j)
-#pragma unroll
-      for (int i = 0; i < 9; ++i) v[j][i] = 0.0f;
-  }
-  // density of entry j (component c), summed in direction order
-  __device__ __forceinline__ float density(const ShiftRef&, int j, int) const {
-    float acc = 0.0f;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) acc += v[j][i];
-    return acc;
-  }
-  __device__ __forceinline__ void decode(const ShiftRef&, int j, float (&f)[9], float& ledger) const {
-#pragma unroll
-    for (int i = 0; i < 9; ++i) f[i] = v[j][i];
-    ledger = 0.0f;
-  }
-};
-
-template <int J>
-struct Pops<StoreF16S, J> {
-  float r[J];          // ledger slot (i = 0)
-  half2_t m[J][4];     // deviations of i = 1 .. 8, two per register
-  __device__ __forceinline__ void set(int j, int i, const char* a) {
-    if (i == 0)
-      r[j] = *reinterpret_cast<const float*>(a);
-    else
-      m[j][(i - 1) >> 1][(i - 1) & 1] = *reinterpret_cast<const _Float16*>(a);
-  }
-  __device__ __forceinline__ void zero() {
-#pragma unroll
-    for (int j = 0; j < J; ++j) {
-      r[j] = 0.0f;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) m[j][k] = half2_t{_Float16(0), _Float16(0)};
-    }
-  }
-  __device__ __forceinline__ float raw(int j, int i) const {
-    return i == 0 ? r[j] : float(m[j][(i - 1) >> 1][(i - 1) & 1]);
-  }
-  // exact total deviation d_0 + sum_{i>0} d_i, in direction order
-  __device__ __forceinline__ float ledger(int j) const {
-    float L = r[j];
-#pragma unroll
-    for (int i = 1; i < 9; ++i) L += raw(j, i);
-    return L;
-  }
-  __device__ __forceinline__ float density(const ShiftRef& sh, int j, int c) const {
-    return __builtin_fmaf(ledger(j), sh.scale[c], sh.csum[c]);
-  }
-  __device__ __forceinline__ void decode(const ShiftRef& sh, int j, float (&f)[9], float& L) const {
-    L = ledger(j);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) f[i] = ::lbm::decode<StoreF16S, 2>(sh, j, i, raw(j, i));
-  }
-};
-
-// The populations pulled into site (x, prow): f_i comes from (x - v_i).
+// Staged row: per component the nine runs of the pulled populations in the
+// block's run order (v_y groups 0 | +1 | -1, each from its source row), then
+// the edge words (per component lane 0's three v_x = +1 populations from
+// column x0 - 1 and lane 63's three v_x = -1 populations from column x0 + 64),
+// then the halo words (the nine populations pulled into each of the columns
+// x0-2, x0-1, x0+64, x0+65, per component).  A word of shifted FP16 storage
+// holds the FP16 values of an even/odd column pair; the parity of the
+// source column selects the half.
 template <class S, int NC>
-__device__ __forceinline__ void load_row(const void* __restrict__ fin, const Params<float>& p, int x, int prow,
-                                         Pops<S, NC>& F) {
-  using L = Lattice<2>;
+struct Staged {
   using B = BlockLayout<S, 9>;
-  const char* base = static_cast<const char*>(fin);
-  const int xm = wrap_add(x, -1, p.nx), xp = wrap_add(x, 1, p.nx);
-  const int ym = wrap_add(prow, -1, p.ny), yp = wrap_add(prow, 1, p.ny);
-#pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    const int sx = L::cx(i) > 0 ? xm : (L::cx(i) < 0 ? xp : x);
-    const int sy = L::cy(i) > 0 ? ym : (L::cy(i) < 0 ? yp : prow);
-    const uint32_t off = blk_off<S, NC>(p.nbx, sx, sy) + B::in_run(i, sx);
-#pragma unroll
-    for (int c = 0; c < NC; ++c) F.set(c, i, base + off + B::run(c, i));
-  }
+  static constexpr uint32_t kGroup0 = kW * (B::kRest + 2 * B::kMove);  // v_y = 0: i = 0, 1, 3
+  static constexpr uint32_t kGroup1 = kW * 3 * B::kMove;               // v_y = +-1: 2, 5, 6 / 4, 7, 8
+  static constexpr uint32_t kMain = NC * B::kComp;
+  static constexpr int kEdge = 6 * NC;
+  static constexpr int kHalo = 36 * NC;
+  static constexpr int kHaloLoads = (kHalo + 63) / 64;
+  static constexpr uint32_t kEdgeOff = kMain;
+  static constexpr uint32_t kHaloOff = kMain + 4 * kEdge;
+  static constexpr uint32_t kBytes = (kHaloOff + 4 * kHalo + 15) / 16 * 16;
+  static constexpr int kLoads = 3 * NC + 1 + kHaloLoads;  // direct loads per staged row
+  static_assert(kGroup0 % 16 == 0 && kGroup1 % 16 == 0 && kGroup0 <= 1024 && kGroup1 <= 1024, "group size");
+};
+
+// LDS bytes of one workgroup and workgroups per CU that LDS allows.
+template <class S, int NC>
+constexpr int sweep_lds() {
+  return int(sizeof(float)) * NC * (kRhoRing * kRW + kHRing * kHW) + 4 * int(Staged<S, NC>::kBytes);
+}
+template <class S, int NC>
+constexpr int sweep_groups_per_cu() {
+  return kLdsBytes / sweep_lds<S, NC>();
 }
 
-// Halo columns x0-2, x0-1, x0+64, x0+65 of the four rows r0 .. r0+3: lane
-// L < 16 NC pulls the nine populations of (row r0 + L / (4 NC), halo column,
-// component).  One wave loads them for the whole workgroup.
+// Edge entry k (0..5) of a component: v_x = +1 velocities 1, 5, 8 (column
+// x0 - 1), then v_x = -1 velocities 3, 6, 7 (column x0 + 64).
+__device__ __forceinline__ int edge_dir(int k) {
+  return k == 0 ? 1 : k == 1 ? 5 : k == 2 ? 8 : k == 3 ? 3 : k == 4 ? 6 : 7;
+}
+__host__ __device__ constexpr int edge_entry(int i) {
+  return i == 1 ? 0 : i == 5 ? 1 : i == 8 ? 2 : i == 3 ? 3 : i == 6 ? 4 : 5;
+}
+
+// Byte offset, without the row part, of the 32-bit word that holds slot i
+// of component c in column sx.
 template <class S, int NC>
-__device__ __forceinline__ void load_halo4(const void* __restrict__ fin, const Params<float>& p, int lane, int x0,
-                                           int r0, Pops<S, 1>& Hv) {
-  using L = Lattice<2>;
+__device__ __forceinline__ uint32_t word_col(int c, int i, int sx) {
   using B = BlockLayout<S, 9>;
-  const char* base = static_cast<const char*>(fin);
-  if (lane < 16 * NC) {
-    const int wr = lane / (4 * NC), hc = (lane % (4 * NC)) / NC, c = lane % NC;
-    const int prow = wrap_mod(r0 + wr, p.ny);
+  return (uint32_t(sx >> 6) * uint32_t(NC * B::kComp) + B::run(c, i) + B::in_run(i, sx)) & ~3u;
+}
+
+// Per-lane parts of the edge and halo words that do not change along the
+// sweep: the column part of the byte offset and which source row (v_y = +1:
+// the row above, 0: the row itself, -1: the row below) the word comes from.
+template <int NC>
+struct Gather {
+  uint32_t col[1 + (36 * NC + 63) / 64];
+  int dy[1 + (36 * NC + 63) / 64];
+};
+
+template <class S, int NC>
+__device__ __forceinline__ Gather<NC> make_gather(const Params<float>& p, int lane, int x0) {
+  using L = Lattice<2>;
+  using G = Staged<S, NC>;
+  Gather<NC> g;
+  {  // edge words: lane e = 6 c + k
+    const int e = lane < G::kEdge ? lane : 0;
+    const int c = e / 6, k = e % 6, i = edge_dir(k);
+    const int sx = k < 3 ? wrap_add(x0, -1, p.nx) : wrap_add(x0 + kW - 1, 1, p.nx);
+    g.col[0] = word_col<S, NC>(c, i, sx);
+    g.dy[0] = L::cy(i);
+  }
+#pragma unroll
+  for (int j = 0; j < G::kHaloLoads; ++j) {  // halo words: value v = (hc NC + c) 9 + i
+    const int v0 = j * 64 + lane;
+    const int v = v0 < G::kHalo ? v0 : 0;
+    const int hc = v / (9 * NC), c = (v / 9) % NC, i = v % 9;
     const int hx = wrap_mod(x0 + (hc < 2 ? hc - 2 : kW + hc - 2), p.nx);
-    const int xm = wrap_add(hx, -1, p.nx), xp = wrap_add(hx, 1, p.nx);
-    const int ym = wrap_add(prow, -1, p.ny), yp = wrap_add(prow, 1, p.ny);
+    g.col[1 + j] = word_col<S, NC>(c, i, wrap_add(hx, -L::cx(i), p.nx));
+    g.dy[1 + j] = L::cy(i);
+  }
+  return g;
+}
+
+// Stage the populations pulled into row r (wave-uniform) of the strip at x0
+// into the LDS slot `dst` (Staged layout) with exactly Staged::kLoads direct
+// loads (each load has at least one active lane).
+template <class S, int NC>
+__device__ __forceinline__ void stage_row(const char* __restrict__ fin, const Params<float>& p, const Gather<NC>& g,
+                                          int lane, int x0, int r, char* dst) {
+  using B = BlockLayout<S, 9>;
+  using G = Staged<S, NC>;
+  const uint32_t stride = uint32_t(p.nbx) * uint32_t(NC * B::kComp);
+  const uint32_t blk = uint32_t(x0 >> 6) * uint32_t(NC * B::kComp);
+  // row parts of the source rows of the v_y groups 0, +1 (row above), -1
+  const uint32_t row0 = uint32_t(r) * stride, rowu = uint32_t(wrap_add(r, -1, p.ny)) * stride,
+                 rowd = uint32_t(wrap_add(r, 1, p.ny)) * stride;
+  const uint32_t ry[3] = {row0, rowu, rowd};
+  constexpr int first[3] = {0, 2, 4};  // first velocity of each group
+  constexpr uint32_t bytes[3] = {G::kGroup0, G::kGroup1, G::kGroup1};
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      const int sx = L::cx(i) > 0 ? xm : (L::cx(i) < 0 ? xp : hx);
-      const int sy = L::cy(i) > 0 ? ym : (L::cy(i) < 0 ? yp : prow);
-      Hv.set(0, i, base + blk_off<S, NC>(p.nbx, sx, sy) + B::in_run(i, sx) + B::run(c, i));
+  for (int c = 0; c < NC; ++c) {
+#pragma unroll
+    for (int g3 = 0; g3 < 3; ++g3) {
+      const char* src = fin + (ry[g3] + blk + B::run(c, first[g3])) + uint32_t(lane) * 16u;
+      if (uint32_t(lane) * 16u < bytes[g3])
+        __builtin_amdgcn_global_load_lds(src, dst + B::run(c, first[g3]), 16, 0, 0);
     }
+  }
+  auto row_of = [&](int dy) { return dy > 0 ? rowu : (dy < 0 ? rowd : row0); };
+  if (lane < G::kEdge)
+    __builtin_amdgcn_global_load_lds(fin + (row_of(g.dy[0]) + g.col[0]), dst + G::kEdgeOff, 4, 0, 0);
+#pragma unroll
+  for (int j = 0; j < G::kHaloLoads; ++j)
+    if (j * 64 + lane < G::kHalo)
+      __builtin_amdgcn_global_load_lds(fin + (row_of(g.dy[1 + j]) + g.col[1 + j]), dst + G::kHaloOff + 256 * j, 4,
+                                       0, 0);
+}
+
+// Raw value of slot i from a staged word: the word itself, or for moving
+// slots of shifted FP16 storage the half of the given column parity.
+template <class S>
+__device__ __forceinline__ float word_value(uint32_t wbits, int i, bool odd) {
+  if constexpr (S::kShift) {
+    if (i == 0) return __builtin_bit_cast(float, wbits);
+    const uint16_t h = uint16_t(odd ? (wbits >> 16) : (wbits & 0xffffu));
+    return float(__builtin_bit_cast(_Float16, h));
+  } else {
+    return __builtin_bit_cast(float, wbits);
   }
 }
 
-template <class S, int NC, int PF>
-__global__ void __launch_bounds__(256) k_sweep_d2q9(const void* __restrict__ fin, void* __restrict__ fout,
+template <class S>
+__device__ __forceinline__ float lds_raw(const char* a, int i) {
+  if (i == 0) return float(*reinterpret_cast<const typename S::Rest*>(a));
+  return float(*reinterpret_cast<const typename S::Move*>(a));
+}
+
+template <class S, int NC>
+__global__ void __launch_bounds__(256) k_sweep_d2q9(const void* __restrict__ fin_v, void* __restrict__ fout,
                                                     Params<float> p, int strips, int seg_rows, int ntiles,
                                                     int tiles_per_xcd) {
   using L = Lattice<2>;
   using T = float;
   using B = BlockLayout<S, 9>;
-  static_assert(PF == 1 || PF == 2, "prefetch depth in rounds");
+  using G = Staged<S, NC>;
   __shared__ T s_rho[kRhoRing][NC][kRW];
   __shared__ T s_h[kHRing][NC][kHW];
+  __shared__ __attribute__((aligned(16))) char s_stage[4][G::kBytes];
+  const char* __restrict__ fin = static_cast<const char*>(fin_v);
 
   const int b = blockIdx.x;
   const int t = (b % kXcds) * tiles_per_xcd + b / kXcds;
   if (t >= ntiles) return;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform over the wave
   const int x0 = (t % strips) * kW;
   const int ya = (t / strips) * seg_rows;
   const int yb = min(ya + seg_rows, p.ny);
   const int rounds = (yb - ya + 3) / 4;
-  const int x = x0 + lane;  // nx is a multiple of 64: every lane is a site
   const int ny = p.ny;
-  constexpr int kHaloWave = 1, kEdgeWave = 0;
 
   // ring slots of virtual row r (r >= ya - 8 always)
   auto rslot = [&](int r) { return (r - ya + 8 * kRhoRing) & (kRhoRing - 1); };
   auto hslot = [&](int r) { return (r - ya + 8 * kHRing) & (kHRing - 1); };
 
-  // density of virtual row r from the wave's populations
-  auto put_rho = [&](int r, const Pops<S, NC>& F) {
+  // columns of the lane's pulled slots in a staged row, clamped into the
+  // strip; the edge lanes take the edge words instead
+  const int lm = lane > 0 ? lane - 1 : 0, lp = lane < kW - 1 ? lane + 1 : kW - 1;
+
+  // Take a staged row into registers: decoded populations, in direction
+  // order, and the ledger of each component (shifted codec).
+  auto take = [&](const char* st, T (&f)[NC][9], T (&ledger)[NC]) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      T led = T(0);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        const int col = L::cx(i) > 0 ? lm : (L::cx(i) < 0 ? lp : lane);
+        T raw = lds_raw<S>(st + B::run(c, i) + B::in_run(i, col), i);
+        if (L::cx(i) != 0) {
+          const uint32_t wbits = *reinterpret_cast<const uint32_t*>(st + G::kEdgeOff + 4 * (6 * c + edge_entry(i)));
+          const T e = word_value<S>(wbits, i, L::cx(i) > 0);  // column x0 - 1 is odd, x0 + 64 even
+          raw = (L::cx(i) > 0 ? lane == 0 : lane == kW - 1) ? e : raw;
+        }
+        led = i == 0 ? raw : led + raw;
+        f[c][i] = decode<S, 2>(p.sh, c, i, raw);
+      }
+      ledger[c] = led;
+    }
+  };
+  // densities of virtual row r from taken populations
+  auto put_rho = [&](int r, const T (&f)[NC][9], const T (&ledger)[NC]) {
     const int sr = rslot(r);
 #pragma unroll
-    for (int c = 0; c < NC; ++c) s_rho[sr][c][lane + 2] = F.density(p.sh, c, c);
+    for (int c = 0; c < NC; ++c) s_rho[sr][c][lane + 2] = site_density<S, 9>(p.sh, c, f[c], ledger[c]);
   };
-  // halo densities of rows r0 .. r0+3 from the halo wave's values
-  auto put_rho_halo = [&](int r0, const Pops<S, 1>& Hv) {
-    if (lane < 16 * NC) {
-      const int wr = lane / (4 * NC), hc = (lane % (4 * NC)) / NC, c = lane % NC;
-      s_rho[rslot(r0 + wr)][c][hc < 2 ? hc : kW + hc] = Hv.density(p.sh, 0, c);
+  // densities of the four halo columns of virtual row r from the staged halo
+  // words: lane hc * NC + c sums its nine values in direction order
+  auto put_rho_halo = [&](int r, const char* st) {
+    if (lane < 4 * NC) {
+      const int hc = lane / NC, c = lane % NC;
+      const int hx = wrap_mod(x0 + (hc < 2 ? hc - 2 : kW + hc - 2), p.nx);
+      T v[9], led = T(0);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        const uint32_t wbits = *reinterpret_cast<const uint32_t*>(st + G::kHaloOff + 4 * (lane * 9 + i));
+        const T raw = word_value<S>(wbits, i, (wrap_add(hx, -L::cx(i), p.nx) & 1) != 0);
+        led = i == 0 ? raw : led + raw;
+        v[i] = decode<S, 2>(p.sh, c, i, raw);
+      }
+      s_rho[rslot(r)][c][hc < 2 ? hc : kW + hc] = site_density<S, 9>(p.sh, c, v, led);
     }
   };
 
@@ -223,134 +298,142 @@ __global__ void __launch_bounds__(256) k_sweep_d2q9(const void* __restrict__ fin
 #pragma unroll
     for (int c = 0; c < NC; ++c) s_h[sh][c][q] = hh[c];
   };
-  // h of rows r0 .. r0+3: each wave its own row's 64 interior columns, the
-  // edge wave the eight edge columns (q = 0 and 65) of all four rows
+  // h of rows r0 .. r0+3: each wave its own row's 64 interior columns, wave 0
+  // the eight edge columns (q = 0 and 65) of all four rows
   auto put_h4 = [&](int r0) {
     put_h(r0 + w, lane + 1);
-    if (w == kEdgeWave && lane < 8) put_h(r0 + (lane >> 1), (lane & 1) ? kHW - 1 : 0);
+    if (w == 0 && lane < 8) put_h(r0 + (lane >> 1), (lane & 1) ? kHW - 1 : 0);
   };
 
-  // F[0]: row collided this round; F[1 .. PF]: rows whose density is formed
-  // in the next rounds (in flight); F[PF + 1]: the row prefetched this round.
-  // Hv[0 .. PF - 1]: halo values of the rows of F[1 .. PF]; Hv[PF] prefetched.
-  Pops<S, NC> F[PF + 2];
-  Pops<S, 1> Hv[PF + 1];
+  // collision of row rc from the populations and ledgers taken one round
+  // earlier; 9 NC stores
+  auto collide_row = [&](int rc, const T (&Fc)[NC][9], const T (&Lc)[NC]) {
+    const int sr = rslot(rc);
+    T rs[NC], jx[NC], jy[NC];
+    T rt = T(0), ux = T(0), uy = T(0);
 #pragma unroll
-  for (int s = 0; s <= PF; ++s) Hv[s].zero();
+    for (int c = 0; c < NC; ++c) {
+      T ax = T(0), ay = T(0);
+#pragma unroll
+      for (int i = 1; i < 9; ++i) {
+        if (L::cx(i)) ax = L::cx(i) > 0 ? ax + Fc[c][i] : ax - Fc[c][i];
+        if (L::cy(i)) ay = L::cy(i) > 0 ? ay + Fc[c][i] : ay - Fc[c][i];
+      }
+      jx[c] = ax;
+      jy[c] = ay;
+      rs[c] = s_rho[sr][c][lane + 2];
+      ux += ax;
+      uy += ay;
+      rt += rs[c];
+    }
+    const T inv_rt = rcp_(rt);
+    ux *= inv_rt;
+    uy *= inv_rt;
+    const int h0 = hslot(rc - 1), h1 = hslot(rc), h2 = hslot(rc + 1);
+    const int r0 = rslot(rc - 1), r2 = rslot(rc + 1);
+    const uint32_t orow = (uint32_t(rc) * uint32_t(p.nbx) + uint32_t(x0 >> 6)) * uint32_t(NC * B::kComp);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      T Ax, Ay, Az;
+      lattice_force<2, T>(
+          [&](int i) {
+            const int sy = L::cy(i) > 0 ? h2 : (L::cy(i) < 0 ? h0 : h1);
+            return s_h[sy][c][lane + 1 + L::cx(i)];
+          },
+          [&](int i) {
+            const int sy = L::cy(i) > 0 ? r2 : (L::cy(i) < 0 ? r0 : sr);
+            return s_rho[sy][c][lane + 2 + L::cx(i)];
+          },
+          rs[c], p, Ax, Ay, Az);
+      const T inv_rs = rcp_(rs[c]);
+      T f[9];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) f[i] = Fc[c][i];
+      collide<2, T>(f, rs[c], ux, uy, T(0), Ax, Ay, Az, jx[c] * inv_rs, jy[c] * inv_rs, T(0), p.inv_tau);
+      char* const outc = static_cast<char*>(fout) + B::run(c, 0);
+      const uint32_t own_rest = orow + B::in_run(0, lane), own_move = orow + B::in_run(1, lane);
+      if constexpr (S::kShift) {
+        // FP16 deviations of the moving populations; the ledger keeps the rest
+        T rest = Lc[c];
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+          const _Float16 d = encode_move<2>(p.sh, c, i, f[i]);
+          rest -= float(d);
+          __builtin_nontemporal_store(d,
+                                      reinterpret_cast<_Float16*>(outc + (own_move + (B::run(c, i) - B::run(c, 0)))));
+        }
+        __builtin_nontemporal_store(rest, reinterpret_cast<float*>(outc + own_rest));
+      } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+          __builtin_nontemporal_store(f[i], reinterpret_cast<T*>(outc + ((i == 0 ? own_rest : own_move) +
+                                                                        (B::run(c, i) - B::run(c, 0)))));
+      }
+    }
+  };
+
+  T F0[NC][9], L0[NC], F1[NC][9], L1[NC];
+  char* const stage = s_stage[w];
+  const Gather<NC> gat = make_gather<S, NC>(p, lane, x0);
 
   // ---- prologue --------------------------------------------------------
   // rho of rows ya-2, ya-1 (waves 2, 3) and ya .. ya+3 (all waves); h of rows
-  // ya-1 .. ya+2; populations of row ya + w (collided in round 0) in F[0] and
-  // of rows ya + 4j + w, j = 1 .. PF, in flight.
-  if (w >= 2) load_row<S, NC>(fin, p, x, wrap_mod(ya - 4 + w, ny), F[1]);
-  if (w == kHaloWave) load_halo4<S, NC>(fin, p, lane, x0, ya - 4, Hv[0]);
-  if (w >= 2) put_rho(ya - 4 + w, F[1]);
-  if (w == kHaloWave) put_rho_halo(ya - 4, Hv[0]);
-  load_row<S, NC>(fin, p, x, wrap_mod(ya + w, ny), F[0]);
-  if (w == kHaloWave) load_halo4<S, NC>(fin, p, lane, x0, ya, Hv[0]);
-  put_rho(ya + w, F[0]);
-  if (w == kHaloWave) put_rho_halo(ya, Hv[0]);
-  __syncthreads();
-  put_h4(ya - 1);
-  __syncthreads();
-#pragma unroll
-  for (int j = 1; j <= PF; ++j) {
-    load_row<S, NC>(fin, p, x, wrap_mod(ya + 4 * j + w, ny), F[j]);
-    if (w == kHaloWave) load_halo4<S, NC>(fin, p, lane, x0, ya + 4 * j, Hv[j - 1]);
+  // ya-1 .. ya+2; populations of row ya + w in F0; row ya + 4 + w staged.
+  if (w >= 2) {
+    stage_row<S, NC>(fin, p, gat, lane, x0, wrap_mod(ya - 4 + w, ny), stage);
+    wait_vm<0>();
+    take(stage, F1, L1);
+    put_rho(ya - 4 + w, F1, L1);
+    put_rho_halo(ya - 4 + w, stage);
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // the slot is read before it is staged again
   }
+  stage_row<S, NC>(fin, p, gat, lane, x0, wrap_mod(ya + w, ny), stage);
+  wait_vm<0>();
+  take(stage, F0, L0);
+  put_rho(ya + w, F0, L0);
+  put_rho_halo(ya + w, stage);
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  stage_row<S, NC>(fin, p, gat, lane, x0, wrap_mod(ya + 4 + w, ny), stage);
+  lds_barrier();
+  put_h4(ya - 1);
+  lds_barrier();
 
   // ---- rounds ------------------------------------------------------------
-  for (int k = 0; k < rounds; ++k) {
-    const int rc = ya + 4 * k + w;  // row collided by this wave
-    const int ra = rc + 4;          // row whose density is formed this round
-    put_rho(ra, F[1]);
-    if (w == kHaloWave) put_rho_halo(ya + 4 * k + 4, Hv[0]);
-    __syncthreads();
+  // Round k collides row rc = ya + 4k + w from Fc and takes row ra = rc + 4
+  // into Fn.
+  auto round = [&](int k, T (&Fc)[NC][9], T (&Lc)[NC], T (&Fn)[NC][9], T (&Ln)[NC]) {
+    const int rc = ya + 4 * k + w;
+    const int ra = rc + 4;
+    wait_vm<0>();  // the row staged in the round before has landed
+    take(stage, Fn, Ln);
+    put_rho(ra, Fn, Ln);
+    put_rho_halo(ra, stage);
+    if (k + 1 < rounds) {
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // the slot is read before it is staged again
+      stage_row<S, NC>(fin, p, gat, lane, x0, wrap_mod(ra + 4, ny), stage);
+    }
+    lds_barrier();
     put_h4(ya + 4 * k + 3);
-    __syncthreads();
-    if (k + PF < rounds) {
-      load_row<S, NC>(fin, p, x, wrap_mod(ra + 4 * PF, ny), F[PF + 1]);
-      if (w == kHaloWave) load_halo4<S, NC>(fin, p, lane, x0, ya + 4 * k + 4 + 4 * PF, Hv[PF]);
-    }
-    if (rc < yb) {
-      const int sr = rslot(rc);
-      T rs[NC], jx[NC], jy[NC];
-      T rt = T(0), ux = T(0), uy = T(0);
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        T f[9], ledger;
-        F[0].decode(p.sh, c, f, ledger);
-        T ax = T(0), ay = T(0);
-#pragma unroll
-        for (int i = 1; i < 9; ++i) {
-          if (L::cx(i)) ax += T(L::cx(i)) * f[i];
-          if (L::cy(i)) ay += T(L::cy(i)) * f[i];
-        }
-        jx[c] = ax;
-        jy[c] = ay;
-        rs[c] = s_rho[sr][c][lane + 2];
-        ux += ax;
-        uy += ay;
-        rt += rs[c];
-      }
-      const T inv_rt = rcp_(rt);
-      ux *= inv_rt;
-      uy *= inv_rt;
-      const int h0 = hslot(rc - 1), h1 = hslot(rc), h2 = hslot(rc + 1);
-      const int r0 = rslot(rc - 1), r2 = rslot(rc + 1);
-      char* own = static_cast<char*>(fout) + blk_off<S, NC>(p.nbx, x, rc);
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        T Ax, Ay, Az;
-        lattice_force<2, T>(
-            [&](int i) {
-              const int sy = L::cy(i) > 0 ? h2 : (L::cy(i) < 0 ? h0 : h1);
-              return s_h[sy][c][lane + 1 + L::cx(i)];
-            },
-            [&](int i) {
-              const int sy = L::cy(i) > 0 ? r2 : (L::cy(i) < 0 ? r0 : sr);
-              return s_rho[sy][c][lane + 2 + L::cx(i)];
-            },
-            rs[c], p, Ax, Ay, Az);
-        const T inv_rs = rcp_(rs[c]);
-        T f[9], ledger;
-        F[0].decode(p.sh, c, f, ledger);
-        collide<2, T>(f, rs[c], ux, uy, T(0), Ax, Ay, Az, jx[c] * inv_rs, jy[c] * inv_rs, T(0), p.inv_tau);
-        if constexpr (S::kShift) {
-          // FP16 deviations of the moving populations; the ledger keeps the rest
-          T rest = ledger;
-#pragma unroll
-          for (int i = 1; i < 9; ++i) {
-            const _Float16 d = encode_move<2>(p.sh, c, i, f[i]);
-            rest -= float(d);
-            __builtin_nontemporal_store(d, reinterpret_cast<_Float16*>(own + B::run(c, i) + B::in_run(i, x)));
-          }
-          __builtin_nontemporal_store(rest, reinterpret_cast<float*>(own + B::run(c, 0) + B::in_run(0, x)));
-        } else {
-#pragma unroll
-          for (int i = 0; i < 9; ++i)
-            __builtin_nontemporal_store(f[i], reinterpret_cast<T*>(own + B::run(c, i) + B::in_run(i, x)));
-        }
-      }
-    }
-    // rotate the register sets (moves; the rotation is not renamed by unrolling
-    // because that needs more registers than one occupancy step allows)
-#pragma unroll
-    for (int s = 0; s <= PF; ++s) F[s] = F[s + 1];
-#pragma unroll
-    for (int s = 0; s < PF; ++s) Hv[s] = Hv[s + 1];
+    lds_barrier();
+    if (rc < yb) collide_row(rc, Fc, Lc);
+  };
+  int k = 0;
+  for (; k + 1 < rounds; k += 2) {
+    round(k, F0, L0, F1, L1);
+    round(k + 1, F1, L1, F0, L0);
   }
+  if (k < rounds) round(k, F0, L0, F1, L1);
 }
 
 }  // namespace sweep
 
-// Rows per segment: about one workgroup per resident slot (three per CU on
-// 256 CUs), rounded up to whole rounds of four rows, so the grid runs in one
-// wave of workgroups and the four rows re-read per segment stay a small
-// fraction of it.
-static int sweep_rows(int nx, int ny) {
+// Rows per segment: about one workgroup per resident slot (as many per CU as
+// their LDS allows, on 256 CUs), rounded up to whole rounds of four rows, so
+// the grid runs in one wave of workgroups and the rows re-read at segment
+// ends stay a small fraction of it.
+static int sweep_rows(int nx, int ny, int groups_per_cu) {
   const int strips = nx / 64;
-  const int slots = 3 * 256;
+  const int slots = groups_per_cu * 256;
   const int segs = (slots + strips - 1) / strips;
   int rows = (ny + segs - 1) / segs;
   rows = (rows + 3) / 4 * 4;
@@ -361,11 +444,11 @@ template <class S, int NC>
 static void launch_sweep(const Ctx& c, const void* fin, void* fout) {
   const Params<float>& p = c.params<float>();
   const int strips = p.nx / 64;
-  const int rows = sweep_rows(p.nx, p.ny);
+  const int rows = sweep_rows(p.nx, p.ny, sweep::sweep_groups_per_cu<S, NC>());
   const int ntiles = strips * ((p.ny + rows - 1) / rows);
   const int per_xcd = (ntiles + sweep::kXcds - 1) / sweep::kXcds;
-  sweep::k_sweep_d2q9<S, NC, 1><<<per_xcd * sweep::kXcds, 256, 0, c.stream>>>(fin, fout, p, strips, rows, ntiles,
-                                                                              per_xcd);
+  sweep::k_sweep_d2q9<S, NC><<<per_xcd * sweep::kXcds, 256, 0, c.stream>>>(fin, fout, p, strips, rows, ntiles,
+                                                                           per_xcd);
 }
 
 template <class S>
@@ -379,8 +462,8 @@ static FusedStepFn sweep_for_n(int n_comp) {
   }
 }
 
-// FP32 and shifted FP16 only: three rows of FP64 populations exceed the
-// register budget.
+// FP32 and shifted FP16 only: FP64 would halve the rows that fit in LDS and
+// registers.
 FusedStepFn sweep_step_for(int storage, int n_comp) {
   if (storage == StoreF32::kId) return sweep_for_n<StoreF32>(n_comp);
   if (storage == StoreF16S::kId) return sweep_for_n<StoreF16S>(n_comp);

@@ -62,6 +62,12 @@ __device__ __forceinline__ double ln_(double x) { return log(x); }
 __device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double rcp_(double x) { return 1.0 / x; }
 
+// Fused multiply-add.  The library is compiled without automatic
+// contraction, so every rounding is the one written here: each kernel that
+// evaluates these functions gets the same bits whatever the code around it.
+__device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // Potential that the force differentiates, at one site:
 //   mu^s = theta [ -1 + (1 + ln phi^s)/m^s - sum_t phi^t/m^t
 //                  + sum_t chi^{st} phi^t - 1/2 sum_{t,t'} chi^{tt'} phi^t phi^t' ]
@@ -83,7 +89,7 @@ __device__ __forceinline__ void site_potential(const Params<T>& p, const T (&rho
 #pragma unroll
   for (int s = 0; s < NC; ++s) {
     phi[s] = s < n ? rho[s] * inv_rt : T(0);
-    sum_phi_m += phi[s] * p.inv_m[s];
+    sum_phi_m = fma_(phi[s], p.inv_m[s], sum_phi_m);
   }
   T lin[NC];
   T quad = T(0);
@@ -91,18 +97,18 @@ __device__ __forceinline__ void site_potential(const Params<T>& p, const T (&rho
   for (int s = 0; s < NC; ++s) {
     T acc = T(0);
 #pragma unroll
-    for (int t = 0; t < NC; ++t) acc += p.chi[s * kMaxComp + t] * phi[t];
+    for (int t = 0; t < NC; ++t) acc = fma_(p.chi[s * kMaxComp + t], phi[t], acc);
     lin[s] = acc;
-    quad += phi[s] * acc;
+    quad = fma_(phi[s], acc, quad);
   }
 #pragma unroll
   for (int s = 0; s < NC; ++s) {
     if (s < n) {
       const T ln_rs = ln_(rho[s]);
       const T ln_phi = ln_rs - ln_rt;
-      const T bulk = T(-1) + (T(1) + ln_phi) * p.inv_m[s] - sum_phi_m + lin[s] - T(0.5) * quad;
-      mu[s] = p.theta * bulk - p.kappa * lap[s];
-      h[s] = p.log_form ? mu[s] - ln_rs * T(1.0 / 3.0) : mu[s];
+      const T bulk = fma_(T(-0.5), quad, (fma_(T(1) + ln_phi, p.inv_m[s], T(-1)) - sum_phi_m) + lin[s]);
+      mu[s] = fma_(p.theta, bulk, -(p.kappa * lap[s]));
+      h[s] = p.log_form ? fma_(ln_rs, T(-1.0 / 3.0), mu[s]) : mu[s];
     } else {
       mu[s] = T(0);
       h[s] = T(0);
@@ -135,11 +141,13 @@ __device__ __forceinline__ T site_psi(const Params<T>& p, const T (&rho)[NC]) {
 }
 
 // BGK collision of one component at one site, Eq. (ssLB):
-//   f*_i = f_i + (f^e_i - f_i)/tau + F_i
+//   f*_i = f_i + (f^e_i - f_i)/tau + F_i = (1 - 1/tau) f_i + G_i,
+//   G_i   = f^e_i / tau + F_i,
 //   f^e_i = w_i rho [1 + 3 v.u + 9/2 (v.u)^2 - 3/2 u.u]      (barycentric u)
 //   F_i   = w_i [3 v.A + 9 (v.A)(v.us) - 3 A.us]            (us = j / rho)
 // Opposite velocities share the even parts of f^e and F and flip the odd
-// ones, so each pair (i, opp(i)) is formed together.
+// ones, so each pair (i, opp(i)) forms G_e + G_o and G_e - G_o; products of
+// the weight with per-site quantities are formed once per weight value.
 // The zeroth moments of f^e and F (rho and 0) fix the rest population:
 //   f*_0 = f_0 + sum_{i>0} (f_i - f*_i).
 // Written this way the stored populations keep their exact sum up to the
@@ -147,30 +155,48 @@ __device__ __forceinline__ T site_psi(const Params<T>& p, const T (&rho)[NC]) {
 // values lie within a factor two of each other), whereas forming f^e_0 and
 // F_0 separately lets biased roundings of the FP32 density sum drift the
 // mass by ~1e-8 per step.
+// v_i . (x, y, z) with the lattice's integer components folded in.
+template <int LAT, typename T>
+__device__ __forceinline__ T vdot(int i, T x, T y, T z) {
+  using L = Lattice<LAT>;
+  T r = T(0);
+  bool any = false;
+  if (L::cx(i)) { r = L::cx(i) > 0 ? x : -x; any = true; }
+  if (L::cy(i)) { r = any ? (L::cy(i) > 0 ? r + y : r - y) : (L::cy(i) > 0 ? y : -y); any = true; }
+  if (L::cz(i)) { r = any ? (L::cz(i) > 0 ? r + z : r - z) : (L::cz(i) > 0 ? z : -z); }
+  return r;
+}
+
 template <int LAT, typename T>
 __device__ __forceinline__ void collide(T (&f)[Lattice<LAT>::Q], T rho, T ux, T uy, T uz, T Ax,
                                         T Ay, T Az, T usx, T usy, T usz, T inv_tau) {
   using L = Lattice<LAT>;
   constexpr int Q = L::Q;
-  const T uu = ux * ux + uy * uy + uz * uz;
-  const T Aus = Ax * usx + Ay * usy + Az * usz;
-  const T base = T(1) - T(1.5) * uu;
+  const T keep = T(1) - inv_tau;
+  const T uu = L::D == 3 ? fma_(uz, uz, fma_(uy, uy, ux * ux)) : (L::D == 2 ? fma_(uy, uy, ux * ux) : ux * ux);
+  const T Aus = L::D == 3 ? fma_(Az, usz, fma_(Ay, usy, Ax * usx)) : (L::D == 2 ? fma_(Ay, usy, Ax * usx) : Ax * usx);
+  const T base = fma_(T(-1.5), uu, T(1));
   T defect = T(0);
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
     if (L::opp(i) < i) continue;
     const int j = L::opp(i);
+    // per weight value (the compiler forms these once per distinct w)
     const T w = T(L::w(i));
     const T wr = w * rho;
-    const T vu = T(L::cx(i)) * ux + T(L::cy(i)) * uy + T(L::cz(i)) * uz;
-    const T vA = T(L::cx(i)) * Ax + T(L::cy(i)) * Ay + T(L::cz(i)) * Az;
-    const T vus = T(L::cx(i)) * usx + T(L::cy(i)) * usy + T(L::cz(i)) * usz;
-    const T e_even = wr * (base + T(4.5) * vu * vu);
-    const T e_odd = wr * (T(3) * vu);
-    const T F_even = w * (T(9) * vA * vus - T(3) * Aus);
-    const T F_odd = w * (T(3) * vA);
-    const T post_i = f[i] + inv_tau * ((e_even + e_odd) - f[i]) + (F_even + F_odd);
-    const T post_j = f[j] + inv_tau * ((e_even - e_odd) - f[j]) + (F_even - F_odd);
+    const T e_even0 = wr * base, e_even2 = wr * T(4.5), e_odd1 = wr * T(3);
+    const T F_even0 = T(-3.0 * L::w(i)) * Aus;
+    const T vu = vdot<LAT, T>(i, ux, uy, uz);
+    const T vA = vdot<LAT, T>(i, Ax, Ay, Az);
+    const T vus = vdot<LAT, T>(i, usx, usy, usz);
+    const T e_even = fma_(e_even2, vu * vu, e_even0);
+    const T e_odd = e_odd1 * vu;
+    const T F_even = fma_(T(9.0 * L::w(i)) * vA, vus, F_even0);
+    const T F_odd = T(3.0 * L::w(i)) * vA;
+    const T G_even = fma_(inv_tau, e_even, F_even);
+    const T G_odd = fma_(inv_tau, e_odd, F_odd);
+    const T post_i = fma_(keep, f[i], G_even + G_odd);
+    const T post_j = fma_(keep, f[j], G_even - G_odd);
     defect += f[i] - post_i;
     defect += f[j] - post_j;
     f[i] = post_i;
@@ -188,7 +214,7 @@ __device__ __forceinline__ T lattice_laplacian(const G& g, T g0) {
   using L = Lattice<LAT>;
   T acc = T(0);
 #pragma unroll
-  for (int i = 1; i < L::Q; ++i) acc += T(L::w(i)) * (g(i) - g0);
+  for (int i = 1; i < L::Q; ++i) acc = fma_(T(L::w(i)), g(i) - g0, acc);
   return T(6) * acc;
 }
 
@@ -200,9 +226,9 @@ __device__ __forceinline__ void lattice_wsum(const G& g, T& sx, T& sy, T& sz) {
 #pragma unroll
   for (int i = 1; i < L::Q; ++i) {
     const T v = g(i);
-    if (L::cx(i)) sx += T(L::cx(i) * L::w(i)) * v;
-    if (L::cy(i)) sy += T(L::cy(i) * L::w(i)) * v;
-    if (L::cz(i)) sz += T(L::cz(i) * L::w(i)) * v;
+    if (L::cx(i)) sx = fma_(T(L::cx(i) * L::w(i)), v, sx);
+    if (L::cy(i)) sy = fma_(T(L::cy(i) * L::w(i)), v, sy);
+    if (L::cz(i)) sz = fma_(T(L::cz(i) * L::w(i)), v, sz);
   }
 }
 
@@ -217,9 +243,9 @@ __device__ __forceinline__ void lattice_force(const GH& h, const GR& r, T rho_s,
   lattice_wsum<LAT, T>(h, hx, hy, hz);
   T qx = T(0), qy = T(0), qz = T(0);
   if (!p.log_form) lattice_wsum<LAT, T>(r, qx, qy, qz);
-  Ax = -p.cforce * (rho_s * (T(3) * hx) - qx);
-  Ay = -p.cforce * (rho_s * (T(3) * hy) - qy);
-  Az = -p.cforce * (rho_s * (T(3) * hz) - qz);
+  Ax = -p.cforce * fma_(rho_s, T(3) * hx, -qx);
+  Ay = -p.cforce * fma_(rho_s, T(3) * hy, -qy);
+  Az = -p.cforce * fma_(rho_s, T(3) * hz, -qz);
 }
 
 constexpr int kBlockX = 64;

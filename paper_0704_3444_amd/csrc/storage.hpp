@@ -23,8 +23,11 @@
 // Block layout (all codecs): sites are grouped in blocks of 64 consecutive
 // x on one row (row = y + ny z).  A block stores, for each component, the
 // rest run (64 Rest values) followed by the Q - 1 moving runs (64 Move
-// values each).  For F64 and F32 this is N*Q runs of 64 values in the order
-// q = sigma * Q + i.
+// values each), in the run order run_slot(i).  On D2Q9 the runs are grouped
+// by the y component of the velocity, v_y = 0 (i = 0, 1, 3), +1 (2, 5, 6),
+// -1 (4, 7, 8): the populations that one row pulls from each of its three
+// source rows are then one contiguous piece of that row's block per
+// component.  Other lattices keep the order of the velocity table.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -57,6 +60,17 @@ struct StoreF16S {
   static constexpr int kId = 2;
 };
 
+// Position of velocity i in a component's run order.
+template <int Q>
+__host__ __device__ constexpr int run_slot(int i) {
+  if constexpr (Q == 9) {
+    constexpr int slot[9] = {0, 1, 3, 2, 6, 4, 5, 7, 8};  // 0 1 3 | 2 5 6 | 4 7 8
+    return slot[i];
+  } else {
+    return i;
+  }
+}
+
 template <class S, int Q>
 struct BlockLayout {
   static constexpr uint32_t kRest = sizeof(typename S::Rest);
@@ -65,7 +79,7 @@ struct BlockLayout {
   static constexpr uint32_t kComp = kBlockX * (kRest + (Q - 1) * kMove);
   // offset of the run of population i of component c inside a block
   static constexpr uint32_t run(int c, int i) {
-    return uint32_t(c) * kComp + (i == 0 ? 0u : kBlockX * (kRest + uint32_t(i - 1) * kMove));
+    return uint32_t(c) * kComp + (i == 0 ? 0u : kBlockX * (kRest + uint32_t(run_slot<Q>(i) - 1) * kMove));
   }
   // offset of site x within its run
   static constexpr uint32_t in_run(int i, int x) { return uint32_t(x & (kBlockX - 1)) * (i == 0 ? kRest : kMove); }
