@@ -13,8 +13,10 @@
 //      the three runs that row pulls from each source row are one
 //      contiguous, aligned piece of that row's block (the block layout
 //      groups the runs by v_y), three 16-byte-per-lane loads per component,
-//      plus the few values from the neighbouring strips (the x shift of
-//      lanes 0 and 63 and the four density-halo columns);
+//      plus, for every run, the aligned 16 bytes at the end of the left
+//      neighbour's run and at the start of the right neighbour's (the x
+//      shift of lanes 0 and 63 and the four density-halo columns read
+//      three columns on either side);
 //   3. (barrier) chemical potentials and the potential h of its row into an
 //      LDS ring (wave 0 also the eight edge columns of the four rows);
 //   4. (barrier) force, equilibrium, forcing term and collision of the row
@@ -44,7 +46,6 @@ constexpr int kHRing = 8;     // rows of h in LDS (8 live; written only between 
 constexpr int kW = 64;        // strip width = block width = wave size
 constexpr int kRW = kW + 4;   // rho row: columns x0 - 2 .. x0 + 65
 constexpr int kHW = kW + 2;   // h row:   columns x0 - 1 .. x0 + 64
-constexpr int kLdsBytes = 163840;
 
 __device__ __forceinline__ int wrap_mod(int v, int n) {
   int r = v % n;
@@ -65,84 +66,51 @@ __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(
 
 // Staged row: per component the nine runs of the pulled populations in the
 // block's run order (v_y groups 0 | +1 | -1, each from its source row), then
-// the edge words (per component lane 0's three v_x = +1 populations from
-// column x0 - 1 and lane 63's three v_x = -1 populations from column x0 + 64),
-// then the halo words (the nine populations pulled into each of the columns
-// x0-2, x0-1, x0+64, x0+65, per component).  A word of shifted FP16 storage
-// holds the FP16 values of an even/odd column pair; the parity of the
-// source column selects the half.
+// the halo pieces: for each run (c, i), from the same source row, the last
+// 16 bytes of the left neighbour block's run (columns x0 - 16/e .. x0 - 1,
+// e the slot size) and the first 16 bytes of the right neighbour block's
+// run (columns x0 + 64 .. x0 + 63 + 16/e); piece (c, i, side) at
+// kHaloOff + 16 ((9 c + i) 2 + side).
 template <class S, int NC>
 struct Staged {
   using B = BlockLayout<S, 9>;
   static constexpr uint32_t kGroup0 = kW * (B::kRest + 2 * B::kMove);  // v_y = 0: i = 0, 1, 3
   static constexpr uint32_t kGroup1 = kW * 3 * B::kMove;               // v_y = +-1: 2, 5, 6 / 4, 7, 8
   static constexpr uint32_t kMain = NC * B::kComp;
-  static constexpr int kEdge = 6 * NC;
-  static constexpr int kHalo = 36 * NC;
-  static constexpr int kHaloLoads = (kHalo + 63) / 64;
-  static constexpr uint32_t kEdgeOff = kMain;
-  static constexpr uint32_t kHaloOff = kMain + 4 * kEdge;
-  static constexpr uint32_t kBytes = (kHaloOff + 4 * kHalo + 15) / 16 * 16;
-  static constexpr int kLoads = 3 * NC + 1 + kHaloLoads;  // direct loads per staged row
+  static constexpr int kPieces = 18 * NC;
+  static constexpr int kHaloLoads = (kPieces + 63) / 64;
+  static constexpr uint32_t kHaloOff = kMain;
+  static constexpr uint32_t kBytes = kHaloOff + 16 * kPieces;
+  static constexpr int kLoads = 3 * NC + kHaloLoads;  // direct loads per staged row
   static_assert(kGroup0 % 16 == 0 && kGroup1 % 16 == 0 && kGroup0 <= 1024 && kGroup1 <= 1024, "group size");
+  static_assert(kMain % 16 == 0, "halo pieces aligned");
 };
 
-// LDS bytes of one workgroup and workgroups per CU that LDS allows.
-template <class S, int NC>
-constexpr int sweep_lds() {
-  return int(sizeof(float)) * NC * (kRhoRing * kRW + kHRing * kHW) + 4 * int(Staged<S, NC>::kBytes);
-}
-template <class S, int NC>
-constexpr int sweep_groups_per_cu() {
-  return kLdsBytes / sweep_lds<S, NC>();
-}
 
-// Edge entry k (0..5) of a component: v_x = +1 velocities 1, 5, 8 (column
-// x0 - 1), then v_x = -1 velocities 3, 6, 7 (column x0 + 64).
-__device__ __forceinline__ int edge_dir(int k) {
-  return k == 0 ? 1 : k == 1 ? 5 : k == 2 ? 8 : k == 3 ? 3 : k == 4 ? 6 : 7;
-}
-__host__ __device__ constexpr int edge_entry(int i) {
-  return i == 1 ? 0 : i == 5 ? 1 : i == 8 ? 2 : i == 3 ? 3 : i == 6 ? 4 : 5;
-}
-
-// Byte offset, without the row part, of the 32-bit word that holds slot i
-// of component c in column sx.
-template <class S, int NC>
-__device__ __forceinline__ uint32_t word_col(int c, int i, int sx) {
-  using B = BlockLayout<S, 9>;
-  return (uint32_t(sx >> 6) * uint32_t(NC * B::kComp) + B::run(c, i) + B::in_run(i, sx)) & ~3u;
-}
-
-// Per-lane parts of the edge and halo words that do not change along the
-// sweep: the column part of the byte offset and which source row (v_y = +1:
-// the row above, 0: the row itself, -1: the row below) the word comes from.
+// Per-lane parts of the halo pieces that do not change along the sweep:
+// the column part of the piece's byte offset and which source row (v_y =
+// +1: the row above, 0: the row itself, -1: the row below) it comes from.
 template <int NC>
 struct Gather {
-  uint32_t col[1 + (36 * NC + 63) / 64];
-  int dy[1 + (36 * NC + 63) / 64];
+  uint32_t col[(18 * NC + 63) / 64];
+  int dy[(18 * NC + 63) / 64];
 };
 
 template <class S, int NC>
 __device__ __forceinline__ Gather<NC> make_gather(const Params<float>& p, int lane, int x0) {
   using L = Lattice<2>;
+  using B = BlockLayout<S, 9>;
   using G = Staged<S, NC>;
   Gather<NC> g;
-  {  // edge words: lane e = 6 c + k
-    const int e = lane < G::kEdge ? lane : 0;
-    const int c = e / 6, k = e % 6, i = edge_dir(k);
-    const int sx = k < 3 ? wrap_add(x0, -1, p.nx) : wrap_add(x0 + kW - 1, 1, p.nx);
-    g.col[0] = word_col<S, NC>(c, i, sx);
-    g.dy[0] = L::cy(i);
-  }
 #pragma unroll
-  for (int j = 0; j < G::kHaloLoads; ++j) {  // halo words: value v = (hc NC + c) 9 + i
-    const int v0 = j * 64 + lane;
-    const int v = v0 < G::kHalo ? v0 : 0;
-    const int hc = v / (9 * NC), c = (v / 9) % NC, i = v % 9;
-    const int hx = wrap_mod(x0 + (hc < 2 ? hc - 2 : kW + hc - 2), p.nx);
-    g.col[1 + j] = word_col<S, NC>(c, i, wrap_add(hx, -L::cx(i), p.nx));
-    g.dy[1 + j] = L::cy(i);
+  for (int j = 0; j < G::kHaloLoads; ++j) {  // piece e = (9 c + i) 2 + side
+    const int e0 = j * 64 + lane;
+    const int e = e0 < G::kPieces ? e0 : 0;
+    const int c = e / 18, i = (e / 2) % 9, side = e & 1;
+    const int bx = side == 0 ? wrap_add(x0, -1, p.nx) : wrap_add(x0 + kW - 1, 1, p.nx);  // neighbour block
+    const uint32_t run_bytes = kW * (i == 0 ? B::kRest : B::kMove);
+    g.col[j] = uint32_t(bx >> 6) * uint32_t(NC * B::kComp) + B::run(c, i) + (side == 0 ? run_bytes - 16u : 0u);
+    g.dy[j] = L::cy(i);
   }
   return g;
 }
@@ -172,27 +140,26 @@ __device__ __forceinline__ void stage_row(const char* __restrict__ fin, const Pa
         __builtin_amdgcn_global_load_lds(src, dst + B::run(c, first[g3]), 16, 0, 0);
     }
   }
-  auto row_of = [&](int dy) { return dy > 0 ? rowu : (dy < 0 ? rowd : row0); };
-  if (lane < G::kEdge)
-    __builtin_amdgcn_global_load_lds(fin + (row_of(g.dy[0]) + g.col[0]), dst + G::kEdgeOff, 4, 0, 0);
 #pragma unroll
-  for (int j = 0; j < G::kHaloLoads; ++j)
-    if (j * 64 + lane < G::kHalo)
-      __builtin_amdgcn_global_load_lds(fin + (row_of(g.dy[1 + j]) + g.col[1 + j]), dst + G::kHaloOff + 256 * j, 4,
-                                       0, 0);
+  for (int j = 0; j < G::kHaloLoads; ++j) {
+    const uint32_t row = g.dy[j] > 0 ? rowu : (g.dy[j] < 0 ? rowd : row0);
+    if (j * 64 + lane < G::kPieces)
+      __builtin_amdgcn_global_load_lds(fin + (row + g.col[j]), dst + G::kHaloOff + 1024 * j, 16, 0, 0);
+  }
 }
 
-// Raw value of slot i from a staged word: the word itself, or for moving
-// slots of shifted FP16 storage the half of the given column parity.
-template <class S>
-__device__ __forceinline__ float word_value(uint32_t wbits, int i, bool odd) {
-  if constexpr (S::kShift) {
-    if (i == 0) return __builtin_bit_cast(float, wbits);
-    const uint16_t h = uint16_t(odd ? (wbits >> 16) : (wbits & 0xffffu));
-    return float(__builtin_bit_cast(_Float16, h));
-  } else {
-    return __builtin_bit_cast(float, wbits);
-  }
+// LDS byte offset of slot i of component c in relative column col (-16/e ..
+// 63 + 16/e, e the slot size) of a staged row: the main runs for 0 .. 63,
+// the halo pieces outside.
+template <class S, int NC>
+__device__ __forceinline__ uint32_t staged_off(int c, int i, int col) {
+  using B = BlockLayout<S, 9>;
+  using G = Staged<S, NC>;
+  const uint32_t e = i == 0 ? B::kRest : B::kMove;
+  const int per = int(16 / e);  // columns per halo piece
+  if (col < 0) return G::kHaloOff + 16u * uint32_t((9 * c + i) * 2) + uint32_t(col + per) * e;
+  if (col >= kW) return G::kHaloOff + 16u * uint32_t((9 * c + i) * 2 + 1) + uint32_t(col - kW) * e;
+  return B::run(c, i) + uint32_t(col) * e;
 }
 
 template <class S>
@@ -243,9 +210,8 @@ __global__ void __launch_bounds__(256) k_sweep_d2q9(const void* __restrict__ fin
       for (int i = 0; i < 9; ++i) {
         const int col = L::cx(i) > 0 ? lm : (L::cx(i) < 0 ? lp : lane);
         T raw = lds_raw<S>(st + B::run(c, i) + B::in_run(i, col), i);
-        if (L::cx(i) != 0) {
-          const uint32_t wbits = *reinterpret_cast<const uint32_t*>(st + G::kEdgeOff + 4 * (6 * c + edge_entry(i)));
-          const T e = word_value<S>(wbits, i, L::cx(i) > 0);  // column x0 - 1 is odd, x0 + 64 even
+        if (L::cx(i) != 0) {  // lane 0 pulls from column -1, lane 63 from column 64
+          const T e = lds_raw<S>(st + staged_off<S, NC>(c, i, L::cx(i) > 0 ? -1 : kW), i);
           raw = (L::cx(i) > 0 ? lane == 0 : lane == kW - 1) ? e : raw;
         }
         led = i == 0 ? raw : led + raw;
@@ -260,17 +226,16 @@ __global__ void __launch_bounds__(256) k_sweep_d2q9(const void* __restrict__ fin
 #pragma unroll
     for (int c = 0; c < NC; ++c) s_rho[sr][c][lane + 2] = site_density<S, 9>(p.sh, c, f[c], ledger[c]);
   };
-  // densities of the four halo columns of virtual row r from the staged halo
-  // words: lane hc * NC + c sums its nine values in direction order
+  // densities of the four halo columns (-2, -1, 64, 65) of virtual row r:
+  // lane hc * NC + c sums its nine pulled values in direction order
   auto put_rho_halo = [&](int r, const char* st) {
     if (lane < 4 * NC) {
       const int hc = lane / NC, c = lane % NC;
-      const int hx = wrap_mod(x0 + (hc < 2 ? hc - 2 : kW + hc - 2), p.nx);
+      const int hcol = hc < 2 ? hc - 2 : kW + hc - 2;
       T v[9], led = T(0);
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
-        const uint32_t wbits = *reinterpret_cast<const uint32_t*>(st + G::kHaloOff + 4 * (lane * 9 + i));
-        const T raw = word_value<S>(wbits, i, (wrap_add(hx, -L::cx(i), p.nx) & 1) != 0);
+        const T raw = lds_raw<S>(st + staged_off<S, NC>(c, i, hcol - L::cx(i)), i);
         led = i == 0 ? raw : led + raw;
         v[i] = decode<S, 2>(p.sh, c, i, raw);
       }
@@ -428,23 +393,38 @@ __global__ void __launch_bounds__(256) k_sweep_d2q9(const void* __restrict__ fin
 }  // namespace sweep
 
 // Rows per segment: about one workgroup per resident slot (as many per CU as
-// their LDS allows, on 256 CUs), rounded up to whole rounds of four rows, so
-// the grid runs in one wave of workgroups and the rows re-read at segment
-// ends stay a small fraction of it.
-static int sweep_rows(int nx, int ny, int groups_per_cu) {
+// registers and LDS allow), rounded up to whole rounds of four rows, so the
+// grid runs in one wave of workgroups and the rows re-read at segment ends
+// stay a small fraction of it.
+static int sweep_rows(int nx, int ny, int slots) {
   const int strips = nx / 64;
-  const int slots = groups_per_cu * 256;
   const int segs = (slots + strips - 1) / strips;
   int rows = (ny + segs - 1) / segs;
   rows = (rows + 3) / 4 * 4;
   return rows < 4 ? 4 : rows;
 }
 
+// Resident workgroups of the sweep kernel on the current device.
+template <class S, int NC>
+static int sweep_slots() {
+  static const int slots = [] {
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sweep::k_sweep_d2q9<S, NC>, 256, 0) != hipSuccess ||
+        per_cu < 1)
+      per_cu = 1;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+      cus = 256;
+    return per_cu * cus;
+  }();
+  return slots;
+}
+
 template <class S, int NC>
 static void launch_sweep(const Ctx& c, const void* fin, void* fout) {
   const Params<float>& p = c.params<float>();
   const int strips = p.nx / 64;
-  const int rows = sweep_rows(p.nx, p.ny, sweep::sweep_groups_per_cu<S, NC>());
+  const int rows = sweep_rows(p.nx, p.ny, sweep_slots<S, NC>());
   const int ntiles = strips * ((p.ny + rows - 1) / rows);
   const int per_xcd = (ntiles + sweep::kXcds - 1) / sweep::kXcds;
   sweep::k_sweep_d2q9<S, NC><<<per_xcd * sweep::kXcds, 256, 0, c.stream>>>(fin, fout, p, strips, rows, ntiles,
