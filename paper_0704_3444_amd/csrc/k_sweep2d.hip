@@ -25,8 +25,9 @@
 // Staged rows are private to their wave, so only the two rings need the
 // workgroup barriers; the loads in flight hold no registers.  The compiler
 // does not track direct loads into LDS, so the wave waits for its own
-// staging with an explicit vmcnt(0) (one counter covers loads and stores,
-// which may complete out of order with respect to each other).  Workgroups
+// staging with an explicit vmcnt: one counter covers loads and stores and
+// retires them in issue order, so the wait names how many operations issued
+// after the staging may stay in flight (the stores of the round before).  Workgroups
 // are banded per XCD so that neighbouring strips share L2.
 //
 // The kernel is templated on the storage codec (storage.hpp): FP32, or
@@ -119,9 +120,15 @@ __device__ __forceinline__ Gather<NC> make_gather(const Params<float>& p, int la
 // into the LDS slot `dst` (Staged layout) with exactly Staged::kLoads direct
 // loads (each load has at least one active lane).
 template <class S, int NC>
-__device__ __forceinline__ void stage_row(const char* __restrict__ fin, const Params<float>& p, const Gather<NC>& g,
-                                          int lane, int x0, int r, char* dst) {
+__device__ __forceinline__ void stage_row(const char* fin, const Params<float>& p, const Gather<NC>& g,
+                                          int lane, int x0, int r, char* dst_in) {
   using B = BlockLayout<S, 9>;
+  // The LDS destination is passed through an empty asm statement: the
+  // compiler's own tracking of direct loads into LDS would otherwise add a
+  // vmcnt(0) before reads of the slot, which also waits for the stores the
+  // explicit waits leave in flight.
+  __attribute__((address_space(3))) char* dst = (__attribute__((address_space(3))) char*)dst_in;
+  asm volatile("" : "+s"(dst));
   using G = Staged<S, NC>;
   const uint32_t stride = uint32_t(p.nbx) * uint32_t(NC * B::kComp);
   const uint32_t blk = uint32_t(x0 >> 6) * uint32_t(NC * B::kComp);
@@ -169,7 +176,7 @@ __device__ __forceinline__ float lds_raw(const char* a, int i) {
 }
 
 template <class S, int NC>
-__global__ void __launch_bounds__(256) k_sweep_d2q9(const void* __restrict__ fin_v, void* __restrict__ fout,
+__global__ void __launch_bounds__(256) k_sweep_d2q9(const void* fin_v, void* fout,
                                                     Params<float> p, int strips, int seg_rows, int ntiles,
                                                     int tiles_per_xcd) {
   using L = Lattice<2>;
@@ -179,7 +186,7 @@ __global__ void __launch_bounds__(256) k_sweep_d2q9(const void* __restrict__ fin
   __shared__ T s_rho[kRhoRing][NC][kRW];
   __shared__ T s_h[kHRing][NC][kHW];
   __shared__ __attribute__((aligned(16))) char s_stage[4][G::kBytes];
-  const char* __restrict__ fin = static_cast<const char*>(fin_v);
+  const char* fin = static_cast<const char*>(fin_v);
 
   const int b = blockIdx.x;
   const int t = (b % kXcds) * tiles_per_xcd + b / kXcds;
@@ -199,6 +206,25 @@ __global__ void __launch_bounds__(256) k_sweep_d2q9(const void* __restrict__ fin
   // columns of the lane's pulled slots in a staged row, clamped into the
   // strip; the edge lanes take the edge words instead
   const int lm = lane > 0 ? lane - 1 : 0, lp = lane < kW - 1 ? lane + 1 : kW - 1;
+
+  // Shift reference of the component of a halo lane (lane % NC), picked by
+  // selects and kept in registers: an indexed read of the parameters would
+  // be a vector memory load inside the rounds, whose wait would also wait
+  // for the stores in flight.
+  float halo_ref[3] = {0.f, 0.f, 0.f};
+  if constexpr (S::kShift) {
+    const int c = lane % NC;
+    halo_ref[0] = p.sh.rbar[0];
+    halo_ref[1] = p.sh.scale[0];
+    halo_ref[2] = p.sh.csum[0];
+#pragma unroll
+    for (int q = 1; q < NC; ++q) {
+      halo_ref[0] = c == q ? p.sh.rbar[q] : halo_ref[0];
+      halo_ref[1] = c == q ? p.sh.scale[q] : halo_ref[1];
+      halo_ref[2] = c == q ? p.sh.csum[q] : halo_ref[2];
+    }
+    asm volatile("" : "+v"(halo_ref[0]), "+v"(halo_ref[1]), "+v"(halo_ref[2]));
+  }
 
   // Take a staged row into registers: decoded populations, in direction
   // order, and the ledger of each component (shifted codec).
@@ -228,18 +254,24 @@ __global__ void __launch_bounds__(256) k_sweep_d2q9(const void* __restrict__ fin
   };
   // densities of the four halo columns (-2, -1, 64, 65) of virtual row r:
   // lane hc * NC + c sums its nine pulled values in direction order
+  // (the lane's component varies over the lanes: its shift reference is
+  // the one picked once per lane below, in slot 0 of sh1)
   auto put_rho_halo = [&](int r, const char* st) {
     if (lane < 4 * NC) {
       const int hc = lane / NC, c = lane % NC;
       const int hcol = hc < 2 ? hc - 2 : kW + hc - 2;
+      ShiftRef sh1 = {};
+      sh1.rbar[0] = halo_ref[0];
+      sh1.scale[0] = halo_ref[1];
+      sh1.csum[0] = halo_ref[2];
       T v[9], led = T(0);
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
         const T raw = lds_raw<S>(st + staged_off<S, NC>(c, i, hcol - L::cx(i)), i);
         led = i == 0 ? raw : led + raw;
-        v[i] = decode<S, 2>(p.sh, c, i, raw);
+        v[i] = decode<S, 2>(sh1, 0, i, raw);
       }
-      s_rho[rslot(r)][c][hc < 2 ? hc : kW + hc] = site_density<S, 9>(p.sh, c, v, led);
+      s_rho[rslot(r)][c][hc < 2 ? hc : kW + hc] = site_density<S, 9>(sh1, 0, v, led);
     }
   };
 
@@ -271,8 +303,9 @@ __global__ void __launch_bounds__(256) k_sweep_d2q9(const void* __restrict__ fin
   };
 
   // collision of row rc from the populations and ledgers taken one round
-  // earlier; 9 NC stores
-  auto collide_row = [&](int rc, const T (&Fc)[NC][9], const T (&Lc)[NC]) {
+  // earlier, in place (shifted codec: Fc then holds the stored deviations,
+  // the ledger the stored rest value)
+  auto collide_row = [&](int rc, T (&Fc)[NC][9], T (&Lc)[NC]) {
     const int sr = rslot(rc);
     T rs[NC], jx[NC], jy[NC];
     T rt = T(0), ux = T(0), uy = T(0);
@@ -296,7 +329,6 @@ __global__ void __launch_bounds__(256) k_sweep_d2q9(const void* __restrict__ fin
     uy *= inv_rt;
     const int h0 = hslot(rc - 1), h1 = hslot(rc), h2 = hslot(rc + 1);
     const int r0 = rslot(rc - 1), r2 = rslot(rc + 1);
-    const uint32_t orow = (uint32_t(rc) * uint32_t(p.nbx) + uint32_t(x0 >> 6)) * uint32_t(NC * B::kComp);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       T Ax, Ay, Az;
@@ -315,8 +347,6 @@ __global__ void __launch_bounds__(256) k_sweep_d2q9(const void* __restrict__ fin
 #pragma unroll
       for (int i = 0; i < 9; ++i) f[i] = Fc[c][i];
       collide<2, T>(f, rs[c], ux, uy, T(0), Ax, Ay, Az, jx[c] * inv_rs, jy[c] * inv_rs, T(0), p.inv_tau);
-      char* const outc = static_cast<char*>(fout) + B::run(c, 0);
-      const uint32_t own_rest = orow + B::in_run(0, lane), own_move = orow + B::in_run(1, lane);
       if constexpr (S::kShift) {
         // FP16 deviations of the moving populations; the ledger keeps the rest
         T rest = Lc[c];
@@ -324,15 +354,35 @@ __global__ void __launch_bounds__(256) k_sweep_d2q9(const void* __restrict__ fin
         for (int i = 1; i < 9; ++i) {
           const _Float16 d = encode_move<2>(p.sh, c, i, f[i]);
           rest -= float(d);
-          __builtin_nontemporal_store(d,
-                                      reinterpret_cast<_Float16*>(outc + (own_move + (B::run(c, i) - B::run(c, 0)))));
+          Fc[c][i] = float(d);
         }
-        __builtin_nontemporal_store(rest, reinterpret_cast<float*>(outc + own_rest));
+        Lc[c] = rest;
       } else {
 #pragma unroll
-        for (int i = 0; i < 9; ++i)
-          __builtin_nontemporal_store(f[i], reinterpret_cast<T*>(outc + ((i == 0 ? own_rest : own_move) +
-                                                                        (B::run(c, i) - B::run(c, 0)))));
+        for (int i = 0; i < 9; ++i) Fc[c][i] = f[i];
+      }
+    }
+  };
+  // non-temporal stores of a collided row: exactly 9 NC store instructions
+  // (one per run; runs are 256 or 128 bytes apart, so none merge), which the
+  // wait at the start of the next round counts on
+  auto store_row = [&](int rc, const T (&Fc)[NC][9], const T (&Lc)[NC]) {
+    const uint32_t orow = (uint32_t(rc) * uint32_t(p.nbx) + uint32_t(x0 >> 6)) * uint32_t(NC * B::kComp);
+    const uint32_t own_rest = orow + B::in_run(0, lane), own_move = orow + B::in_run(1, lane);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      char* const outc = static_cast<char*>(fout) + B::run(c, 0);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        const uint32_t off = (i == 0 ? own_rest : own_move) + (B::run(c, i) - B::run(c, 0));
+        if constexpr (S::kShift) {
+          if (i == 0)
+            __builtin_nontemporal_store(Lc[c], reinterpret_cast<float*>(outc + off));
+          else
+            __builtin_nontemporal_store(_Float16(Fc[c][i]), reinterpret_cast<_Float16*>(outc + off));
+        } else {
+          __builtin_nontemporal_store(Fc[c][i], reinterpret_cast<T*>(outc + off));
+        }
       }
     }
   };
@@ -364,14 +414,24 @@ __global__ void __launch_bounds__(256) k_sweep_d2q9(const void* __restrict__ fin
   lds_barrier();
 
   // ---- rounds ------------------------------------------------------------
-  // Round k collides row rc = ya + 4k + w from Fc and takes row ra = rc + 4
-  // into Fn.
-  auto round = [&](int k, T (&Fc)[NC][9], T (&Lc)[NC], T (&Fn)[NC][9], T (&Ln)[NC]) {
+  // Round k takes row ra = rc + 4 (staged in the round before) into F1 and
+  // collides row rc = ya + 4k + w from F0, then moves F1 into F0.  Vector
+  // memory operations retire in issue order, and a round that collided
+  // issued its 9 NC stores after its staging loads, so the next round waits
+  // until at most 9 NC operations remain in flight: the staged row has
+  // landed, the stores complete during that round.  In a full round every
+  // wave collides and stores unconditionally; rounds 1 .. full - 1 are
+  // entered only from full rounds, so the compiler's own wait before the
+  // first read of the staged row counts the same 9 NC stores.
+  auto round = [&](int k, bool full, bool prev_stored) {
     const int rc = ya + 4 * k + w;
     const int ra = rc + 4;
-    wait_vm<0>();  // the row staged in the round before has landed
-    take(stage, Fn, Ln);
-    put_rho(ra, Fn, Ln);
+    if (prev_stored)
+      wait_vm<9 * NC>();
+    else
+      wait_vm<0>();
+    take(stage, F1, L1);
+    put_rho(ra, F1, L1);
     put_rho_halo(ra, stage);
     if (k + 1 < rounds) {
       asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // the slot is read before it is staged again
@@ -380,14 +440,25 @@ __global__ void __launch_bounds__(256) k_sweep_d2q9(const void* __restrict__ fin
     lds_barrier();
     put_h4(ya + 4 * k + 3);
     lds_barrier();
-    if (rc < yb) collide_row(rc, Fc, Lc);
+    if (full || rc < yb) {
+      collide_row(rc, F0, L0);
+      store_row(rc, F0, L0);
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) F0[c][i] = F1[c][i];
+      L0[c] = L1[c];
+    }
   };
-  int k = 0;
-  for (; k + 1 < rounds; k += 2) {
-    round(k, F0, L0, F1, L1);
-    round(k + 1, F1, L1, F0, L0);
+  const int full = (yb - ya) / 4;  // rounds in which all four waves collide
+  if (full > 0) {
+    round(0, true, false);
+    for (int k = 1; k < full; ++k) round(k, true, true);
+    if (full < rounds) round(full, false, true);
+  } else {
+    round(0, false, false);  // a segment of fewer than four rows
   }
-  if (k < rounds) round(k, F0, L0, F1, L1);
 }
 
 }  // namespace sweep
