@@ -227,7 +227,8 @@ def main():
         f16s = {"value": round(h["value"], 1), "ms_per_step": round(h["ms_per_step"], 5), "path": h["path"],
                 "speedup_vs_f32": round(h["value"] / value, 3),
                 "hbm_frac": round(hb / (h["ms_per_step"] / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-                "algorithmic_bytes_per_launch": hb, "mass_drift": h["mass_drift"], "status": h["health"]["status"]}
+                "algorithmic_bytes_per_launch": hb, "traffic": measured_traffic(args.workload, "f16s", h["path"]),
+                "mass_drift": h["mass_drift"], "status": h["health"]["status"]}
 
     serving = None
     if not args.no_serving:
