@@ -351,7 +351,15 @@ int moments_impl(lb_ctx* h, void* scratch, double* rho, double* U, double* mu, d
 extern "C" {
 
 int lb_init(const lb_params* p, const double* rho0, void* workspace, size_t workspace_bytes, lb_ctx** out) {
-  return lbm::init_impl(p, rho0, workspace, workspace_bytes, nullptr, out);
+  const int rc = lbm::init_impl(p, rho0, workspace, workspace_bytes, nullptr, out);
+  if (rc != LB_OK || (*out)->c.path != LB_PATH_SWEEP) return rc;
+  const int e = lbm::sweep_tune((*out)->c);
+  if (e != 0) {
+    lb_free(*out);
+    *out = nullptr;
+    return hip_fail(static_cast<hipError_t>(e), "sweep segment tuning");
+  }
+  return LB_OK;
 }
 
 int lb_step(lb_ctx* h, int64_t nsteps) {

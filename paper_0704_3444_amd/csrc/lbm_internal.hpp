@@ -14,6 +14,9 @@ struct Ctx;
 using FusedStepFn = void (*)(const Ctx&, const void* fin, void* fout);
 FusedStepFn fused_step_for(int lattice, int storage, int n_comp);  // tile kernel, D2Q9
 FusedStepFn sweep_step_for(int storage, int n_comp);               // strip sweep, D2Q9, nx % 64 == 0
+// Pick the sweep's segment length for the context by timing (synchronises
+// its stream); returns a hipError_t.
+int sweep_tune(Ctx& c);
 
 // Context behind the opaque lb_ctx handle.
 struct Ctx {
@@ -40,6 +43,7 @@ struct Ctx {
   int64_t t = 0;
   int path = LB_PATH_SPLIT;
   FusedStepFn fused = nullptr;      // kernel of LB_PATH_TILE / LB_PATH_SWEEP
+  int sweep_rows = 0;               // segment length of the sweep (0: one-wave default)
 
   Params<float> pf;
   Params<double> pd;

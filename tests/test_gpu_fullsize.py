@@ -84,3 +84,22 @@ def test_fullsize_mass_conserved(workload, storage):
     drift = np.abs(m / m0 - 1).max()
     print(f"[fullsize] {storage} mass drift over 300 steps {drift:.3e}", flush=True)
     assert drift < 1e-6
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16s"])
+def test_fullsize_tuned_sweep_equals_split_path(workload, storage):
+    """lb_init times a few segment lengths of the sweep on grids this large;
+    whichever it keeps, every site must come out bit for bit as on the
+    one-thread-per-site split path."""
+    from paper_0704_3444_amd import Simulation
+
+    cfg, rho0 = workload
+    out = {}
+    for path in ("sweep", "split"):
+        sim = Simulation(cfg, rho0, storage=storage, path=path)
+        sim.step(3)
+        out[path] = sim.moments(fields=True)
+        sim.close()
+    print(f"[fullsize] {storage} tuned sweep vs split, 3 steps", flush=True)
+    assert np.array_equal(out["sweep"]["rho"], out["split"]["rho"])
+    assert np.array_equal(out["sweep"]["U"], out["split"]["U"])
