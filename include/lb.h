@@ -121,7 +121,12 @@ size_t lb_workspace_bytes(const lb_params* p);
 
 /* Create a context and set every site to rest equilibrium,
  * f^sigma_i = w_i rho0^sigma (the paper prescribes the initial volume
- * fractions of a fluid at rest).
+ * fractions of a fluid at rest).  Waits for the stream before returning.
+ * When the context runs the strip-sweep kernel (lb_path_in_use) on a grid
+ * of at least 2^20 sites, lb_init also times a few segment lengths of that
+ * kernel on the initial state (about 2 x 8 x 9 launches; each writes only
+ * the context's second population copy) and keeps the fastest; every
+ * length gives the same results bit for bit.
  *   p          parameters, copied.
  *   rho0       host FP64 [N][S] initial component densities, each > 0; copied.
  *   workspace  device memory of at least lb_workspace_bytes(p) bytes, 256-byte
