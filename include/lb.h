@@ -122,11 +122,6 @@ size_t lb_workspace_bytes(const lb_params* p);
 /* Create a context and set every site to rest equilibrium,
  * f^sigma_i = w_i rho0^sigma (the paper prescribes the initial volume
  * fractions of a fluid at rest).  Waits for the stream before returning.
- * When the context runs the strip-sweep kernel (lb_path_in_use) on a grid
- * of at least 2^20 sites, lb_init also times a few segment lengths of that
- * kernel on the initial state (about 2 x 8 x 9 launches; each writes only
- * the context's second population copy) and keeps the fastest; every
- * length gives the same results bit for bit.
  *   p          parameters, copied.
  *   rho0       host FP64 [N][S] initial component densities, each > 0; copied.
  *   workspace  device memory of at least lb_workspace_bytes(p) bytes, 256-byte
@@ -141,7 +136,13 @@ int lb_init(const lb_params* p, const double* rho0, void* workspace, size_t work
 
 /* Advance nsteps >= 0 time steps of Eq. (ssLB): per site and component the
  * moments, chemical potentials, force, equilibrium, forcing term, BGK
- * collision and streaming.  Asynchronous on the context's stream. */
+ * collision and streaming.  Asynchronous on the context's stream.
+ * On the strip-sweep path (lb_path_in_use) of a grid of at least 2^20
+ * sites, the first call with at least 32 steps runs 4 of them with each of
+ * up to 8 segment lengths of the sweep, between events on the stream, and a
+ * later call (not during stream capture) keeps the fastest once those
+ * events have completed, without waiting for them.  Every segment length
+ * gives the same results bit for bit. */
 int lb_step(lb_ctx* c, int64_t nsteps);
 
 /* Observables at the current time, computed on the device in FP64 from the

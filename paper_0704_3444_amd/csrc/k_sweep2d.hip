@@ -507,82 +507,42 @@ static void launch_sweep(const Ctx& c, const void* fin, void* fout) {
   launch_rows<S, NC>(c, fin, fout, c.sweep_rows > 0 ? c.sweep_rows : sweep_rows(p.nx, p.ny, sweep_slots<S, NC>()));
 }
 
-// Segment length for this run.  The one-wave sizing above is the default;
-// on large grids the time also depends on how the segments fall on the
-// workgroup slots and the L2s (neighbouring short segments share their halo
-// rows in L2), irregularly enough that a few lengths are timed on the run's
-// own state: each trial reads the current copy and writes the other, which
-// the next step overwrites, and every length gives the same result.
+// Segment lengths worth timing for this run, the one-wave default first.
+// Large grids only: there the time also depends on how the segments fall on
+// the workgroup slots and the L2s (neighbouring short segments share their
+// halo rows in L2), irregularly enough to be measured rather than predicted.
 template <class S, int NC>
-static int tune_rows(const Ctx& c) {
+static int candidates(const Ctx& c, int* cand) {
   const Params<float>& p = c.params<float>();
-  const int base = sweep_rows(p.nx, p.ny, sweep_slots<S, NC>());
-  if (static_cast<long long>(p.nx) * p.ny < (1LL << 20)) return base;
+  if (static_cast<long long>(p.nx) * p.ny < (1LL << 20)) return 0;
   const int top = (p.ny + 3) / 4 * 4;
-  int cand[8], nc = 0;
+  int nc = 0;
   auto add = [&](int r) {
     r = r > top ? top : r;
     for (int i = 0; i < nc; ++i)
       if (cand[i] == r) return;
     cand[nc++] = r;
   };
-  add(base);
+  add(sweep_rows(p.nx, p.ny, sweep_slots<S, NC>()));
   for (int r : {16, 24, 32, 48, 64, 96, 128}) add(r);
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
-    if (e0) (void)hipEventDestroy(e0);
-    return base;
-  }
-  // two passes (the first also brings the clocks up), 8 timed launches per
-  // length, best time of each length kept
-  const void* fin = c.f[c.cur];
-  void* fout = c.f[1 - c.cur];
-  float t[8];
-  bool ok = true;
-  for (int pass = 0; pass < 2 && ok; ++pass) {
-    for (int i = 0; i < nc && ok; ++i) {
-      launch_rows<S, NC>(c, fin, fout, cand[i]);  // warm-up
-      float ms = 0.f;
-      ok = hipEventRecord(e0, c.stream) == hipSuccess;
-      for (int k = 0; ok && k < 8; ++k) launch_rows<S, NC>(c, fin, fout, cand[i]);
-      ok = ok && hipEventRecord(e1, c.stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
-           hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
-      if (ok) t[i] = pass == 0 || ms < t[i] ? ms : t[i];
-    }
-  }
-  int best = base;
-  if (ok) {
-    float best_ms = t[0];
-    for (int i = 1; i < nc; ++i)
-      if (t[i] < best_ms) {
-        best_ms = t[i];
-        best = cand[i];
-      }
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  return best;
+  return nc;
 }
 
 template <class S>
-static int tune_for_n(const Ctx& c) {
+static int candidates_for_n(const Ctx& c, int* cand) {
   switch (c.prm.n_comp) {
-    case 1: return tune_rows<S, 1>(c);
-    case 2: return tune_rows<S, 2>(c);
-    case 3: return tune_rows<S, 3>(c);
-    case 4: return tune_rows<S, 4>(c);
+    case 1: return candidates<S, 1>(c, cand);
+    case 2: return candidates<S, 2>(c, cand);
+    case 3: return candidates<S, 3>(c, cand);
+    case 4: return candidates<S, 4>(c, cand);
     default: return 0;
   }
 }
 
-int sweep_tune(Ctx& c) {
-  c.sweep_rows = 0;
-  int rows = 0;
-  if (c.prm.storage == StoreF32::kId) rows = tune_for_n<StoreF32>(c);
-  if (c.prm.storage == StoreF16S::kId) rows = tune_for_n<StoreF16S>(c);
-  c.sweep_rows = rows;
-  const hipError_t e = hipStreamSynchronize(c.stream);
-  return e == hipSuccess ? hipGetLastError() : e;
+int sweep_candidates(const Ctx& c, int* cand) {
+  if (c.prm.storage == StoreF32::kId) return candidates_for_n<StoreF32>(c, cand);
+  if (c.prm.storage == StoreF16S::kId) return candidates_for_n<StoreF16S>(c, cand);
+  return 0;
 }
 
 template <class S>

@@ -182,11 +182,46 @@ lbm::ShiftRef shift_ref_of(const lb_params* p, const double* rho0, size_t S) {
   return r;
 }
 
+void destroy_tuner_events(lbm::SweepTuner& tu) {
+  for (hipEvent_t& e : tu.ev) {
+    if (e) (void)hipEventDestroy(e);
+    e = nullptr;
+  }
+}
+
+// Once the trial steps' events have completed, keep the fastest segment
+// length (no wait: a call that finds them pending tries again next time).
+void finish_tuning(Ctx& c) {
+  lbm::SweepTuner& tu = c.tune;
+  if (hipEventQuery(tu.ev[tu.nc]) != hipSuccess) {
+    (void)hipGetLastError();  // hipErrorNotReady is not an error here
+    return;
+  }
+  int best = -1;
+  float best_ms = 0.f;
+  for (int i = 0; i < tu.nc; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, tu.ev[i], tu.ev[i + 1]) != hipSuccess) {
+      best = -1;
+      break;
+    }
+    if (best < 0 || ms < best_ms) {
+      best = i;
+      best_ms = ms;
+    }
+  }
+  (void)hipGetLastError();
+  c.sweep_rows = best >= 0 ? tu.cand[best] : 0;
+  destroy_tuner_events(tu);
+  tu.running = false;
+  tu.done = true;
+}
+
 // Step the context's state n times on its stream.
 int advance(Ctx& c, int64_t n) {
   const lbm::SplitTable& st = lbm::split_table(c.prm.lattice, c.prm.storage);
   lbm::FusedStepFn fused = c.path == LB_PATH_SPLIT ? nullptr : c.fused;
-  for (int64_t k = 0; k < n; ++k) {
+  auto step = [&]() {
     void* fin = c.f[c.cur];
     void* fout = c.f[1 - c.cur];
     if (fused)
@@ -196,7 +231,37 @@ int advance(Ctx& c, int64_t n) {
     c.cur = 1 - c.cur;
     c.t += 1;
     if (c.prm.check_every > 0 && c.t % c.prm.check_every == 0) st.diag(c, c.f[c.cur]);
+  };
+  int64_t k = 0;
+  lbm::SweepTuner& tu = c.tune;
+  if (c.path == LB_PATH_SWEEP && !tu.done && tu.nc > 0) {
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    const bool capturing = hipStreamIsCapturing(c.stream, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone;
+    (void)hipGetLastError();
+    if (tu.running) {
+      if (!capturing) finish_tuning(c);
+    } else if (!capturing && n >= int64_t(tu.nc) * tu.steps_per) {
+      // trial steps: every candidate length for steps_per real steps, each
+      // block between two events (all within this call, so no host gaps)
+      bool ok = true;
+      for (int i = 0; ok && i <= tu.nc; ++i) ok = hipEventCreate(&tu.ev[i]) == hipSuccess;
+      if (!ok) {
+        destroy_tuner_events(tu);
+        (void)hipGetLastError();
+        tu.done = true;
+      } else {
+        for (int i = 0; i < tu.nc; ++i) {
+          (void)hipEventRecord(tu.ev[i], c.stream);
+          c.sweep_rows = tu.cand[i];
+          for (int j = 0; j < tu.steps_per; ++j, ++k) step();
+        }
+        (void)hipEventRecord(tu.ev[tu.nc], c.stream);
+        c.sweep_rows = 0;
+        tu.running = true;
+      }
+    }
   }
+  for (; k < n; ++k) step();
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return LB_OK;
@@ -352,14 +417,8 @@ extern "C" {
 
 int lb_init(const lb_params* p, const double* rho0, void* workspace, size_t workspace_bytes, lb_ctx** out) {
   const int rc = lbm::init_impl(p, rho0, workspace, workspace_bytes, nullptr, out);
-  if (rc != LB_OK || (*out)->c.path != LB_PATH_SWEEP) return rc;
-  const int e = lbm::sweep_tune((*out)->c);
-  if (e != 0) {
-    lb_free(*out);
-    *out = nullptr;
-    return hip_fail(static_cast<hipError_t>(e), "sweep segment tuning");
-  }
-  return LB_OK;
+  if (rc == LB_OK && (*out)->c.path == LB_PATH_SWEEP) (*out)->c.tune.nc = lbm::sweep_candidates((*out)->c, (*out)->c.tune.cand);
+  return rc;
 }
 
 int lb_step(lb_ctx* h, int64_t nsteps) {
@@ -534,6 +593,7 @@ void lb_free(lb_ctx* h) {
   if (!h) return;
   Ctx& c = h->c;
   (void)hipStreamSynchronize(c.stream);
+  destroy_tuner_events(c.tune);
   if (c.owns_ws && c.ws) (void)hipFree(c.ws);
   delete h;
 }

@@ -14,9 +14,23 @@ struct Ctx;
 using FusedStepFn = void (*)(const Ctx&, const void* fin, void* fout);
 FusedStepFn fused_step_for(int lattice, int storage, int n_comp);  // tile kernel, D2Q9
 FusedStepFn sweep_step_for(int storage, int n_comp);               // strip sweep, D2Q9, nx % 64 == 0
-// Pick the sweep's segment length for the context by timing (synchronises
-// its stream); returns a hipError_t.
-int sweep_tune(Ctx& c);
+// Segment lengths of the sweep to time for this context (up to 8, the
+// default first) into cand; 0 when the grid is too small to tune.
+int sweep_candidates(const Ctx& c, int* cand);
+
+// Choice of the sweep's segment length during stepping: the first lb_step
+// call of at least nc * steps_per steps runs steps_per steps with each
+// candidate between events on the context's stream; a later call reads the
+// events once they have completed (without waiting) and keeps the fastest.
+struct SweepTuner {
+  static constexpr int kMax = 8;
+  static constexpr int steps_per = 4;
+  int cand[kMax] = {};
+  int nc = 0;             // candidates; 0: nothing to tune
+  bool running = false;   // trial steps queued, events pending
+  bool done = false;
+  hipEvent_t ev[kMax + 1] = {};
+};
 
 // Context behind the opaque lb_ctx handle.
 struct Ctx {
@@ -44,6 +58,7 @@ struct Ctx {
   int path = LB_PATH_SPLIT;
   FusedStepFn fused = nullptr;      // kernel of LB_PATH_TILE / LB_PATH_SWEEP
   int sweep_rows = 0;               // segment length of the sweep (0: one-wave default)
+  SweepTuner tune;
 
   Params<float> pf;
   Params<double> pd;

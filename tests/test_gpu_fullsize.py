@@ -88,8 +88,9 @@ def test_fullsize_mass_conserved(workload, storage):
 
 @pytest.mark.parametrize("storage", ["f32", "f16s"])
 def test_fullsize_tuned_sweep_equals_split_path(workload, storage):
-    """lb_init times a few segment lengths of the sweep on grids this large;
-    whichever it keeps, every site must come out bit for bit as on the
+    """On grids this large the sweep times several segment lengths during
+    its first 32 steps and keeps the fastest from the next lb_step call on;
+    whichever lengths ran, every site must come out bit for bit as on the
     one-thread-per-site split path."""
     from paper_0704_3444_amd import Simulation
 
@@ -97,9 +98,11 @@ def test_fullsize_tuned_sweep_equals_split_path(workload, storage):
     out = {}
     for path in ("sweep", "split"):
         sim = Simulation(cfg, rho0, storage=storage, path=path)
-        sim.step(3)
+        sim.step(34)  # trial steps (sweep)
+        sim.step(2)   # chosen length
         out[path] = sim.moments(fields=True)
         sim.close()
-    print(f"[fullsize] {storage} tuned sweep vs split, 3 steps", flush=True)
+    print(f"[fullsize] {storage} tuned sweep vs split, 36 steps", flush=True)
+    assert out["sweep"]["step"] == out["split"]["step"] == 36
     assert np.array_equal(out["sweep"]["rho"], out["split"]["rho"])
     assert np.array_equal(out["sweep"]["U"], out["split"]["U"])
