@@ -157,13 +157,18 @@ def run_serving(n_req):
     info = lb.lb_batch_config_info("f32", 3, best)
     batched, bsum = serve.serve_batched(reqs, config=best, chunk=100, graph_steps=50)
     print(f"bench: serving batched {bsum}", file=sys.stderr, flush=True)
+    best16, _ = serve.tune_batch(reqs[:48], storage="f16s", steps=10)
+    info16 = lb.lb_batch_config_info("f16s", 3, best16)
+    batched16, bsum16 = serve.serve_batched(reqs, storage="f16s", config=best16, chunk=100, graph_steps=50)
+    print(f"bench: serving batched, shifted FP16 storage {bsum16}", file=sys.stderr, flush=True)
     serial, ssum = serve.serve_serial(reqs)
     print(f"bench: serving one at a time {ssum}", file=sys.stderr, flush=True)
-    bad = sum(x["status"] != 0 for x in batched) + sum(x["status"] != 0 for x in serial)
+    bad = sum(x["status"] != 0 for x in batched + batched16 + serial)
     return {"workload": f"poisson_mix_{n_req}", "rate_hz": 40.0, "steps_per_request": reqs[0]["nsteps"],
             "storage": "f32", "tuned_config": dict(info, index=best), "batched": bsum, "one_at_a_time": ssum,
             "speedup_throughput": round(bsum["mlups_x_comp"] / ssum["mlups_x_comp"], 3),
-            "speedup_p99": round(ssum["p99_ms"] / bsum["p99_ms"], 3), "failed_requests": bad}
+            "speedup_p99": round(ssum["p99_ms"] / bsum["p99_ms"], 3),
+            "batched_f16s": dict(bsum16, tuned_config=dict(info16, index=best16)), "failed_requests": bad}
 
 
 def main():

@@ -83,7 +83,7 @@ typedef enum lb_force_form { LB_FORCE_LOG = 0, LB_FORCE_EXPANDED = 1 } lb_force_
  *   LB_PATH_AUTO:  the fastest path that supports the run (sweep, then tile,
  *                  then split).
  *   LB_PATH_TILE:  fused one-kernel D2Q9 step over 2-D tiles with a two-site
- *                  density halo (any nx, LB_F64 and LB_F32).
+ *                  density halo (any nx, every storage).
  *   LB_PATH_SPLIT: three kernels per step (density, potential, collide and
  *                  stream); every lattice.
  *   LB_PATH_SWEEP: fused one-kernel D2Q9 step that sweeps 64-column strips
@@ -213,7 +213,7 @@ void lb_free(lb_ctx* c);
 typedef struct lb_batch lb_batch;
 
 typedef struct lb_batch_params {
-  int32_t storage;      /* LB_F32 or LB_F64, for every slot                      */
+  int32_t storage;      /* LB_F64, LB_F32 or LB_F16S, for every slot             */
   int32_t max_comp;     /* bound on N of the slots, 1 .. 4                        */
   int32_t max_slots;    /* slot capacity, 1 .. 4096                               */
   int32_t config;       /* kernel configuration (tile shape and grid), index

@@ -34,44 +34,55 @@ __device__ __forceinline__ int wrap_mod(int v, int n) {
   return r < 0 ? r + n : r;
 }
 
-// 32-bit byte offset of population 0 of site (x, y); population q sits 64 q
-// elements further (the block layout of pop_index).  The host only takes
-// this path when one population copy is smaller than 4 GiB, so that every
-// access is a uniform 64-bit base plus a 32-bit per-lane offset.
-template <typename T>
-__device__ __forceinline__ uint32_t site_offset(int nbx, int nq, int x, int y) {
-  return (((uint32_t(y) * uint32_t(nbx) + uint32_t(x >> 6)) * uint32_t(nq) << 6) + uint32_t(x & 63)) *
-         uint32_t(sizeof(T));
+// 32-bit byte offset of the block that holds site (x, y) (the block layout
+// of storage.hpp: n components of kComp bytes per 64-site block).  The host
+// only takes this path when one population copy is smaller than 4 GiB, so
+// that every access is a uniform 64-bit base plus a 32-bit per-lane offset.
+template <class S>
+__device__ __forceinline__ uint32_t block_off(const Params<typename S::T>& p, int x, int y) {
+  return (uint32_t(y) * uint32_t(p.nbx) + uint32_t(x >> 6)) * uint32_t(p.n) * BlockLayout<S, 9>::kComp;
 }
 
-template <typename T>
-__device__ __forceinline__ T load_at(const T* __restrict__ base, uint32_t byte_off) {
-  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
-}
-
-// rho^sigma at (x, y), summing the pulled populations in lattice order (the
-// same order as the split path's density kernel).
-template <typename T, int NC>
-__device__ __forceinline__ void pulled_density(const T* __restrict__ fin, const Params<T>& p, int x, int y,
-                                               T (&rho)[NC]) {
+// Byte offsets, without the component part, of the nine slots pulled into
+// site (x, y): slot i of the site r - v_i.
+template <class S>
+__device__ __forceinline__ void pull_offsets(const Params<typename S::T>& p, int x, int y, uint32_t (&off)[9]) {
   using L = Lattice<2>;
+  using B = BlockLayout<S, 9>;
   const int xm = wrap_add(x, -1, p.nx), xp = wrap_add(x, 1, p.nx);
   const int ym = wrap_add(y, -1, p.ny), yp = wrap_add(y, 1, p.ny);
-  uint32_t off[L::Q];
 #pragma unroll
   for (int i = 0; i < L::Q; ++i) {
     const int sx = L::cx(i) > 0 ? xm : (L::cx(i) < 0 ? xp : x);
     const int sy = L::cy(i) > 0 ? ym : (L::cy(i) < 0 ? yp : y);
-    off[i] = site_offset<T>(p.nbx, p.nq, sx, sy) + uint32_t(run_slot<L::Q>(i) * kBlockX * sizeof(T));
+    off[i] = block_off<S>(p, sx, sy) + B::in_run(i, sx);
   }
+}
+
+// rho^sigma at (x, y) from the pulled slots: the sum of the decoded
+// populations in lattice order, or the ledger for the shifted codec (the
+// same values as the split path's density kernel).
+template <class S, int NC>
+__device__ __forceinline__ void pulled_density(const void* __restrict__ fin, const Params<typename S::T>& p, int x,
+                                               int y, typename S::T (&rho)[NC]) {
+  using T = typename S::T;
+  using B = BlockLayout<S, 9>;
+  uint32_t off[9];
+  pull_offsets<S>(p, x, y, off);
 #pragma unroll
   for (int k = 0; k < NC; ++k) {
-    T acc = T(0);
+    T v[9], led = T(0);
     if (k < p.n) {
 #pragma unroll
-      for (int i = 0; i < L::Q; ++i) acc += load_at(fin, off[i] + uint32_t(k * L::Q * kBlockX * sizeof(T)));
+      for (int i = 0; i < 9; ++i) {
+        const T raw = load_slot<S>(fin, off[i] + B::run(k, i), i);
+        led = i == 0 ? raw : led + raw;
+        v[i] = decode<S, 2>(p.sh, k, i, raw);
+      }
+      rho[k] = site_density<S, 9>(p.sh, k, v, led);
+    } else {
+      rho[k] = T(0);
     }
-    rho[k] = acc;
   }
 }
 
@@ -84,9 +95,12 @@ struct TileLds {
 
 // The whole step for the tile with corner (x0, y0).  Every thread of the
 // workgroup calls it (it contains workgroup barriers).
-template <typename T, int NC, int TX, int TY, int NT, bool NTSTORE>
-__device__ __forceinline__ void tile_step(const T* __restrict__ fin, T* __restrict__ fout, const Params<T>& p,
-                                          int x0, int y0, TileLds<T, NC, TX, TY>& lds) {
+template <class S, int NC, int TX, int TY, int NT, bool NTSTORE>
+__device__ __forceinline__ void tile_step(const void* __restrict__ fin, void* __restrict__ fout,
+                                          const Params<typename S::T>& p, int x0, int y0,
+                                          TileLds<typename S::T, NC, TX, TY>& lds) {
+  using T = typename S::T;
+  using B = BlockLayout<S, 9>;
   using L = Lattice<2>;
   constexpr int Q = L::Q;
   constexpr int HX = TX + 4, HY = TY + 4;  // rho region: tile + 2
@@ -100,31 +114,35 @@ __device__ __forceinline__ void tile_step(const T* __restrict__ fin, T* __restri
   const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
 
   // ---- A: the tile's own populations, kept in registers -------------------
+  // (decoded; the shifted codec also keeps each site's ledger)
   T f[SPT][NC][Q];
+  T led[SPT][NC];
   bool valid[SPT];
 #pragma unroll
   for (int k = 0; k < SPT; ++k) {
     const int x = x0 + tx, y = y0 + ty + k * RS;
     valid[k] = x < nx && y < ny;
     if (valid[k]) {
-      const int xm = wrap_add(x, -1, nx), xp = wrap_add(x, 1, nx);
-      const int ym = wrap_add(y, -1, ny), yp = wrap_add(y, 1, ny);
       uint32_t off[Q];
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        const int sx = L::cx(i) > 0 ? xm : (L::cx(i) < 0 ? xp : x);
-        const int sy = L::cy(i) > 0 ? ym : (L::cy(i) < 0 ? yp : y);
-        off[i] = site_offset<T>(p.nbx, p.nq, sx, sy) + uint32_t(run_slot<Q>(i) * kBlockX * sizeof(T));
-      }
+      pull_offsets<S>(p, x, y, off);
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        T acc = T(0);
+        // one uniform branch per component, so that its nine loads are
+        // issued together
+        T l = T(0);
+        if (c < n) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-          f[k][c][i] = c < n ? load_at(fin, off[i] + uint32_t(c * Q * kBlockX * sizeof(T))) : T(0);
-          acc += f[k][c][i];
+          for (int i = 0; i < Q; ++i) {
+            const T raw = load_slot<S>(fin, off[i] + B::run(c, i), i);
+            l = i == 0 ? raw : l + raw;
+            f[k][c][i] = decode<S, 2>(p.sh, c, i, raw);
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < Q; ++i) f[k][c][i] = T(0);
         }
-        s_rho[c][ty + k * RS + 2][tx + 2] = acc;
+        led[k][c] = l;
+        s_rho[c][ty + k * RS + 2][tx + 2] = c < n ? site_density<S, Q>(p.sh, c, f[k][c], l) : T(0);
       }
     }
   }
@@ -152,7 +170,7 @@ __device__ __forceinline__ void tile_step(const T* __restrict__ fin, T* __restri
         px = TX + 2 + j % 2;
       }
       T r[NC];
-      pulled_density<T, NC>(fin, p, wrap_mod(x0 - 2 + px, nx), wrap_mod(y0 - 2 + py, ny), r);
+      pulled_density<S, NC>(fin, p, wrap_mod(x0 - 2 + px, nx), wrap_mod(y0 - 2 + py, ny), r);
 #pragma unroll
       for (int c = 0; c < NC; ++c) s_rho[c][py][px] = r[c];
     }
@@ -162,7 +180,7 @@ __device__ __forceinline__ void tile_step(const T* __restrict__ fin, T* __restri
       const bool inner = px >= 2 && px < TX + 2 && py >= 2 && py < TY + 2 && x0 + px - 2 < nx && y0 + py - 2 < ny;
       if (inner) continue;  // filled in phase A
       T r[NC];
-      pulled_density<T, NC>(fin, p, wrap_mod(x0 - 2 + px, nx), wrap_mod(y0 - 2 + py, ny), r);
+      pulled_density<S, NC>(fin, p, wrap_mod(x0 - 2 + px, nx), wrap_mod(y0 - 2 + py, ny), r);
 #pragma unroll
       for (int c = 0; c < NC; ++c) s_rho[c][py][px] = r[c];
     }
@@ -215,7 +233,7 @@ __device__ __forceinline__ void tile_step(const T* __restrict__ fin, T* __restri
     const T inv_rt = rcp_(rt);
     ux *= inv_rt;
     uy *= inv_rt;
-    const uint32_t own = site_offset<T>(p.nbx, p.nq, x, y);
+    const uint32_t own = block_off<S>(p, x, y);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       if (c >= n) continue;
@@ -225,29 +243,50 @@ __device__ __forceinline__ void tile_step(const T* __restrict__ fin, T* __restri
                           Ay, Az);
       const T inv_rs = rcp_(rs[c]);
       collide<2, T>(f[k][c], rs[c], ux, uy, T(0), Ax, Ay, Az, jx[c] * inv_rs, jy[c] * inv_rs, T(0), p.inv_tau);
+      char* const out = static_cast<char*>(fout);
+      if constexpr (S::kShift) {
+        // FP16 deviations of the moving populations; the ledger keeps the rest
+        T rest = led[k][c];
 #pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        T* dst = reinterpret_cast<T*>(reinterpret_cast<char*>(fout) + own +
-                                      uint32_t((c * Q + run_slot<Q>(i)) * kBlockX * sizeof(T)));
+        for (int i = 1; i < Q; ++i) {
+          const _Float16 d = encode_move<2>(p.sh, c, i, f[k][c][i]);
+          rest -= float(d);
+          _Float16* dst = reinterpret_cast<_Float16*>(out + (own + B::run(c, i) + B::in_run(i, x)));
+          if constexpr (NTSTORE)
+            __builtin_nontemporal_store(d, dst);
+          else
+            *dst = d;
+        }
+        float* dst0 = reinterpret_cast<float*>(out + (own + B::run(c, 0) + B::in_run(0, x)));
         if constexpr (NTSTORE)
-          __builtin_nontemporal_store(f[k][c][i], dst);
+          __builtin_nontemporal_store(rest, dst0);
         else
-          *dst = f[k][c][i];
+          *dst0 = rest;
+      } else {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          T* dst = reinterpret_cast<T*>(out + (own + B::run(c, i) + B::in_run(i, x)));
+          if constexpr (NTSTORE)
+            __builtin_nontemporal_store(f[k][c][i], dst);
+          else
+            *dst = f[k][c][i];
+        }
       }
     }
   }
 }
 
-template <typename T, int NC, int TX, int TY, int NT, bool NTSTORE>
-__global__ void __launch_bounds__(NT) k_fused_d2q9(const T* __restrict__ fin, T* __restrict__ fout, Params<T> p,
-                                                   int nbx, int ntiles, int tiles_per_xcd, int xcd_remap) {
-  __shared__ TileLds<T, NC, TX, TY> lds;
+template <class S, int NC, int TX, int TY, int NT, bool NTSTORE>
+__global__ void __launch_bounds__(NT) k_fused_d2q9(const void* __restrict__ fin, void* __restrict__ fout,
+                                                   Params<typename S::T> p, int nbx, int ntiles, int tiles_per_xcd,
+                                                   int xcd_remap) {
+  __shared__ TileLds<typename S::T, NC, TX, TY> lds;
   // XCD-aware tile order: workgroup b runs on XCD b % 8; give XCD c the
   // contiguous tile range [c * tiles_per_xcd, (c + 1) * tiles_per_xcd).
   const int b = blockIdx.x;
   const int t = xcd_remap ? (b % kXcds) * tiles_per_xcd + b / kXcds : b;
   if (t >= ntiles) return;
-  tile_step<T, NC, TX, TY, NT, NTSTORE>(fin, fout, p, (t % nbx) * TX, (t / nbx) * TY, lds);
+  tile_step<S, NC, TX, TY, NT, NTSTORE>(fin, fout, p, (t % nbx) * TX, (t / nbx) * TY, lds);
 }
 
 // ---------------------------------------------------------- batched ----
@@ -261,11 +300,12 @@ __global__ void __launch_bounds__(NT) k_fused_d2q9(const T* __restrict__ fin, T*
 // robin) takes the contiguous range [c * per_xcd, (c + 1) * per_xcd), its
 // workgroups striding through it, so that the halo rows of neighbouring
 // tiles stay in that XCD's L2.
-template <typename T, int NC, int TX, int TY, int NT>
-__global__ void __launch_bounds__(NT) k_batch_d2q9(const BatchSlot<T>* __restrict__ slots,
+template <class S, int NC, int TX, int TY, int NT>
+__global__ void __launch_bounds__(NT) k_batch_d2q9(const BatchSlot<typename S::T>* __restrict__ slots,
                                                    const long long* __restrict__ t_now,
                                                    const BatchHeader* __restrict__ hdr,
                                                    const int* __restrict__ item_slot) {
+  using T = typename S::T;
   __shared__ TileLds<T, NC, TX, TY> lds;
   const int items = hdr->items;
   const int groups = gridDim.x / kXcds;  // workgroups per XCD (the grid is a multiple of 8)
@@ -279,8 +319,7 @@ __global__ void __launch_bounds__(NT) k_batch_d2q9(const BatchSlot<T>* __restric
     if (t >= sl.t_end) continue;  // uniform: the whole workgroup skips
     const int tile = w - sl.first_item;
     const int x0 = (tile % sl.tiles_x) * TX, y0 = (tile / sl.tiles_x) * TY;
-    tile_step<T, NC, TX, TY, NT, true>(static_cast<const T*>(sl.f[t & 1]), static_cast<T*>(sl.f[(t + 1) & 1]),
-                                       sl.p, x0, y0, lds);
+    tile_step<S, NC, TX, TY, NT, true>(sl.f[t & 1], sl.f[(t + 1) & 1], sl.p, x0, y0, lds);
     __syncthreads();  // the next tile reuses the LDS
   }
 }
@@ -295,11 +334,11 @@ __global__ void k_batch_advance(const BatchSlot<T>* __restrict__ slots, long lon
   if (t_now[id] < slots[s].t_end) t_now[id] += 1;
 }
 
-template <typename T, int NC, int TX, int TY, int NT>
+template <class S, int NC, int TX, int TY, int NT>
 static void batch_step_launch(const void* slots, const long long* t_now, const BatchHeader* hdr,
                               const int* item_slot, int grid, hipStream_t s) {
-  k_batch_d2q9<T, NC, TX, TY, NT><<<grid, NT, 0, s>>>(static_cast<const BatchSlot<T>*>(slots), t_now, hdr,
-                                                       item_slot);
+  k_batch_d2q9<S, NC, TX, TY, NT><<<grid, NT, 0, s>>>(static_cast<const BatchSlot<typename S::T>*>(slots), t_now,
+                                                       hdr, item_slot);
 }
 
 template <typename T>
@@ -308,103 +347,103 @@ static void batch_advance_launch(const void* slots, long long* t_now, const Batc
   k_batch_advance<T><<<(max_slots + 255) / 256, 256, 0, s>>>(static_cast<const BatchSlot<T>*>(slots), t_now, hdr);
 }
 
-template <typename T, int NC, int TX, int TY, int NT>
+template <class S, int NC, int TX, int TY, int NT>
 static constexpr BatchKernel batch_kernel() {
-  return BatchKernel{TX, TY, NT, batch_step_launch<T, NC, TX, TY, NT>, batch_advance_launch<T>};
+  return BatchKernel{TX, TY, NT, batch_step_launch<S, NC, TX, TY, NT>, batch_advance_launch<typename S::T>};
 }
 
 // Candidate tile shapes for the autotuner, per precision and component
-// bound: FP32 keeps SPT * NC * 9 populations per thread in registers, FP64
-// twice the bytes, so FP64 and large NC get the shorter tiles.
-template <typename T, int NC>
+// bound: FP32 (and the shifted codec, decoded to FP32) keeps SPT * NC * 9
+// populations per thread in registers, FP64 twice the bytes, so FP64 and
+// large NC get the shorter tiles.
+template <class S, int NC>
 static const BatchKernel* batch_list(int* n) {
-  if constexpr (sizeof(T) == 4 && NC <= 3) {
-    static const BatchKernel k[] = {batch_kernel<T, NC, 64, 16, 256>(), batch_kernel<T, NC, 64, 8, 256>(),
-                                    batch_kernel<T, NC, 64, 4, 256>(),  batch_kernel<T, NC, 128, 8, 256>(),
-                                    batch_kernel<T, NC, 32, 16, 256>(), batch_kernel<T, NC, 32, 8, 256>()};
+  if constexpr (sizeof(typename S::T) == 4 && NC <= 3) {
+    static const BatchKernel k[] = {batch_kernel<S, NC, 64, 16, 256>(), batch_kernel<S, NC, 64, 8, 256>(),
+                                    batch_kernel<S, NC, 64, 4, 256>(),  batch_kernel<S, NC, 128, 8, 256>(),
+                                    batch_kernel<S, NC, 32, 16, 256>(), batch_kernel<S, NC, 32, 8, 256>()};
     *n = int(sizeof(k) / sizeof(k[0]));
     return k;
   } else {
-    static const BatchKernel k[] = {batch_kernel<T, NC, 64, 8, 256>(), batch_kernel<T, NC, 64, 4, 256>(),
-                                    batch_kernel<T, NC, 32, 8, 256>()};
+    static const BatchKernel k[] = {batch_kernel<S, NC, 64, 8, 256>(), batch_kernel<S, NC, 64, 4, 256>(),
+                                    batch_kernel<S, NC, 32, 8, 256>()};
     *n = int(sizeof(k) / sizeof(k[0]));
     return k;
+  }
+}
+
+template <class S>
+static const BatchKernel* batch_for_n(int max_comp, int* n) {
+  switch (max_comp) {
+    case 1: return batch_list<S, 1>(n);
+    case 2: return batch_list<S, 2>(n);
+    case 3: return batch_list<S, 3>(n);
+    case 4: return batch_list<S, 4>(n);
+    default: return nullptr;
   }
 }
 
 const BatchKernel* batch_kernels(int storage, int max_comp, int* n) {
   *n = 0;
-  if (storage == 1) {
-    switch (max_comp) {
-      case 1: return batch_list<float, 1>(n);
-      case 2: return batch_list<float, 2>(n);
-      case 3: return batch_list<float, 3>(n);
-      case 4: return batch_list<float, 4>(n);
-      default: return nullptr;
-    }
-  }
-  if (storage == 0) {
-    switch (max_comp) {
-      case 1: return batch_list<double, 1>(n);
-      case 2: return batch_list<double, 2>(n);
-      case 3: return batch_list<double, 3>(n);
-      case 4: return batch_list<double, 4>(n);
-      default: return nullptr;
-    }
-  }
+  if (storage == StoreF64::kId) return batch_for_n<StoreF64>(max_comp, n);
+  if (storage == StoreF32::kId) return batch_for_n<StoreF32>(max_comp, n);
+  if (storage == StoreF16S::kId) return batch_for_n<StoreF16S>(max_comp, n);
   return nullptr;
 }
 
 // ------------------------------------------------------------ dispatch ----
-template <typename T, int NC, int TX, int TY, int NT = 256, bool NTSTORE = true>
-static void launch_tile(const Params<T>& p, const T* fin, T* fout, hipStream_t stream, bool remap = true) {
+template <class S, int NC, int TX, int TY, int NT = 256, bool NTSTORE = true>
+static void launch_tile(const Params<typename S::T>& p, const void* fin, void* fout, hipStream_t stream,
+                        bool remap = true) {
   const int nbx = (p.nx + TX - 1) / TX;
   const int nby = (p.ny + TY - 1) / TY;
   const int ntiles = nbx * nby;
   const int per_xcd = (ntiles + kXcds - 1) / kXcds;
   const int grid = remap ? per_xcd * kXcds : ntiles;
-  k_fused_d2q9<T, NC, TX, TY, NT, NTSTORE><<<grid, NT, 0, stream>>>(fin, fout, p, nbx, ntiles, per_xcd, remap);
+  k_fused_d2q9<S, NC, TX, TY, NT, NTSTORE><<<grid, NT, 0, stream>>>(fin, fout, p, nbx, ntiles, per_xcd, remap);
 }
 
-template <typename T, int NC, int TX, int TY>
+template <class S, int NC, int TX, int TY>
 static void launch_fused(const Ctx& c, const void* fin, void* fout) {
-  launch_tile<T, NC, TX, TY>(c.params<T>(), static_cast<const T*>(fin), static_cast<T*>(fout), c.stream);
+  launch_tile<S, NC, TX, TY>(c.params<typename S::T>(), fin, fout, c.stream);
 }
 
 // Tile per precision and component count: registers hold SPT * N * 9
-// populations per thread and LDS holds N rho and N h tiles.
-template <typename T, int NC>
+// populations per thread (decoded, so the shifted codec counts as FP32) and
+// LDS holds N rho and N h tiles.
+template <class S, int NC>
 static FusedStepFn pick() {
-  if constexpr (sizeof(T) == 4) {
-    if constexpr (NC <= 3) return launch_fused<T, NC, 64, 16>;
-    else if constexpr (NC <= 5) return launch_fused<T, NC, 64, 8>;
-    else return launch_fused<T, NC, 64, 4>;
+  if constexpr (sizeof(typename S::T) == 4) {
+    if constexpr (NC <= 3) return launch_fused<S, NC, 64, 16>;
+    else if constexpr (NC <= 5) return launch_fused<S, NC, 64, 8>;
+    else return launch_fused<S, NC, 64, 4>;
   } else {
-    if constexpr (NC <= 2) return launch_fused<T, NC, 64, 8>;
-    else return launch_fused<T, NC, 64, 4>;
+    if constexpr (NC <= 2) return launch_fused<S, NC, 64, 8>;
+    else return launch_fused<S, NC, 64, 4>;
   }
 }
 
-template <typename T>
+template <class S>
 static FusedStepFn pick_n(int n) {
   switch (n) {
-    case 1: return pick<T, 1>();
-    case 2: return pick<T, 2>();
-    case 3: return pick<T, 3>();
-    case 4: return pick<T, 4>();
-    case 5: return pick<T, 5>();
-    case 6: return pick<T, 6>();
-    case 7: return pick<T, 7>();
-    case 8: return pick<T, 8>();
+    case 1: return pick<S, 1>();
+    case 2: return pick<S, 2>();
+    case 3: return pick<S, 3>();
+    case 4: return pick<S, 4>();
+    case 5: return pick<S, 5>();
+    case 6: return pick<S, 6>();
+    case 7: return pick<S, 7>();
+    case 8: return pick<S, 8>();
     default: return nullptr;
   }
 }
 
 FusedStepFn fused_step_for(int lattice, int storage, int n_comp) {
   if (lattice != 2) return nullptr;  // slot-count limit checked by the caller
-  if (storage == 0) return pick_n<double>(n_comp);
-  if (storage == 1) return pick_n<float>(n_comp);
-  return nullptr;  // shifted FP16 storage: split and sweep paths only
+  if (storage == StoreF64::kId) return pick_n<StoreF64>(n_comp);
+  if (storage == StoreF32::kId) return pick_n<StoreF32>(n_comp);
+  if (storage == StoreF16S::kId) return pick_n<StoreF16S>(n_comp);
+  return nullptr;
 }
 
 }  // namespace lbm

@@ -255,6 +255,9 @@ int ensure(void** buf, size_t* have, size_t need, hipStream_t side) {
   return LB_OK;
 }
 
+// Stored bytes of the nine populations of one site and component.
+size_t site_bytes(int storage) { return storage == LB_F64 ? 72 : (storage == LB_F32 ? 36 : 4 + 8 * 2); }
+
 int check_run(const lb_batch* b, const lb_params* p, size_t* bytes) {
   if (!p) return fail(LB_EINVAL, "params is NULL");
   if (p->lattice != LB_D2Q9) return fail(LB_ENOTSUP, "batches take D2Q9 runs");
@@ -262,8 +265,7 @@ int check_run(const lb_batch* b, const lb_params* p, size_t* bytes) {
   if (p->n_comp > b->bp.max_comp) return fail(LB_ENOTSUP, "the run has more components than the batch's max_comp");
   const size_t need = lb_workspace_bytes(p);
   if (need == 0) return LB_EINVAL;  // message set by lb_workspace_bytes
-  const size_t esz = p->storage == LB_F64 ? 8 : 4;
-  const size_t copy = size_t(p->ny) * size_t((p->nx + 63) / 64) * 64 * size_t(p->n_comp) * 9 * esz;
+  const size_t copy = size_t(p->ny) * size_t((p->nx + 63) / 64) * 64 * size_t(p->n_comp) * site_bytes(p->storage);
   if (copy >= (size_t(1) << 32)) return fail(LB_ENOTSUP, "a batched run's population copy must be below 4 GiB");
   *bytes = need;
   return LB_OK;
@@ -277,7 +279,8 @@ int lb_batch_create(const lb_batch_params* bp, lb_batch** out) {
   if (!out) return fail(LB_EINVAL, "out is NULL");
   *out = nullptr;
   if (!bp) return fail(LB_EINVAL, "params is NULL");
-  if (bp->storage != LB_F32 && bp->storage != LB_F64) return fail(LB_ENOTSUP, "batches take LB_F32 or LB_F64");
+  if (bp->storage != LB_F32 && bp->storage != LB_F64 && bp->storage != LB_F16S)
+    return fail(LB_ENOTSUP, "batches take LB_F64, LB_F32 or LB_F16S");
   if (bp->max_comp < 1 || bp->max_comp > 4) return fail(LB_ENOTSUP, "max_comp must be in 1..4");
   if (bp->max_slots < 1 || bp->max_slots > 4096) return fail(LB_EINVAL, "max_slots must be in 1..4096");
   if (bp->graph_steps < 0 || bp->graph_steps > 100000) return fail(LB_EINVAL, "graph_steps must be in 0..100000");
@@ -313,7 +316,7 @@ int lb_batch_create(const lb_batch_params* bp, lb_batch** out) {
   b->alloc.reset(bp->arena_bytes);
   // work items: at most one per 256 sites of the arena's smallest run, plus
   // the ragged tiles of every slot
-  const size_t min_site_bytes = size_t(2) * 9 * (bp->storage == LB_F64 ? 8 : 4);
+  const size_t min_site_bytes = size_t(2) * site_bytes(bp->storage);
   const size_t cap = bp->arena_bytes / (min_site_bytes * 256) * 2 + size_t(bp->max_slots) * 64 + 1024;
   b->item_cap = int(std::min<size_t>(cap, size_t(1) << 28));
   const size_t table = align_up(size_t(bp->max_slots) * b->slot_bytes);

@@ -11,12 +11,11 @@ TOL = {"f64": 1e-12, "f32": 1e-5}
 
 def paths_for(cfg, storage):
     """Kernel paths that support a run: split always; the tile kernel for
-    D2Q9 in FP64 and FP32; the strip sweep for D2Q9 in FP32 or shifted FP16
+    D2Q9 in every storage; the strip sweep for D2Q9 in FP32 or shifted FP16
     with nx a multiple of 64 and N <= 4."""
     paths = ["split"]
     if cfg["lattice"] == "D2Q9":
-        if storage in ("f64", "f32"):
-            paths.append("tile")
+        paths.append("tile")
         if storage in ("f32", "f16s") and cfg["shape"][0] % 64 == 0 and cfg["n_comp"] <= 4:
             paths.append("sweep")
     return paths

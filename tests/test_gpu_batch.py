@@ -53,7 +53,7 @@ def drain(batch, slots, max_calls=10000, chunk=7):
     raise AssertionError("slots did not finish")
 
 
-@pytest.mark.parametrize("storage", ["f32", "f64"])
+@pytest.mark.parametrize("storage", ["f32", "f64", "f16s"])
 def test_batch_equals_each_run_alone(storage):
     from paper_0704_3444_amd import Batch
 
@@ -200,24 +200,27 @@ def test_batch_rejects_what_it_cannot_run():
     b.close()
 
 
-def test_serving_loop_each_result_same_alone_and_in_mix():
+@pytest.mark.parametrize("storage,tol", [("f32", TOL["f32"]), ("f16s", 1e-4)])
+def test_serving_loop_each_result_same_alone_and_in_mix(storage, tol):
     """Continuous batching of a Poisson mix: every request completes, and
     its densities equal the same run alone (bit for bit) and the oracle
-    within the FP32 bar."""
+    within the storage's bar (shifted FP16: these near-uniform mixtures stay
+    within 1e-4 over 150 steps)."""
     from paper_0704_3444_amd import serve
 
     reqs = LI.serving_mix(12, seed=77, rate_hz=400.0, side=(64, 160), steps=150)
-    recs, summary = serve.serve_batched(reqs, max_slots=6, arena_bytes=96 << 20, chunk=20, graph_steps=10,
-                                        keep_fields=True)
-    print(f"[serve] {summary}", flush=True)
+    recs, summary = serve.serve_batched(reqs, storage=storage, max_slots=6, arena_bytes=96 << 20, chunk=20,
+                                        graph_steps=10, keep_fields=True)
+    print(f"[serve] {storage} {summary}", flush=True)
     assert summary["requests"] == 12 and summary["p99_ms"] >= summary["p50_ms"] > 0
     by_id = {x["id"]: x for x in recs}
     for r in reqs:
         rec = by_id[r["id"]]
         assert rec["status"] == 0 and rec["step"] == r["nsteps"]
-        alone = solo(r["cfg"], r["rho0"], r["nsteps"], "f32", "auto")
+        alone = solo(r["cfg"], r["rho0"], r["nsteps"], storage, "auto")
         assert np.array_equal(rec["rho"], alone["rho"]), r["id"]
     r = reqs[0]
     o = run_oracle(r["cfg"], r["rho0"], r["nsteps"])
     err = float(np.max(np.abs(by_id[r["id"]]["rho"] - o["rho"]) / o["rho"]))
-    assert err < TOL["f32"], err
+    print(f"[serve] {storage} request {r['id']} vs oracle {err:.2e}", flush=True)
+    assert err < tol, err

@@ -13,7 +13,7 @@ PATHS = ["split", "tile", "sweep"]
 
 
 def storages(path):
-    return {"sweep": ["f32", "f16s"], "tile": ["f64", "f32"], "split": ["f64", "f32", "f16s"]}[path]
+    return {"sweep": ["f32", "f16s"], "tile": ["f64", "f32", "f16s"], "split": ["f64", "f32", "f16s"]}[path]
 
 
 def sim(cfg, rho0, **kw):
