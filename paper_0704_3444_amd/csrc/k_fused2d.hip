@@ -43,6 +43,29 @@ __device__ __forceinline__ uint32_t block_off(const Params<typename S::T>& p, in
   return (uint32_t(y) * uint32_t(p.nbx) + uint32_t(x >> 6)) * uint32_t(p.n) * BlockLayout<S, 9>::kComp;
 }
 
+// Loads and stores of population slots through the global address space.
+// The batched kernel reads its population pointers from the slot table,
+// where the compiler cannot tell their address space and would otherwise
+// emit flat accesses (which also count against the LDS counter).
+using GChar = __attribute__((address_space(1))) char;
+
+template <class S>
+__device__ __forceinline__ typename S::T gload_slot(const void* base, uint32_t off, int i) {
+  using T = typename S::T;
+  const GChar* b = (const GChar*)base + off;
+  if (i == 0) return T(*(const __attribute__((address_space(1))) typename S::Rest*)b);
+  return T(*(const __attribute__((address_space(1))) typename S::Move*)b);
+}
+
+template <bool NTSTORE, typename V>
+__device__ __forceinline__ void gstore(void* base, uint32_t off, V v) {
+  __attribute__((address_space(1))) V* d = (__attribute__((address_space(1))) V*)((GChar*)base + off);
+  if constexpr (NTSTORE)
+    __builtin_nontemporal_store(v, d);
+  else
+    *d = v;
+}
+
 // Byte offsets, without the component part, of the nine slots pulled into
 // site (x, y): slot i of the site r - v_i.
 template <class S>
@@ -75,7 +98,7 @@ __device__ __forceinline__ void pulled_density(const void* __restrict__ fin, con
     if (k < p.n) {
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
-        const T raw = load_slot<S>(fin, off[i] + B::run(k, i), i);
+        const T raw = gload_slot<S>(fin, off[i] + B::run(k, i), i);
         led = i == 0 ? raw : led + raw;
         v[i] = decode<S, 2>(p.sh, k, i, raw);
       }
@@ -133,7 +156,7 @@ __device__ __forceinline__ void tile_step(const void* __restrict__ fin, void* __
         if (c < n) {
 #pragma unroll
           for (int i = 0; i < Q; ++i) {
-            const T raw = load_slot<S>(fin, off[i] + B::run(c, i), i);
+            const T raw = gload_slot<S>(fin, off[i] + B::run(c, i), i);
             l = i == 0 ? raw : l + raw;
             f[k][c][i] = decode<S, 2>(p.sh, c, i, raw);
           }
@@ -243,7 +266,6 @@ __device__ __forceinline__ void tile_step(const void* __restrict__ fin, void* __
                           Ay, Az);
       const T inv_rs = rcp_(rs[c]);
       collide<2, T>(f[k][c], rs[c], ux, uy, T(0), Ax, Ay, Az, jx[c] * inv_rs, jy[c] * inv_rs, T(0), p.inv_tau);
-      char* const out = static_cast<char*>(fout);
       if constexpr (S::kShift) {
         // FP16 deviations of the moving populations; the ledger keeps the rest
         T rest = led[k][c];
@@ -251,26 +273,12 @@ __device__ __forceinline__ void tile_step(const void* __restrict__ fin, void* __
         for (int i = 1; i < Q; ++i) {
           const _Float16 d = encode_move<2>(p.sh, c, i, f[k][c][i]);
           rest -= float(d);
-          _Float16* dst = reinterpret_cast<_Float16*>(out + (own + B::run(c, i) + B::in_run(i, x)));
-          if constexpr (NTSTORE)
-            __builtin_nontemporal_store(d, dst);
-          else
-            *dst = d;
+          gstore<NTSTORE>(fout, own + B::run(c, i) + B::in_run(i, x), d);
         }
-        float* dst0 = reinterpret_cast<float*>(out + (own + B::run(c, 0) + B::in_run(0, x)));
-        if constexpr (NTSTORE)
-          __builtin_nontemporal_store(rest, dst0);
-        else
-          *dst0 = rest;
+        gstore<NTSTORE>(fout, own + B::run(c, 0) + B::in_run(0, x), rest);
       } else {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-          T* dst = reinterpret_cast<T*>(out + (own + B::run(c, i) + B::in_run(i, x)));
-          if constexpr (NTSTORE)
-            __builtin_nontemporal_store(f[k][c][i], dst);
-          else
-            *dst = f[k][c][i];
-        }
+        for (int i = 0; i < Q; ++i) gstore<NTSTORE>(fout, own + B::run(c, i) + B::in_run(i, x), f[k][c][i]);
       }
     }
   }
