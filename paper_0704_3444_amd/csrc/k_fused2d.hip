@@ -422,8 +422,11 @@ static void launch_fused(const Ctx& c, const void* fin, void* fout) {
 template <class S, int NC>
 static FusedStepFn pick() {
   if constexpr (sizeof(typename S::T) == 4) {
+    // (the shifted codec also keeps a ledger per site and component: at
+    // N = 5 on 64x8 tiles the register pressure serialises the ring loads)
+    constexpr int kMid = S::kShift ? 4 : 5;
     if constexpr (NC <= 3) return launch_fused<S, NC, 64, 16>;
-    else if constexpr (NC <= 5) return launch_fused<S, NC, 64, 8>;
+    else if constexpr (NC <= kMid) return launch_fused<S, NC, 64, 8>;
     else return launch_fused<S, NC, 64, 4>;
   } else {
     if constexpr (NC <= 2) return launch_fused<S, NC, 64, 8>;

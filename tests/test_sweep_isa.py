@@ -81,3 +81,43 @@ def test_waits_after_staging_are_the_explicit_ones(asm):
                 assert explicit, (store, nc, i, line.strip())
             if explicit:
                 assert int(m.group(1)) in (0, 9 * nc), (store, nc, line.strip())
+
+
+TILE_KERNEL = re.compile(r"^(_ZN3lbm12k_(fused|batch)_d2q9INS_\d+(Store\w+?)ELi(\d)E\w*):", re.M)
+
+
+@pytest.fixture(scope="module")
+def tile_asm(tmp_path_factory):
+    if not shutil.which(B.HIPCC) and not os.path.exists(B.HIPCC):
+        pytest.skip("hipcc not available")
+    out = tmp_path_factory.mktemp("isa") / "tile.s"
+    flags = [f for f in B.FLAGS if f not in ("-fPIC", "-Wall")]
+    cmd = [B.HIPCC, *flags, "-S", "--cuda-device-only", os.path.join(B.CSRC, "k_fused2d.hip"), "-o", str(out)]
+    subprocess.run(cmd, check=True, capture_output=True)
+    return out.read_text()
+
+
+def test_tile_kernels_use_global_memory_instructions(tile_asm):
+    """The batched kernel reads its population pointers from the slot table;
+    the tile step must still reach them with global (not flat) loads and
+    stores, which would also count against the LDS counter."""
+    kernels = 0
+    for m in TILE_KERNEL.finditer(tile_asm):
+        end = tile_asm.index("s_endpgm", m.end())
+        body = tile_asm[m.end():end]
+        kernels += 1
+        assert "flat_load" not in body and "flat_store" not in body, m.group(1)
+        assert "global_load" in body and "global_store" in body, m.group(1)
+    assert kernels > 0
+
+
+def test_tile_kernel_loads_are_not_serialised(tile_asm):
+    """A component's pulled loads must be issued together: no global load is
+    followed straight away by a wait for all loads (a branch and a wait
+    around each 2-byte load once made the FP16 tile step twice as slow)."""
+    for m in TILE_KERNEL.finditer(tile_asm):
+        end = tile_asm.index("s_endpgm", m.end())
+        lines = [l.strip() for l in tile_asm[m.end():end].split("\n")]
+        serial = [j for j, l in enumerate(lines) if l.startswith("global_load")
+                  and any(lines[j + d].startswith("s_waitcnt vmcnt(0)") for d in (1, 2) if j + d < len(lines))]
+        assert len(serial) <= 8, (m.group(1), len(serial))
