@@ -18,7 +18,10 @@
 // left the caches, and keeping them out preserves L2 for the halo rows).  Workgroup
 // indices are remapped so that the eight XCDs (dispatched round-robin) each
 // sweep a contiguous band of tiles, keeping halo rows in their own L2.
-// No MFMA: the step is a bandwidth-bound stencil, not a contraction.
+// The kernel is templated on the storage codec (storage.hpp): FP64, FP32,
+// or shifted FP16 (decoded on load, the density from the site's ledger,
+// encoded on store).  No MFMA: the step is a bandwidth-bound stencil, not a
+// contraction.
 #include <hip/hip_runtime.h>
 
 #include "lbm_internal.hpp"

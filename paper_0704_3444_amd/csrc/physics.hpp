@@ -10,12 +10,13 @@
 // post-collision value f*_i computed at site r, so the population that sits
 // at site r at the next step is the one stored at r - v_i.
 //
-// Layout in HBM (pop_index): sites are grouped in blocks of 64 consecutive x
-// on one row (row = y + ny z); a block stores the N*Q populations of its 64
-// sites as N*Q contiguous runs of 64 values.  A wavefront that owns one
-// block reads and writes one contiguous N*Q*64-value region per step, so the
-// N*Q population streams do not land on the same HBM channels at the same
-// time (a plain structure of arrays puts them a power-of-two apart).
+// Layout in HBM (storage.hpp, BlockLayout): sites are grouped in blocks of
+// 64 consecutive x on one row (row = y + ny z); a block stores the N*Q
+// populations of its 64 sites as N*Q contiguous runs of 64 values.  A
+// wavefront that owns one block reads and writes one contiguous region per
+// step, so the N*Q population streams do not land on the same HBM channels
+// at the same time (a plain structure of arrays puts them a power-of-two
+// apart).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -249,11 +250,6 @@ __device__ __forceinline__ void lattice_force(const GH& h, const GR& r, T rho_s,
 }
 
 constexpr int kBlockX = 64;
-
-// Storage index of population q = sigma * Q + i of site (x, row).
-__device__ __forceinline__ long long pop_index(int nbx, int nq, int q, int x, long long row) {
-  return ((row * nbx + (x >> 6)) * nq + q) * kBlockX + (x & (kBlockX - 1));
-}
 
 // Periodic neighbour coordinate: x + d with d in {-1, 0, 1}.
 __device__ __forceinline__ int wrap_add(int x, int d, int n) {

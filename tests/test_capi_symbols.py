@@ -82,8 +82,9 @@ def test_batch_configurations_host_only():
         assert info["groups_per_cu"] in (2, 4, 8)
         seen.add((tx, ty, info["groups_per_cu"]))
     assert len(seen) == 18
+    assert lb.lb_batch_config_count("f16s", 3) == 18  # decoded to FP32: the FP32 tile shapes
     with pytest.raises(lb.LBError):
-        lb.lb_batch_config_count("f16s", 3)
+        lb.lb_batch_config_count("f32", 5)  # max_comp above 4
     with pytest.raises(lb.LBError):
         lb.lb_batch_config_info("f32", 3, 18)
 
