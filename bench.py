@@ -187,7 +187,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one GPU only (a single lattice per device; multi-GPU "
+        print("bench.py: measures one GPU only (a single lattice per device; multi-GPU "
               "slab decomposition is not implemented); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.calibrate_copy:

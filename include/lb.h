@@ -44,7 +44,7 @@ typedef enum lb_status {
   LB_OK = 0,
   LB_EINVAL = -1,    /* invalid argument or parameter (message: lb_last_error) */
   LB_ENOMEM = -2,    /* device or host allocation failed, or workspace too small */
-  LB_ENOTSUP = -3,   /* valid but not supported by this build                   */
+  LB_ENOTSUP = -3,   /* valid but not supported by this library                 */
   LB_EDEVICE = -4,   /* a HIP runtime call failed                               */
   LB_ENUMERIC = -5   /* a non-finite or non-positive density was detected       */
 } lb_status;
