@@ -285,6 +285,46 @@ int lb_batch_tune(lb_batch* b, int32_t steps, double* ms_per_step, int32_t* best
 /* Free the batch, its slots and its arena (waits for both streams). */
 void lb_batch_free(lb_batch* b);
 
+/* ------------------------------------------------------------------------
+ * Groups of one-dimensional runs (the phase-equilibrium experiments of
+ * Sec. IV: D1Q3 lines, one run per interaction strength, relaxation time or
+ * starting composition).
+ *
+ * A group steps the runs of several contexts made by lb_init with one
+ * kernel launch per call: one wavefront holds a whole line in registers and
+ * takes all nsteps steps there, reading and writing the populations in
+ * device memory once per call.  A run's populations after lb_lines_step are
+ * bit for bit those lb_step gives it.  The contexts stay usable as before
+ * (lb_moments, lb_get_f, checkpoints) and keep their step counters.
+ *
+ * Requirements on the contexts: lattice LB_D1Q3, storage LB_F64 or LB_F32,
+ * nx = 64, 128, 192 or 256, N <= 4; within a group the same N, storage, nx
+ * and stream; no context twice.  Parameters of Eq. (ssLB) and Eq. (lgf)
+ * (tau, theta, m, chi, kappa, force form) may differ between runs.
+ * ------------------------------------------------------------------------ */
+typedef struct lb_lines lb_lines;
+
+/* Form a group of n contexts (ctxs[0..n-1], host array of handles; the
+ * library keeps the handles, not the array).  Uploads a table of the runs'
+ * parameters and population addresses to device memory and waits for it.
+ * The contexts must have taken steps of the same parity (e.g. all freshly
+ * made) and must outlive the group.  Errors: LB_EINVAL (NULL, duplicates,
+ * mixed N / storage / nx / stream / parity), LB_ENOTSUP (lattice, storage,
+ * nx or N outside the requirements), LB_ENOMEM, LB_EDEVICE. */
+int lb_lines_create(lb_ctx* const* ctxs, int32_t n, lb_lines** out);
+
+/* Advance every run of the group by nsteps steps, asynchronously on the
+ * group's stream; each context's step counter grows by nsteps.  A density
+ * that is not finite and > 0 in any step sets the context's health flag
+ * (lb_moments then returns LB_ENUMERIC); the periodic checks of
+ * check_every are not run.  Errors: LB_EINVAL (nsteps < 0, or a context
+ * stepped outside the group since), LB_EDEVICE. */
+int lb_lines_step(lb_lines* g, int64_t nsteps);
+
+/* Release the group (not its contexts); waits for the group's stream.  NULL
+ * is a no-op. */
+void lb_lines_free(lb_lines* g);
+
 /* Static description of a status code. */
 const char* lb_strerror(int code);
 

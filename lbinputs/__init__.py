@@ -221,3 +221,69 @@ WORKLOADS = {
     "ternary_d3q19_256": lambda: ternary_d3q19(256),
     "five_d2q9_512": lambda: five_component(512),
 }
+
+
+# --------------------------------------------------------------------------
+# Phase-equilibrium experiments of Sec. IV: periodic D1Q3 lines.
+# --------------------------------------------------------------------------
+
+LINE_SITES = 128  # the paper does not give the line length; any L = 64 P works
+
+
+def _line(n_comp, m, chi, inv_tau, phi0, L=LINE_SITES, theta=1.0 / 3.0):
+    p = params("D1Q3", n_comp, (L,), tau=1.0 / inv_tau, theta=theta, kappa=0.0, m=m, chi=chi)
+    return p, sine_profile(p, phi0, amp=0.1)
+
+
+def binodal_runs(experiment: str, L: int = LINE_SITES, theta: float = 1.0 / 3.0):
+    """Run sets of the binodal experiments of Sec. IV (Figs. 1 and 3): each
+    entry is (cfg, rho0, label).  kappa = 0, total density 1 (the paper's
+    100; with kappa = 0 the update is homogeneous of degree one in f),
+    theta = 1/3 unless given (the paper does not state it), the sine
+    perturbation of amplitude 0.1 over the line.
+
+    binary_monomer   m = (1, 1), phi0 = (1/2, 1/2), 1/tau = 0.7 and 0.9,
+                     chi^AB = 2.05 ... 3.50 (critical value 2)
+    binary_polymer   m = (10, 1), phi0 = (0.24, 0.76), 1/tau = 0.9,
+                     chi^AB = 0.88 ... 1.50 (critical value 0.866)
+    ternary_monomer  m = (1, 1, 1), chi^AB = 3, chi^AC = 0.5, chi^BC = 0.2,
+                     1/tau = 0.9, phi0 on the segment from the critical point
+                     the paper quotes, (0.32, 0.32, 0.36), towards
+                     (0.5, 0.5, 0): phi0 = c + s ((0.5, 0.5, 0) - c),
+                     s = 0.05 ... 0.95
+    ternary_polymer  m = (10, 1, 1), same chi, segment from (0.14, 0.11, 0.75)
+    """
+    runs = []
+    if experiment == "binary_monomer":
+        for inv_tau in (0.7, 0.9):
+            for chi in np.round(np.arange(2.05, 3.5001, 0.05), 2):
+                p, r = _line(2, (1, 1), _chi(2, {(0, 1): chi}), inv_tau, (0.5, 0.5), L, theta)
+                runs.append((p, r, f"1/tau={inv_tau} chi={chi:.2f}"))
+    elif experiment == "binary_polymer":
+        for chi in np.round(np.arange(0.88, 1.5001, 0.02), 2):
+            p, r = _line(2, (10, 1), _chi(2, {(0, 1): chi}), 0.9, (0.24, 0.76), L, theta)
+            runs.append((p, r, f"chi={chi:.2f}"))
+    elif experiment in ("ternary_monomer", "ternary_polymer"):
+        m = (1, 1, 1) if experiment == "ternary_monomer" else (10, 1, 1)
+        crit = np.array((0.32, 0.32, 0.36) if experiment == "ternary_monomer" else (0.14, 0.11, 0.75))
+        end = np.array((0.5, 0.5, 0.0))
+        chi = _chi(3, {(0, 1): 3.0, (0, 2): 0.5, (1, 2): 0.2})
+        for s in np.round(np.arange(0.05, 0.9501, 0.05), 2):
+            phi0 = crit + s * (end - crit)
+            p, r = _line(3, m, chi, 0.9, phi0, L, theta)
+            runs.append((p, r, f"s={s:.2f}"))
+    else:
+        raise ValueError(f"unknown experiment {experiment!r}")
+    return runs
+
+
+def profile_run(experiment: str, L: int = LINE_SITES):
+    """The single runs behind the profile figures of Sec. IV: binary polymer
+    m = (10, 1), chi^AB = 0.94 from phi0 = (0.24, 0.76) (Fig. 2); ternary
+    polymer m = (10, 1, 1) with the chi of Fig. 3 from phi0 =
+    (0.14, 0.11, 0.75) (Fig. 4); 1/tau = 0.9, kappa = 0."""
+    if experiment == "binary_polymer_profile":
+        return _line(2, (10, 1), _chi(2, {(0, 1): 0.94}), 0.9, (0.24, 0.76), L)
+    if experiment == "ternary_polymer_profile":
+        return _line(3, (10, 1, 1), _chi(3, {(0, 1): 3.0, (0, 2): 0.5, (1, 2): 0.2}), 0.9, (0.14, 0.11, 0.75), L)
+    raise ValueError(f"unknown experiment {experiment!r}")

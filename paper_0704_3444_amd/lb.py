@@ -30,6 +30,7 @@ EXPORTS = [
     "lb_batch_create", "lb_batch_footprint", "lb_batch_add", "lb_batch_step", "lb_batch_poll",
     "lb_batch_moments", "lb_batch_remove", "lb_batch_config_count", "lb_batch_config_info",
     "lb_batch_set_config", "lb_batch_tune", "lb_batch_free",
+    "lb_lines_create", "lb_lines_step", "lb_lines_free",
 ]
 
 
@@ -109,10 +110,15 @@ def load() -> C.CDLL:
     lib.lb_batch_tune.argtypes = [bp, C.c_int32, dp, i32p]
     lib.lb_batch_free.argtypes = [bp]
     lib.lb_batch_free.restype = None
+    lib.lb_lines_create.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(vp)]
+    lib.lb_lines_step.argtypes = [vp, C.c_int64]
+    lib.lb_lines_free.argtypes = [vp]
+    lib.lb_lines_free.restype = None
     for name in ("lb_init", "lb_step", "lb_moments", "lb_get_f", "lb_get_state", "lb_set_state",
                  "lb_lattice_tables", "lb_path_in_use", "lb_batch_create", "lb_batch_add", "lb_batch_step",
                  "lb_batch_poll", "lb_batch_moments", "lb_batch_remove", "lb_batch_config_count",
-                 "lb_batch_config_info", "lb_batch_set_config", "lb_batch_tune"):
+                 "lb_batch_config_info", "lb_batch_set_config", "lb_batch_tune", "lb_lines_create",
+                 "lb_lines_step"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -375,6 +381,48 @@ class Batch:
         if getattr(self, "h", None):
             load().lb_batch_free(C.c_void_p(self.h))
             self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------ line groups
+def lb_lines_create(ctxs) -> int:
+    arr = (C.c_void_p * len(ctxs))(*ctxs)
+    out = C.c_void_p()
+    _check(load().lb_lines_create(arr, len(ctxs), C.byref(out)))
+    return out.value
+
+
+def lb_lines_step(group: int, nsteps: int) -> None:
+    _check(load().lb_lines_step(C.c_void_p(group), nsteps))
+
+
+def lb_lines_free(group: int) -> None:
+    if group:
+        load().lb_lines_free(C.c_void_p(group))
+
+
+class Lines:
+    """Several D1Q3 Simulations stepped together (lb_lines_* of the C ABI):
+    one wavefront per run holds the whole line in registers for all the
+    steps of a call.  The Simulations stay usable for moments(), get_f()
+    and checkpoints, and must outlive the group."""
+
+    def __init__(self, sims):
+        self.sims = list(sims)
+        self.group = lb_lines_create([s.ctx for s in self.sims])
+
+    def step(self, n: int) -> None:
+        lb_lines_step(self.group, n)
+
+    def close(self) -> None:
+        if getattr(self, "group", None):
+            lb_lines_free(self.group)
+            self.group = None
 
     def __del__(self):
         try:
