@@ -13,12 +13,14 @@ peak: its algorithmic traffic per launch is every population read once and
 written once, 2 * N * S * (rest + (Q - 1) * moving slot bytes).  `cpu_baseline` times the FP64 CPU
 oracle on a bounded sample of the same workload on the host cores.
 
-Two more objects on the same line (skipped with --no-f16s / --no-serving):
-`f16s` times the same workload with shifted FP16 storage; `serving` runs a
-Poisson mix of 256 phase-separation requests (N 2 or 3, square boxes of
-side 64..512, 5000 steps each) through the continuous-batching loop and,
-for comparison, one request at a time, and reports p50/p99 latency and
-throughput of both.
+Three more objects on the same line (skipped with --no-f16s / --no-serving /
+--no-phase): `f16s` times the same workload with shifted FP16 storage;
+`serving` runs a Poisson mix of 256 phase-separation requests (N 2 or 3,
+square boxes of side 64..512, 5000 steps each) through the
+continuous-batching loop and, for comparison, one request at a time, and
+reports p50/p99 latency and throughput of both; `phase_sweeps` times the
+four binodal run sets of Sec. IV (D1Q3 lines of 128 sites, the paper's step
+counts) through line groups, one launch per set.
 """
 import argparse
 import hashlib
@@ -92,6 +94,55 @@ def cpu_baseline(cfg, rho0, target_s=15.0):
     return {"value": round(value, 3), "unit": "MLUPS×components", "cores": threads, "kind": "oracle",
             "sample": f"{n} steps (after 1 warm-up step) of the full {cfg['shape'][0]}x{cfg['shape'][1]} "
                       f"N={cfg['n_comp']} workload from its initial state, FP64, {dt:.1f} s"}
+
+
+def cpu_line_baseline(target_s=5.0):
+    """FP64 oracle on one ternary D1Q3 line of the binodal experiments (one
+    host core: a single row), as many steps as fit in about target_s."""
+    from oracle import Oracle, OracleParams
+    import lbinputs as LI
+
+    cfg, rho0, _ = LI.binodal_runs("ternary_monomer")[9]
+    o = Oracle(OracleParams(**cfg), rho0)
+    t0 = time.perf_counter()
+    o.step(1000)
+    n = max(1000, int(target_s / max(time.perf_counter() - t0, 1e-6) * 1000))
+    t0 = time.perf_counter()
+    o.step(n)
+    dt = time.perf_counter() - t0
+    return {"value": round(cfg["shape"][0] * cfg["n_comp"] * n / dt / 1e6, 3), "unit": "MLUPS×components",
+            "sample": f"{n} steps of one 128-site ternary D1Q3 line, FP64, {dt:.1f} s"}
+
+
+def run_phase_sweeps():
+    """The binodal run sets of Sec. IV, each stepped by one line group for the
+    paper's step count; the timed region is the group's single launch."""
+    import torch
+    import lbinputs as LI
+    from paper_0704_3444_amd import Lines, Simulation
+
+    out = {}
+    for exp, steps in (("binary_monomer", 50000), ("binary_polymer", 50000), ("ternary_monomer", 200000),
+                       ("ternary_polymer", 200000)):
+        runs = LI.binodal_runs(exp)
+        sims = [Simulation(c, r) for c, r, _ in runs]
+        group = Lines(sims)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        group.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        healthy = sum(1 for x in sims if x.moments(fields=False, raise_numeric=False)["status"] == 0)
+        group.close()
+        n = runs[0][0]["n_comp"]
+        L = runs[0][0]["shape"][0]
+        out[exp] = {"runs": len(runs), "steps": steps, "seconds": round(dt, 4),
+                    "us_per_step": round(dt / steps * 1e6, 3),
+                    "value": round(len(runs) * L * n * steps / dt / 1e6, 1), "unit": "MLUPS×components",
+                    "healthy_runs": healthy}
+        for x in sims:
+            x.close()
+    return out
 
 
 def calibrate_copy(gib=1.0, reps=5):
@@ -183,6 +234,7 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--no-f16s", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-phase", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=256)
     args = ap.parse_args()
 
@@ -239,10 +291,16 @@ def main():
     if not args.no_serving:
         serving = run_serving(args.serving_requests)
 
+    phase_sweeps = None
+    if not args.no_phase:
+        phase_sweeps = run_phase_sweeps()
+
     cpu = None
     if not args.no_cpu:
         print("bench: timing the CPU oracle on the same workload", file=sys.stderr, flush=True)
         cpu = cpu_baseline(cfg, rho0)
+        if phase_sweeps is not None:
+            cpu["line_run"] = cpu_line_baseline()
 
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "MLUPS×components", "n_gpus": 1,
@@ -253,7 +311,7 @@ def main():
                    "n_comp": N, "storage": args.storage, "path": path, "force_form": cfg["force_form"]},
         "hbm_frac": round(achieved / HBM_PEAK_GBS, 4),
         "wall_s": round(wall, 4), "mass_drift": mass_drift, "status": health["status"],
-        "roofline": roofline, "cpu_baseline": cpu, "f16s": f16s, "serving": serving,
+        "roofline": roofline, "cpu_baseline": cpu, "f16s": f16s, "serving": serving, "phase_sweeps": phase_sweeps,
     }
     print(json.dumps(line), flush=True)
 

@@ -228,11 +228,22 @@ WORKLOADS = {
 # --------------------------------------------------------------------------
 
 LINE_SITES = 128  # the paper does not give the line length; any L = 64 P works
+# Plait points of the ternary systems of Fig. 3 (chi^AB = 3, chi^AC = 0.5,
+# chi^BC = 0.2) for m = (1, 1, 1) and (10, 1, 1), rounded to 1e-4; computed
+# with the Flory-Huggins theory tools of the test suite, which check them.
+PLAIT_MONOMER = (0.3568, 0.3078, 0.3354)
+PLAIT_POLYMER = (0.1659, 0.0752, 0.7589)
 
 
-def _line(n_comp, m, chi, inv_tau, phi0, L=LINE_SITES, theta=1.0 / 3.0):
+LINE_NOISE = 1e-6  # seeded noise on every line's start, see binodal_runs
+
+
+def _line(n_comp, m, chi, inv_tau, phi0, L=LINE_SITES, theta=1.0 / 3.0, amp=0.1, seed=1010):
     p = params("D1Q3", n_comp, (L,), tau=1.0 / inv_tau, theta=theta, kappa=0.0, m=m, chi=chi)
-    return p, sine_profile(p, phi0, amp=0.1)
+    r = sine_profile(p, phi0, amp=amp)
+    for c in range(n_comp):
+        r[c] += LINE_NOISE * (2.0 * uniform(seed, c, L) - 1.0)
+    return p, r
 
 
 def binodal_runs(experiment: str, L: int = LINE_SITES, theta: float = 1.0 / 3.0):
@@ -240,7 +251,11 @@ def binodal_runs(experiment: str, L: int = LINE_SITES, theta: float = 1.0 / 3.0)
     entry is (cfg, rho0, label).  kappa = 0, total density 1 (the paper's
     100; with kappa = 0 the update is homogeneous of degree one in f),
     theta = 1/3 unless given (the paper does not state it), the sine
-    perturbation of amplitude 0.1 over the line.
+    perturbation of amplitude 0.1 over the line, plus seeded noise of
+    amplitude 1e-6 on every component (seed 1010 + the run's index): on
+    these lines modes of a few sites outgrow the sine, and without the noise
+    they would grow from the rounding of the arithmetic, so that the domain
+    pattern would depend on the order of operations of each implementation.
 
     binary_monomer   m = (1, 1), phi0 = (1/2, 1/2), 1/tau = 0.7 and 0.9,
                      chi^AB = 2.05 ... 3.50 (critical value 2)
@@ -252,25 +267,38 @@ def binodal_runs(experiment: str, L: int = LINE_SITES, theta: float = 1.0 / 3.0)
                      (0.5, 0.5, 0): phi0 = c + s ((0.5, 0.5, 0) - c),
                      s = 0.05 ... 0.95
     ternary_polymer  m = (10, 1, 1), same chi, segment from (0.14, 0.11, 0.75)
+    ternary_monomer_plait, ternary_polymer_plait
+                     the same segments started from the plait points of
+                     Eq. (lgf) for these chi (PLAIT_MONOMER, PLAIT_POLYMER;
+                     the quoted critical points lie a few 1e-2 away), with a
+                     perturbation of amplitude 0.05 (0.1 would make phi^B
+                     negative next to the polymer plait point)
     """
     runs = []
     if experiment == "binary_monomer":
         for inv_tau in (0.7, 0.9):
             for chi in np.round(np.arange(2.05, 3.5001, 0.05), 2):
-                p, r = _line(2, (1, 1), _chi(2, {(0, 1): chi}), inv_tau, (0.5, 0.5), L, theta)
+                p, r = _line(2, (1, 1), _chi(2, {(0, 1): chi}), inv_tau, (0.5, 0.5), L, theta,
+                             seed=1010 + len(runs))
                 runs.append((p, r, f"1/tau={inv_tau} chi={chi:.2f}"))
     elif experiment == "binary_polymer":
         for chi in np.round(np.arange(0.88, 1.5001, 0.02), 2):
-            p, r = _line(2, (10, 1), _chi(2, {(0, 1): chi}), 0.9, (0.24, 0.76), L, theta)
+            p, r = _line(2, (10, 1), _chi(2, {(0, 1): chi}), 0.9, (0.24, 0.76), L, theta, seed=1010 + len(runs))
             runs.append((p, r, f"chi={chi:.2f}"))
-    elif experiment in ("ternary_monomer", "ternary_polymer"):
-        m = (1, 1, 1) if experiment == "ternary_monomer" else (10, 1, 1)
-        crit = np.array((0.32, 0.32, 0.36) if experiment == "ternary_monomer" else (0.14, 0.11, 0.75))
+    elif experiment.startswith(("ternary_monomer", "ternary_polymer")):
+        polymer = experiment.startswith("ternary_polymer")
+        m = (10, 1, 1) if polymer else (1, 1, 1)
+        if experiment.endswith("_plait"):
+            crit = np.array(PLAIT_POLYMER if polymer else PLAIT_MONOMER)
+            amp = 0.05
+        else:
+            crit = np.array((0.14, 0.11, 0.75) if polymer else (0.32, 0.32, 0.36))
+            amp = 0.1
         end = np.array((0.5, 0.5, 0.0))
         chi = _chi(3, {(0, 1): 3.0, (0, 2): 0.5, (1, 2): 0.2})
         for s in np.round(np.arange(0.05, 0.9501, 0.05), 2):
             phi0 = crit + s * (end - crit)
-            p, r = _line(3, m, chi, 0.9, phi0, L, theta)
+            p, r = _line(3, m, chi, 0.9, phi0, L, theta, amp=amp, seed=1010 + len(runs))
             runs.append((p, r, f"s={s:.2f}"))
     else:
         raise ValueError(f"unknown experiment {experiment!r}")

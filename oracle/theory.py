@@ -135,3 +135,51 @@ def coexistence(phi_mean, m, chi, guess_a, guess_b, theta=1.0 / 3.0):
         raise RuntimeError(msg)
     pa, pb, lam = unpack(sol)
     return pa, pb, float(lam)
+
+
+# ---------------------------------------------------- three components ----
+
+def _ternary_hessian(pa, pb, m, chi):
+    """Hessian of the mixing free energy per site, f = sum_s phi_s ln(phi_s)/m_s
+    + sum_{s<t} chi^{st} phi_s phi_t (Eq. (lgf) divided by the total mer
+    density; theta and the terms linear in phi drop out of phase behaviour),
+    in the independent fractions (phi_A, phi_B), phi_C = 1 - phi_A - phi_B."""
+    pc = 1.0 - pa - pb
+    mA, mB, mC = m
+    g = 1.0 / (mC * pc)
+    haa = 1.0 / (mA * pa) + g - 2.0 * chi[0][2]
+    hbb = 1.0 / (mB * pb) + g - 2.0 * chi[1][2]
+    hab = g + chi[0][1] - chi[0][2] - chi[1][2]
+    return haa, hab, hbb
+
+
+def _ternary_critical_residual(x, m, chi):
+    pa, pb = x
+    pc = 1.0 - pa - pb
+    if pa <= 0 or pb <= 0 or pc <= 0:
+        return [1e3, 1e3]
+    haa, hab, hbb = _ternary_hessian(pa, pb, m, chi)
+    det = haa * hbb - hab * hab
+    # null direction of the Hessian on the spinodal
+    va, vb = (-hab, haa) if abs(haa) >= abs(hbb) else (hbb, -hab)
+    nrm = np.hypot(va, vb)
+    va, vb = va / nrm, vb / nrm
+    mA, mB, mC = m
+    gc = 1.0 / (mC * pc * pc)
+    faaa = -1.0 / (mA * pa * pa) + gc
+    fbbb = -1.0 / (mB * pb * pb) + gc
+    third = faaa * va ** 3 + 3.0 * gc * va * va * vb + 3.0 * gc * va * vb * vb + fbbb * vb ** 3
+    return [det, third]
+
+
+def ternary_plait_point(m, chi, guess):
+    """Critical (plait) point of a three-component Flory-Huggins mixture:
+    the spinodal det H = 0 where the third derivative of f along the null
+    direction of H also vanishes.  Returns (phi_A, phi_B, phi_C)."""
+    chi = np.asarray(chi, float)
+    sol, info, ier, msg = optimize.fsolve(_ternary_critical_residual, np.asarray(guess[:2], float),
+                                          args=(tuple(m), chi), full_output=True, xtol=1e-12)
+    r = _ternary_critical_residual(sol, tuple(m), chi)
+    if max(abs(r[0]), abs(r[1])) > 1e-8:
+        raise RuntimeError(f"plait point residual {r}")
+    return np.array([sol[0], sol[1], 1.0 - sol[0] - sol[1]])

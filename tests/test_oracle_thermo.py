@@ -109,3 +109,44 @@ def test_symmetric_ncomponent_critical_interaction():
             return np.linalg.eigvalsh(0.5 * (H + H.T)).min()
         assert hess_min_eig(0.98 * n) > 0
         assert hess_min_eig(1.02 * n) < 0
+
+
+def test_ternary_plait_point():
+    """Critical point of three components: closed form for a neutral third
+    component (chi^AC = chi^BC = 0, m = 1): the exchange mode of A and B at
+    phi_A = phi_B = x has f_AA - f_AB = 1/x - chi, so the plait point is
+    (1/chi, 1/chi, 1 - 2/chi).  For the systems of Fig. 3 the point must lie
+    on the spinodal of the complex-step chemical potentials (an independent
+    route to the Hessian) and differ from the quoted critical points by a
+    few 1e-2 (reading R16)."""
+    for chi in (2.5, 3.0, 4.0):
+        c = np.array([[0, chi, 0], [chi, 0, 0], [0, 0, 0.0]])
+        p = T.ternary_plait_point((1, 1, 1), c, (0.3, 0.35))
+        assert np.abs(p - [1 / chi, 1 / chi, 1 - 2 / chi]).max() < 1e-10
+    chi3 = np.array([[0, 3.0, 0.5], [3.0, 0, 0.2], [0.5, 0.2, 0]])
+    for m, quoted in (((1, 1, 1), (0.32, 0.32, 0.36)), ((10, 1, 1), (0.14, 0.11, 0.75))):
+        p = T.ternary_plait_point(m, chi3, quoted)
+        H = np.zeros((2, 2))
+        h = 1e-6
+        for a in range(2):
+            d = np.zeros(3)
+            d[a], d[2] = 1, -1
+            dmu = (T.mu_per_mer(p + h * d, m, chi3) - T.mu_per_mer(p - h * d, m, chi3)) / (2 * h)
+            for b in range(2):
+                e = np.zeros(3)
+                e[b], e[2] = 1, -1
+                H[a, b] = dmu @ e / (1.0 / 3.0)  # mu carries theta = 1/3
+        eig = np.linalg.eigvalsh(0.5 * (H + H.T))
+        assert abs(eig[0]) < 1e-6 * abs(eig[1]), eig
+        assert 0.01 < np.abs(p - quoted).max() < 0.06
+
+
+def test_plait_points_of_the_inputs():
+    """The starting points of the plait-point run sets in lbinputs are the
+    plait points of the theory tools, to their stated rounding."""
+    import lbinputs as LI
+
+    chi3 = np.array([[0, 3.0, 0.5], [3.0, 0, 0.2], [0.5, 0.2, 0]])
+    for m, stored in (((1, 1, 1), LI.PLAIT_MONOMER), ((10, 1, 1), LI.PLAIT_POLYMER)):
+        p = T.ternary_plait_point(m, chi3, stored)
+        assert np.abs(p - stored).max() < 6e-5
