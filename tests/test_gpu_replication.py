@@ -154,3 +154,46 @@ def test_ternary_binodal_sweep(experiment):
             near.append(d)
     if experiment == "ternary_monomer":
         assert len(near) >= 3 and max(near) < 0.015, near
+
+
+def profile_stats(rho, mu):
+    """Differences between the bulk phases (centres of the widest domains)
+    and ranges over the whole line: total density (relative) and each mu."""
+    from paper_0704_3444_amd.phase import _domains
+
+    rt = rho.sum(axis=0)
+    a = rho[0] / rt
+    mid = 0.5 * (a.max() + a.min())
+    centre = {}
+    for name, mask in (("rich", a > mid), ("poor", a <= mid)):
+        s, n = max(_domains(mask), key=lambda d: d[1])
+        centre[name] = (s + n // 2) % a.size
+    i, j = centre["rich"], centre["poor"]
+    out = {"drho_bulk": abs(rt[i] - rt[j]) / rt.mean(), "drho_range": float(np.ptp(rt) / rt.mean())}
+    for k in range(mu.shape[0]):
+        out[f"mu{k}_bulk"] = abs(mu[k, i] - mu[k, j])
+        out[f"mu{k}_range"] = float(np.ptp(mu[k]))
+    return out
+
+
+def test_polymer_profiles():
+    """Figs. 2 and 4: the binary polymer profile at chi = 0.94 (theta = 1/3
+    and, since the paper does not give theta, theta = 1), at equilibrium
+    after 500 000 steps; the ternary polymer start (0.14, 0.11, 0.75).
+    Printed beside the paper's figures; asserted: the polymer's potential
+    varies more than the solvent's, and the density stays within 1%."""
+    from paper_0704_3444_amd import phase
+
+    cfg, rho0 = LI.profile_run("binary_polymer_profile")
+    runs = [(cfg, rho0, "theta=1/3"), (dict(cfg, theta=1.0), rho0, "theta=1")]
+    for (c, _, label), r in zip(runs, phase.run_lines(runs, 500000)):
+        assert r["healthy"], label
+        st = profile_stats(r["rho"], r["mu"])
+        print(f"[replication] Fig. 2 profile {label}: drho/rho bulk {st['drho_bulk']:.1e} range {st['drho_range']:.1e}; "
+              f"mu^A bulk {st['mu0_bulk']:.1e} range {st['mu0_range']:.1e}; mu^B bulk {st['mu1_bulk']:.1e} "
+              f"range {st['mu1_range']:.1e} (paper: < 1e-5; 2e-2, 4e-2; < 1e-4, 1e-3)", flush=True)
+        assert st["mu0_range"] > st["mu1_range"] and st["drho_range"] < 1e-2
+    cfg3, rho3 = LI.profile_run("ternary_polymer_profile")
+    r3 = phase.run_lines([(cfg3, rho3, "")], 200000)[0]
+    print(f"[replication] Fig. 4 profile: {'healthy' if r3['healthy'] else 'unstable'} after 200000 steps",
+          flush=True)
