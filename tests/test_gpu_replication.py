@@ -195,5 +195,12 @@ def test_polymer_profiles():
         assert st["mu0_range"] > st["mu1_range"] and st["drho_range"] < 1e-2
     cfg3, rho3 = LI.profile_run("ternary_polymer_profile")
     r3 = phase.run_lines([(cfg3, rho3, "")], 200000)[0]
-    print(f"[replication] Fig. 4 profile: {'healthy' if r3['healthy'] else 'unstable'} after 200000 steps",
-          flush=True)
+    if not r3["healthy"]:
+        print("[replication] Fig. 4 profile: unstable within 200000 steps", flush=True)
+        return
+    st = profile_stats(r3["rho"], r3["mu"])
+    ph = phase.coexisting_phases(r3["rho"])
+    print(f"[replication] Fig. 4 profile after 200000 steps: phases {np.round(ph['rich'], 4)} | "
+          f"{np.round(ph['poor'], 4)}; drho/rho bulk {st['drho_bulk']:.1e} range {st['drho_range']:.1e}; "
+          f"mu^A bulk {st['mu0_bulk']:.1e}; mu^B bulk {st['mu1_bulk']:.1e}; mu^C bulk {st['mu2_bulk']:.1e} "
+          f"(paper: < 1e-4 bulk, < 1e-2 interface; 2e-2; < 1e-4; < 1e-4)", flush=True)
