@@ -198,8 +198,11 @@ def test_polymer_profiles():
     if not r3["healthy"]:
         print("[replication] Fig. 4 profile: unstable within 200000 steps", flush=True)
         return
-    st = profile_stats(r3["rho"], r3["mu"])
     ph = phase.coexisting_phases(r3["rho"])
+    if ph is None:
+        print("[replication] Fig. 4 profile: not separated after 200000 steps", flush=True)
+        return
+    st = profile_stats(r3["rho"], r3["mu"])
     print(f"[replication] Fig. 4 profile after 200000 steps: phases {np.round(ph['rich'], 4)} | "
           f"{np.round(ph['poor'], 4)}; drho/rho bulk {st['drho_bulk']:.1e} range {st['drho_range']:.1e}; "
           f"mu^A bulk {st['mu0_bulk']:.1e}; mu^B bulk {st['mu1_bulk']:.1e}; mu^C bulk {st['mu2_bulk']:.1e} "
