@@ -235,6 +235,7 @@ def main():
     ap.add_argument("--no-f16s", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-phase", action="store_true")
+    ap.add_argument("--only-phase", action="store_true", help="time only the phase sweeps (for profiling them)")
     ap.add_argument("--serving-requests", type=int, default=256)
     args = ap.parse_args()
 
@@ -254,6 +255,11 @@ def main():
     if not os.path.exists(lb.LIB_PATH):
         from paper_0704_3444_amd import build as gpu_build
         gpu_build.build()
+
+    if args.only_phase:
+        torch.cuda.set_device(0)
+        print(json.dumps({"phase_sweeps": run_phase_sweeps()}), flush=True)
+        return
 
     cfg, rho0 = workload(args.workload)
     shape = list(cfg["shape"]) + [1] * (3 - len(cfg["shape"]))
