@@ -96,6 +96,62 @@ def cpu_baseline(cfg, rho0, target_s=15.0):
                       f"N={cfg['n_comp']} workload from its initial state, FP64, {dt:.1f} s"}
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+_ONE_CORE = """
+import json, sys, time
+sys.path.insert(0, {root!r})
+import lbinputs as LI
+from oracle import Oracle, OracleParams
+cfg, rho0 = LI.ternary_immersion(2048)
+o = Oracle(OracleParams(**cfg), rho0)
+t0 = time.perf_counter(); o.step(1); t1 = time.perf_counter() - t0
+n = min(20, int({target} / max(t1, 1e-6)))
+if n < 2:
+    print(json.dumps({{"steps": 1, "seconds": t1}}))
+else:
+    t0 = time.perf_counter(); o.step(n); dt = time.perf_counter() - t0
+    print(json.dumps({{"steps": n, "seconds": dt}}))
+"""
+
+
+def cpu_single_core(target_s=10.0):
+    """The same oracle sample on one host core (a child process with
+    OMP_NUM_THREADS=1, since the thread count is fixed once OpenMP starts)."""
+    import subprocess
+
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, "-c", _ONE_CORE.format(root=ROOT, target=target_s)], env=env,
+                         capture_output=True, text=True, timeout=600, check=True)
+    r = json.loads(out.stdout.strip().splitlines()[-1])
+    value = 2048 * 2048 * 3 * r["steps"] / r["seconds"] / 1e6
+    return {"value": round(value, 3), "unit": "MLUPS×components", "cores": 1,
+            "sample": f"{r['steps']} steps of the full 2048x2048 N=3 workload, FP64, {r['seconds']:.1f} s"}
+
+
+def cpu_small_full_run():
+    """The oracle over the whole small binary case (64x64, 2000 steps), all host cores."""
+    from oracle import Oracle, OracleParams
+    import lbinputs as LI
+
+    cfg, rho0 = LI.binary_spinodal(64)
+    o = Oracle(OracleParams(**cfg), rho0)
+    t0 = time.perf_counter()
+    o.step(2000)
+    dt = time.perf_counter() - t0
+    return {"workload": "binary_d2q9_64", "steps": 2000, "seconds": round(dt, 3),
+            "value": round(64 * 64 * 2 * 2000 / dt / 1e6, 3), "unit": "MLUPS×components"}
+
+
 def cpu_line_baseline(target_s=5.0):
     """FP64 oracle on one ternary D1Q3 line of the binodal experiments (one
     host core: a single row), as many steps as fit in about target_s."""
@@ -305,6 +361,11 @@ def main():
     if not args.no_cpu:
         print("bench: timing the CPU oracle on the same workload", file=sys.stderr, flush=True)
         cpu = cpu_baseline(cfg, rho0)
+        cpu["cpu_model"] = cpu_model()
+        cpu["host_cpus"] = len(os.sched_getaffinity(0))
+        if args.workload == "ternary_d2q9_2048":
+            cpu["single_core"] = cpu_single_core()
+        cpu["small_full_run"] = cpu_small_full_run()
         if phase_sweeps is not None:
             cpu["line_run"] = cpu_line_baseline()
 
