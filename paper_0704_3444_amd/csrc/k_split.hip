@@ -3,7 +3,7 @@
 // The split step runs three kernels: k_density (rho^sigma), k_potential
 // (mu^sigma and the potential the force differentiates) and k_collide
 // (force, equilibrium, forcing term, BGK, and the write that streams by
-// pull).  It is the path for D1Q3 and D3Q19 and the cross-check of the
+// pull; k_collide_nc for N <= 4).  It is the path for D1Q3 and D3Q19 and the cross-check of the
 // fused D2Q9 kernel.  The same kernels, instantiated in FP64, produce the
 // observables of lb_moments.  k_diag/k_diag_final form the FP64 mass and
 // momentum sums and the density health flag with a fixed reduction order.
@@ -268,6 +268,65 @@ __global__ void __launch_bounds__(kBlock) k_collide(const void* __restrict__ fin
   }
 }
 
+// The same step for a compile-time component count (N <= 4): each
+// component's pulled populations are loaded once and stay in registers from
+// the barycentric velocity to the collision (k_collide loads them twice,
+// which on large 3D lattices means twice from HBM).  Same operations in the
+// same order, so the same bits.
+template <class S, int LAT, int NC>
+__global__ void __launch_bounds__(kBlock) k_collide_nc(const void* __restrict__ fin, void* __restrict__ fout,
+                                                       const typename S::T* __restrict__ rho,
+                                                       const typename S::T* __restrict__ h,
+                                                       Params<typename S::T> p) {
+  using L = Lattice<LAT>;
+  using T = typename S::T;
+  constexpr int Q = L::Q;
+  const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= p.S) return;
+  const SiteCoord c = coord_of(s, p);
+  long long nb[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) nb[i] = neighbour<LAT>(c, i, +1, p);
+  T f[NC][Q], led[NC];
+  T jx[NC], jy[NC], jz[NC];
+  T rt = T(0), ux = T(0), uy = T(0), uz = T(0);
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    pull_pops<S, LAT>(fin, c, k, p, f[k], led[k]);
+    T ax = T(0), ay = T(0), az = T(0);
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      if (L::cx(i)) ax += T(L::cx(i)) * f[k][i];
+      if (L::cy(i)) ay += T(L::cy(i)) * f[k][i];
+      if (L::cz(i)) az += T(L::cz(i)) * f[k][i];
+    }
+    jx[k] = ax;
+    jy[k] = ay;
+    jz[k] = az;
+    ux += ax;
+    uy += ay;
+    uz += az;
+    rt += rho[(long long)k * p.S + s];
+  }
+  const T inv_rt = rcp_(rt);
+  ux *= inv_rt;
+  uy *= inv_rt;
+  uz *= inv_rt;
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    const T rs = rho[(long long)k * p.S + s];
+    const T* hk = h + (long long)k * p.S;
+    const T* rk = rho + (long long)k * p.S;
+    T Ax, Ay, Az;
+    lattice_force<LAT, T>([&](int i) { return hk[nb[i]]; }, [&](int i) { return rk[nb[i]]; }, rs, p, Ax, Ay,
+                          Az);
+    const T inv_rs = rcp_(rs);
+    collide<LAT, T>(f[k], rs, ux, uy, uz, Ax, Ay, Az, jx[k] * inv_rs, jy[k] * inv_rs, jz[k] * inv_rs,
+                    p.inv_tau);
+    store_pops<S, LAT>(fout, c, k, p, f[k], led[k]);
+  }
+}
+
 // --------------------------------------------------------- observables ----
 // U = u + (1/2) sum A / rho, and the pressure tensor
 //   P_ab = [p0 - kappa sum_s (rho lap rho + |grad rho|^2 / 2)] d_ab
@@ -457,7 +516,14 @@ struct SplitOps {
     T* h = static_cast<T*>(c.h_scratch);
     k_density<S, LAT, T><<<grid_for(c.S), kBlock, 0, c.stream>>>(fin, rho, p);
     k_potential<LAT, T><<<grid_for(c.S), kBlock, 0, c.stream>>>(rho, nullptr, h, p);
-    k_collide<S, LAT><<<grid_for(c.S), kBlock, 0, c.stream>>>(fin, fout, rho, h, p);
+    const unsigned g = grid_for(c.S);
+    switch (p.n) {
+      case 1: k_collide_nc<S, LAT, 1><<<g, kBlock, 0, c.stream>>>(fin, fout, rho, h, p); break;
+      case 2: k_collide_nc<S, LAT, 2><<<g, kBlock, 0, c.stream>>>(fin, fout, rho, h, p); break;
+      case 3: k_collide_nc<S, LAT, 3><<<g, kBlock, 0, c.stream>>>(fin, fout, rho, h, p); break;
+      case 4: k_collide_nc<S, LAT, 4><<<g, kBlock, 0, c.stream>>>(fin, fout, rho, h, p); break;
+      default: k_collide<S, LAT><<<g, kBlock, 0, c.stream>>>(fin, fout, rho, h, p);
+    }
   }
   static void observe(const Ctx& c, const void* fin, double* rho, double* mu, double* h, double* U,
                       double* P) {
