@@ -3,7 +3,8 @@
 // The split step runs three kernels: k_density (rho^sigma), k_potential
 // (mu^sigma and the potential the force differentiates) and k_collide
 // (force, equilibrium, forcing term, BGK, and the write that streams by
-// pull; k_collide_nc for N <= 4).  It is the path for D1Q3 and D3Q19 and the cross-check of the
+// pull; for N <= 4 the component count is a template parameter of the
+// potential and the collision).  It is the path for D1Q3 and D3Q19 and the cross-check of the
 // fused D2Q9 kernel.  The same kernels, instantiated in FP64, produce the
 // observables of lb_moments.  k_diag/k_diag_final form the FP64 mass and
 // momentum sums and the density health flag with a fixed reduction order.
@@ -185,7 +186,9 @@ __global__ void __launch_bounds__(kBlock) k_density(const void* __restrict__ f, 
 // ----------------------------------------------------------- potential ----
 // lap rho^sigma = 6 sum_i w_i (rho^sigma(r + v_i) - rho^sigma(r)), then the
 // chemical potentials and the potential h^sigma the force differentiates.
-template <int LAT, typename T>
+// NC: compile-time bound on the component count (kMaxComp for any N, or N
+// itself); entries from p.n up are padding that the potential ignores.
+template <int LAT, typename T, int NC = kMaxComp>
 __global__ void __launch_bounds__(kBlock) k_potential(const T* __restrict__ rho, T* __restrict__ mu_out,
                                                       T* __restrict__ h_out, Params<T> p) {
   using L = Lattice<LAT>;
@@ -195,9 +198,9 @@ __global__ void __launch_bounds__(kBlock) k_potential(const T* __restrict__ rho,
   long long nb[L::Q];
 #pragma unroll
   for (int i = 0; i < L::Q; ++i) nb[i] = neighbour<LAT>(c, i, +1, p);
-  T r[kMaxComp], lap[kMaxComp], mu[kMaxComp], h[kMaxComp];
+  T r[NC], lap[NC], mu[NC], h[NC];
 #pragma unroll
-  for (int k = 0; k < kMaxComp; ++k) {
+  for (int k = 0; k < NC; ++k) {
     r[k] = T(1);
     lap[k] = T(0);
     if (k < p.n) {
@@ -206,7 +209,7 @@ __global__ void __launch_bounds__(kBlock) k_potential(const T* __restrict__ rho,
       lap[k] = lattice_laplacian<LAT, T>([&](int i) { return rk[nb[i]]; }, r[k]);
     }
   }
-  site_potential<T, kMaxComp>(p, r, lap, mu, h);
+  site_potential<T, NC>(p, r, lap, mu, h);
   for (int k = 0; k < p.n; ++k) {
     if (mu_out) mu_out[(long long)k * p.S + s] = mu[k];
     h_out[(long long)k * p.S + s] = h[k];
@@ -515,14 +518,27 @@ struct SplitOps {
     T* rho = static_cast<T*>(c.rho_scratch);
     T* h = static_cast<T*>(c.h_scratch);
     k_density<S, LAT, T><<<grid_for(c.S), kBlock, 0, c.stream>>>(fin, rho, p);
-    k_potential<LAT, T><<<grid_for(c.S), kBlock, 0, c.stream>>>(rho, nullptr, h, p);
     const unsigned g = grid_for(c.S);
     switch (p.n) {
-      case 1: k_collide_nc<S, LAT, 1><<<g, kBlock, 0, c.stream>>>(fin, fout, rho, h, p); break;
-      case 2: k_collide_nc<S, LAT, 2><<<g, kBlock, 0, c.stream>>>(fin, fout, rho, h, p); break;
-      case 3: k_collide_nc<S, LAT, 3><<<g, kBlock, 0, c.stream>>>(fin, fout, rho, h, p); break;
-      case 4: k_collide_nc<S, LAT, 4><<<g, kBlock, 0, c.stream>>>(fin, fout, rho, h, p); break;
-      default: k_collide<S, LAT><<<g, kBlock, 0, c.stream>>>(fin, fout, rho, h, p);
+      case 1:
+        k_potential<LAT, T, 1><<<g, kBlock, 0, c.stream>>>(rho, nullptr, h, p);
+        k_collide_nc<S, LAT, 1><<<g, kBlock, 0, c.stream>>>(fin, fout, rho, h, p);
+        break;
+      case 2:
+        k_potential<LAT, T, 2><<<g, kBlock, 0, c.stream>>>(rho, nullptr, h, p);
+        k_collide_nc<S, LAT, 2><<<g, kBlock, 0, c.stream>>>(fin, fout, rho, h, p);
+        break;
+      case 3:
+        k_potential<LAT, T, 3><<<g, kBlock, 0, c.stream>>>(rho, nullptr, h, p);
+        k_collide_nc<S, LAT, 3><<<g, kBlock, 0, c.stream>>>(fin, fout, rho, h, p);
+        break;
+      case 4:
+        k_potential<LAT, T, 4><<<g, kBlock, 0, c.stream>>>(rho, nullptr, h, p);
+        k_collide_nc<S, LAT, 4><<<g, kBlock, 0, c.stream>>>(fin, fout, rho, h, p);
+        break;
+      default:
+        k_potential<LAT, T><<<g, kBlock, 0, c.stream>>>(rho, nullptr, h, p);
+        k_collide<S, LAT><<<g, kBlock, 0, c.stream>>>(fin, fout, rho, h, p);
     }
   }
   static void observe(const Ctx& c, const void* fin, double* rho, double* mu, double* h, double* U,
