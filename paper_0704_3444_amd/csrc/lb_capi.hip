@@ -189,31 +189,26 @@ void destroy_tuner_events(lbm::SweepTuner& tu) {
   }
 }
 
-// Once the trial steps' events have completed, keep the fastest segment
-// length (no wait: a call that finds them pending tries again next time).
+// After the trial steps: the candidate with the shortest timing over its
+// passes (the caller has waited for the last event).
 void finish_tuning(Ctx& c) {
   lbm::SweepTuner& tu = c.tune;
-  if (hipEventQuery(tu.ev[tu.nc]) != hipSuccess) {
-    (void)hipGetLastError();  // hipErrorNotReady is not an error here
-    return;
-  }
   int best = -1;
   float best_ms = 0.f;
   for (int i = 0; i < tu.nc; ++i) {
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, tu.ev[i], tu.ev[i + 1]) != hipSuccess) {
-      best = -1;
-      break;
-    }
-    if (best < 0 || ms < best_ms) {
-      best = i;
-      best_ms = ms;
+    for (int q = 0; q < tu.passes; ++q) {
+      const int e = 2 * (q * tu.nc + i);
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, tu.ev[e], tu.ev[e + 1]) != hipSuccess) continue;
+      if (best < 0 || ms < best_ms) {
+        best = i;
+        best_ms = ms;
+      }
     }
   }
   (void)hipGetLastError();
   c.sweep_rows = best >= 0 ? tu.cand[best] : 0;
   destroy_tuner_events(tu);
-  tu.running = false;
   tu.done = true;
 }
 
@@ -234,30 +229,41 @@ int advance(Ctx& c, int64_t n) {
   };
   int64_t k = 0;
   lbm::SweepTuner& tu = c.tune;
-  if (c.path == LB_PATH_SWEEP && !tu.done && tu.nc > 0) {
+  const int64_t trial_steps = int64_t(tu.nc) * tu.passes * (1 + tu.steps_per);
+  if (c.path == LB_PATH_SWEEP && !tu.done && tu.nc > 0 && n >= trial_steps) {
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     const bool capturing = hipStreamIsCapturing(c.stream, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone;
     (void)hipGetLastError();
-    if (tu.running) {
-      if (!capturing) finish_tuning(c);
-    } else if (!capturing && n >= int64_t(tu.nc) * tu.steps_per) {
-      // trial steps: every candidate length for steps_per real steps, each
-      // block between two events (all within this call, so no host gaps)
+    if (!capturing) {
+      // trial steps: in each pass, every candidate for one step that
+      // switches to it and steps_per steps between two events
+      const int nev = 2 * tu.nc * tu.passes;
       bool ok = true;
-      for (int i = 0; ok && i <= tu.nc; ++i) ok = hipEventCreate(&tu.ev[i]) == hipSuccess;
+      for (int i = 0; ok && i < nev; ++i) ok = hipEventCreate(&tu.ev[i]) == hipSuccess;
       if (!ok) {
         destroy_tuner_events(tu);
         (void)hipGetLastError();
         tu.done = true;
       } else {
-        for (int i = 0; i < tu.nc; ++i) {
-          (void)hipEventRecord(tu.ev[i], c.stream);
-          c.sweep_rows = tu.cand[i];
-          for (int j = 0; j < tu.steps_per; ++j, ++k) step();
+        for (int q = 0; q < tu.passes; ++q) {
+          for (int i = 0; i < tu.nc; ++i) {
+            const int e = 2 * (q * tu.nc + i);
+            c.sweep_rows = tu.cand[i];
+            step();
+            ++k;
+            (void)hipEventRecord(tu.ev[e], c.stream);
+            for (int j = 0; j < tu.steps_per; ++j, ++k) step();
+            (void)hipEventRecord(tu.ev[e + 1], c.stream);
+          }
         }
-        (void)hipEventRecord(tu.ev[tu.nc], c.stream);
-        c.sweep_rows = 0;
-        tu.running = true;
+        if (hipEventSynchronize(tu.ev[nev - 1]) == hipSuccess) {
+          finish_tuning(c);
+        } else {
+          (void)hipGetLastError();
+          destroy_tuner_events(tu);
+          c.sweep_rows = 0;
+          tu.done = true;
+        }
       }
     }
   }

@@ -19,17 +19,19 @@ FusedStepFn sweep_step_for(int storage, int n_comp);               // strip swee
 int sweep_candidates(const Ctx& c, int* cand);
 
 // Choice of the sweep's segment length during stepping: the first lb_step
-// call of at least nc * steps_per steps runs steps_per steps with each
-// candidate between events on the context's stream; a later call reads the
-// events once they have completed (without waiting) and keeps the fastest.
+// call of at least nc * passes * (1 + steps_per) steps runs, in each of
+// `passes` passes, for each candidate one step that switches to it and
+// steps_per steps between two events on the context's stream; it waits for
+// the last event, keeps the candidate with the shortest of its timings, and
+// takes its remaining steps with it.
 struct SweepTuner {
   static constexpr int kMax = 8;
   static constexpr int steps_per = 4;
+  static constexpr int passes = 2;
   int cand[kMax] = {};
   int nc = 0;             // candidates; 0: nothing to tune
-  bool running = false;   // trial steps queued, events pending
   bool done = false;
-  hipEvent_t ev[kMax + 1] = {};
+  hipEvent_t ev[2 * kMax * passes] = {};
 };
 
 // Context behind the opaque lb_ctx handle.

@@ -88,21 +88,21 @@ def test_fullsize_mass_conserved(workload, storage):
 
 @pytest.mark.parametrize("storage", ["f32", "f16s"])
 def test_fullsize_tuned_sweep_equals_split_path(workload, storage):
-    """On grids this large the sweep times several segment lengths during
-    its first 32 steps and keeps the fastest from the next lb_step call on;
-    whichever lengths ran, every site must come out bit for bit as on the
-    one-thread-per-site split path."""
+    """On grids this large the first lb_step call of at least 80 steps
+    times several segment lengths on its first 80 steps and takes the rest
+    with the fastest; whichever lengths ran, every site must come out bit
+    for bit as on the one-thread-per-site split path."""
     from paper_0704_3444_amd import Simulation
 
     cfg, rho0 = workload
     out = {}
     for path in ("sweep", "split"):
         sim = Simulation(cfg, rho0, storage=storage, path=path)
-        sim.step(34)  # trial steps (sweep)
-        sim.step(2)   # chosen length
+        sim.step(82)  # 80 trial steps, 2 with the chosen length (sweep)
+        sim.step(2)
         out[path] = sim.moments(fields=True)
         sim.close()
-    print(f"[fullsize] {storage} tuned sweep vs split, 36 steps", flush=True)
-    assert out["sweep"]["step"] == out["split"]["step"] == 36
+    print(f"[fullsize] {storage} tuned sweep vs split, 84 steps", flush=True)
+    assert out["sweep"]["step"] == out["split"]["step"] == 84
     assert np.array_equal(out["sweep"]["rho"], out["split"]["rho"])
     assert np.array_equal(out["sweep"]["U"], out["split"]["U"])
