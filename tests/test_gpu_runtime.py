@@ -183,3 +183,65 @@ def test_sweep_steps_captured_in_a_hip_graph():
         assert np.array_equal(a, b), k
     g_sim.close()
     eager.close()
+
+
+# bytes of one stored population slot: (rest, moving)
+SLOT_BYTES = {"f64": (8, 8), "f32": (4, 4), "f16s": (4, 2)}
+
+
+def copy_bytes(cfg, storage):
+    """Bytes of one population copy in the block layout (x padded to 64)."""
+    shape = list(cfg["shape"]) + [1] * (3 - len(cfg["shape"]))
+    Q = {"D1Q3": 3, "D2Q9": 9, "D3Q19": 19}[cfg["lattice"]]
+    rest, move = SLOT_BYTES[storage]
+    return shape[1] * shape[2] * ((shape[0] + 63) // 64) * cfg["n_comp"] * 64 * (rest + (Q - 1) * move)
+
+
+def poison_copy(s, cfg, storage, which):
+    """Fill population copy `which` of a Simulation's workspace with 0xFF
+    bytes (NaN in FP64, FP32 and FP16)."""
+    base = s.workspace.data_ptr()
+    off = (base + 255) // 256 * 256 - base
+    n = copy_bytes(cfg, storage)
+    start = off + which * ((n + 255) // 256 * 256)
+    s.workspace[start:start + n].fill_(255)
+
+
+@pytest.mark.parametrize("case", ["d2q9", "ragged", "d3q19", "lines"])
+def test_every_slot_written_each_step(case):
+    """The copy a step writes is filled with NaN before the step; after three
+    steps the state equals that of an unpoisoned run bit for bit, so every
+    population slot is written by every step of every path (no slot left
+    from an earlier step, none read before it is written)."""
+    from paper_0704_3444_amd import Lines, Simulation
+
+    if case == "d2q9":
+        cfg, rho0 = LI.ternary_immersion(128, ny=64)
+        combos = [(p, st) for p in PATHS for st in storages(p)]
+    elif case == "ragged":
+        cfg, rho0 = LI.ternary_immersion(100, ny=37)
+        combos = [(p, st) for p in ("split", "tile") for st in storages(p)]
+    elif case == "d3q19":
+        cfg, rho0 = LI.ternary_d3q19(24)
+        combos = [("split", st) for st in storages("split")]
+    else:
+        cfg, rho0, _ = LI.binodal_runs("ternary_monomer")[9]
+        combos = [("lines", "f64"), ("lines", "f32")]
+    for path, storage in combos:
+        kw = {"storage": storage} if path == "lines" else {"storage": storage, "path": path}
+        ref, pois = Simulation(cfg, rho0, **kw), Simulation(cfg, rho0, **kw)
+        group = Lines([pois]) if path == "lines" else None
+        for k in range(3):
+            poison_copy(pois, cfg, storage, 1 - k % 2)  # the copy this step writes
+            ref.step(1)
+            if group:
+                group.step(1)
+            else:
+                pois.step(1)
+        a, b = ref.get_f(), pois.get_f()
+        assert np.all(np.isfinite(b)), (case, path, storage)
+        assert np.array_equal(a, b), (case, path, storage)
+        if group:
+            group.close()
+        ref.close()
+        pois.close()
