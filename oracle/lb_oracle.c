@@ -183,13 +183,50 @@ struct orc_state {
   double* mu;    /* [N][S]                                      */
 };
 
+/* Coordinate c + d (|d| <= 1) along an axis of n layers: periodic, or, on
+ * an axis closed by walls, the mirror image of the layer next to the wall
+ * when c + d lies beyond it (a zero normal gradient of the field at the
+ * wall). */
+static int64_t axis_step(int64_t c, int d, int64_t n, int wall) {
+  int64_t y = c + d;
+  if (wall) return y < 0 ? -1 - y : (y >= n ? 2 * n - 1 - y : y);
+  return (y % n + n) % n;
+}
+
+/* Site r + sign * v for the gradient and Laplacian stencils. */
 static int64_t neighbour(const orc_state* st, int64_t s, const int v[3], int sign) {
   const int64_t nx = st->p.nx, ny = st->p.ny, nz = st->p.nz;
+  const int w = st->p.walls;
   int64_t x = s % nx, y = (s / nx) % ny, z = s / (nx * ny);
-  x = ((x + sign * v[0]) % nx + nx) % nx;
-  y = ((y + sign * v[1]) % ny + ny) % ny;
-  z = ((z + sign * v[2]) % nz + nz) % nz;
+  x = axis_step(x, sign * v[0], nx, w & 1);
+  y = axis_step(y, sign * v[1], ny, w & 2);
+  z = axis_step(z, sign * v[2], nz, w & 4);
   return x + nx * (y + ny * z);
+}
+
+/* Site that a population leaving s with velocity v reaches in one step, or
+ * -1 if it meets a wall on the way (half-way bounce-back: it then returns to
+ * s with velocity -v). */
+static int64_t stream_target(const orc_state* st, int64_t s, const int v[3]) {
+  const int64_t n[3] = {st->p.nx, st->p.ny, st->p.nz};
+  int64_t c[3] = {s % n[0], (s / n[0]) % n[1], s / (n[0] * n[1])};
+  for (int a = 0; a < 3; ++a) {
+    int64_t y = c[a] + v[a];
+    if ((st->p.walls >> a) & 1) {
+      if (y < 0 || y >= n[a]) return -1;
+    } else {
+      y = (y % n[a] + n[a]) % n[a];
+    }
+    c[a] = y;
+  }
+  return c[0] + n[0] * (c[1] + n[1] * c[2]);
+}
+
+/* Index of the velocity -v_i. */
+static int opposite(const lattice_t* L, int i) {
+  for (int j = 0; j < L->Q; ++j)
+    if (L->v[j][0] == -L->v[i][0] && L->v[j][1] == -L->v[i][1] && L->v[j][2] == -L->v[i][2]) return j;
+  return -1;
 }
 
 #define F(arr, sg, i, s) (arr)[(((int64_t)(sg) * st->L.Q + (i)) * st->S) + (s)]
@@ -352,7 +389,11 @@ static void pass_collide_stream(orc_state* st) {
       for (int i = 0; i < Q; ++i) {
         double fs = F(st->f, sg, i, s);
         double post = fs + inv_tau * (feq[i] - fs) + Fi[i];
-        F(st->fnew, sg, i, neighbour(st, s, st->L.v[i], +1)) = post;
+        const int64_t d = stream_target(st, s, st->L.v[i]);
+        if (d >= 0)
+          F(st->fnew, sg, i, d) = post;
+        else
+          F(st->fnew, sg, opposite(&st->L, i), s) = post;  /* bounced at a wall */
       }
     }
   }

@@ -32,8 +32,10 @@ typedef struct {
   int32_t lattice;     /* ORC_D1Q3, ORC_D2Q9 or ORC_D3Q19                     */
   int32_t n_comp;      /* 1 .. ORC_MAX_COMP                                    */
   int32_t force_form;  /* ORC_FORCE_EXPANDED (default) or ORC_FORCE_LOG        */
-  int32_t reserved;
-  int64_t nx, ny, nz;  /* periodic box; unused axes are 1                      */
+  int32_t walls;       /* bit a set: axis a (0 x, 1 y, 2 z) is closed by walls
+                          half a site beyond its first and last layers (not in
+                          the paper; see orc_step); 0: periodic               */
+  int64_t nx, ny, nz;  /* box; unused axes are 1                               */
   double tau;          /* BGK relaxation time, common to all components        */
   double theta;        /* temperature of the Flory-Huggins free energy         */
   double kappa;        /* square-gradient coefficient                          */
@@ -59,6 +61,12 @@ double orc_psi_site(const orc_params* p, const double* rho);
 /* Whole-lattice state. */
 orc_state* orc_create(const orc_params* p, const double* rho0 /* [N][S] */);
 void orc_destroy(orc_state* st);
+/* nsteps time steps.  With walls (the paper's boxes are periodic; walls are
+ * this library's own addition): a population that would stream across a
+ * wall returns to its site with the opposite velocity (half-way
+ * bounce-back: no slip, every component's mass kept), and the gradient and
+ * Laplacian stencils take the layer next to a wall as its own mirror image
+ * beyond it (zero normal gradient: a wall that favours no component). */
 void orc_step(orc_state* st, int64_t nsteps);
 int64_t orc_time(const orc_state* st);
 void orc_get_f(const orc_state* st, double* f /* [N][Q][S] */);

@@ -23,7 +23,7 @@ FORCE_FORMS = {"expanded": 0, "log": 1}
 class _Params(C.Structure):
     _fields_ = [
         ("lattice", C.c_int32), ("n_comp", C.c_int32), ("force_form", C.c_int32),
-        ("reserved", C.c_int32),
+        ("walls", C.c_int32),
         ("nx", C.c_int64), ("ny", C.c_int64), ("nz", C.c_int64),
         ("tau", C.c_double), ("theta", C.c_double), ("kappa", C.c_double),
         ("m", C.c_double * MAX_COMP), ("chi", C.c_double * (MAX_COMP * MAX_COMP)),
@@ -77,12 +77,14 @@ class OracleParams:
     m: Sequence[float] = field(default_factory=lambda: [1.0, 1.0])
     chi: Optional[np.ndarray] = None         # N x N symmetric, zero diagonal
     force_form: str = "expanded"
+    walls: int = 0                            # bit a: axis a closed by walls (not in the paper)
 
     def to_c(self) -> _Params:
         p = _Params()
         p.lattice = LATTICES[self.lattice]
         p.n_comp = self.n_comp
         p.force_form = FORCE_FORMS[self.force_form]
+        p.walls = int(self.walls)
         dims = list(self.shape) + [1] * (3 - len(self.shape))
         p.nx, p.ny, p.nz = dims
         p.tau, p.theta, p.kappa = self.tau, self.theta, self.kappa
