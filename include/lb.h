@@ -111,6 +111,16 @@ typedef struct lb_params {
                             NaN or <= 0 (0: only in lb_moments); a failed check
                             makes the next synchronising call return LB_ENUMERIC */
   void* stream;          /* hipStream_t for all device work (NULL: null stream)   */
+  int32_t walls;         /* 0: periodic box (the paper's).  Bit a set: axis a
+                            (0 x, 1 y, 2 z) is closed by walls half a site
+                            beyond its first and last layers -- not in the
+                            paper, this library's own addition: populations that
+                            would cross a wall bounce back to their site
+                            reversed (no slip; every component's mass kept), and
+                            the density and potential stencils mirror the layer
+                            next to the wall (zero normal gradient, a wall that
+                            favours no component).  LB_PATH_SPLIT only.        */
+  int32_t reserved;      /* 0                                                     */
 } lb_params;
 
 typedef struct lb_ctx lb_ctx;
@@ -233,7 +243,7 @@ int lb_batch_create(const lb_batch_params* bp, lb_batch** out);
  * or not admissible to b). */
 size_t lb_batch_footprint(const lb_batch* b, const lb_params* p);
 
-/* Admit a run: validate p (D2Q9, the batch's storage, N <= max_comp; path,
+/* Admit a run: validate p (D2Q9, periodic, the batch's storage, N <= max_comp; path,
  * check_every and stream are ignored), carve its workspace from the arena,
  * set rest equilibrium from rho0 (host FP64 [N][S], as lb_init) and make it
  * a live slot that lb_batch_step advances until it has taken nsteps steps.
@@ -299,7 +309,7 @@ void lb_batch_free(lb_batch* b);
  * (lb_moments, lb_get_f, checkpoints) and keep their step counters.
  *
  * Requirements on the contexts: lattice LB_D1Q3, storage LB_F64 or LB_F32,
- * nx = 64, 128, 192 or 256, N <= 4; within a group the same N, storage, nx
+ * nx = 64, 128, 192 or 256, N <= 4, periodic (no walls); within a group the same N, storage, nx
  * and stream; no context twice.  Parameters of Eq. (ssLB) and Eq. (lgf)
  * (tau, theta, m, chi, kappa, force form) may differ between runs.
  * ------------------------------------------------------------------------ */

@@ -39,19 +39,47 @@ __device__ __forceinline__ long long site_of(int x, int y, int z, const Params<T
   return (long long)x + (long long)p.nx * ((long long)y + (long long)p.ny * z);
 }
 
-// Site r + sign * v_i.
+// Coordinate x + d (|d| <= 1) along an axis of n layers: periodic, or, on
+// an axis closed by walls, the mirror image of the layer next to the wall
+// when x + d lies beyond it (zero normal gradient of the stencils' fields).
+__device__ __forceinline__ int axis_step(int x, int d, int n, bool wall) {
+  const int y = x + d;
+  if (wall) return y < 0 ? -1 - y : (y >= n ? 2 * n - 1 - y : y);
+  return wrap_add(x, d, n);
+}
+
+// Site r + sign * v_i for the stencils.
 template <int LAT, typename T>
 __device__ __forceinline__ long long neighbour(const SiteCoord& c, int i, int sign, const Params<T>& p) {
   using L = Lattice<LAT>;
-  return site_of(wrap_add(c.x, sign * L::cx(i), p.nx), wrap_add(c.y, sign * L::cy(i), p.ny),
-                 wrap_add(c.z, sign * L::cz(i), p.nz), p);
+  return site_of(axis_step(c.x, sign * L::cx(i), p.nx, p.walls & 1), axis_step(c.y, sign * L::cy(i), p.ny, p.walls & 2),
+                 axis_step(c.z, sign * L::cz(i), p.nz, p.walls & 4), p);
+}
+
+// True when site c + sign * v_i lies beyond a wall.
+template <int LAT, typename T>
+__device__ __forceinline__ bool beyond_wall(const SiteCoord& c, int i, int sign, const Params<T>& p) {
+  using L = Lattice<LAT>;
+  const int x = c.x + sign * L::cx(i), y = c.y + sign * L::cy(i), z = c.z + sign * L::cz(i);
+  return ((p.walls & 1) && (x < 0 || x >= p.nx)) || ((p.walls & 2) && (y < 0 || y >= p.ny)) ||
+         ((p.walls & 4) && (z < 0 || z >= p.nz));
+}
+
+// Site that a population leaving c with velocity v_i reaches in one step:
+// c + v_i, or c itself when a wall lies between (half-way bounce-back
+// returns it there reversed).
+template <int LAT, typename T>
+__device__ __forceinline__ long long stream_target(const SiteCoord& c, int i, const Params<T>& p) {
+  return beyond_wall<LAT>(c, i, +1, p) ? site_of(c.x, c.y, c.z, p) : neighbour<LAT>(c, i, +1, p);
 }
 
 // Byte offset of population i of component k at the site r - v_i (the slot
-// pulled into r).
+// pulled into r); across a wall, the slot of -v_i at r itself (bounce-back).
 template <class S, int LAT, typename T>
 __device__ __forceinline__ uint64_t pull_byte(const SiteCoord& c, int k, int i, const Params<T>& p) {
   using L = Lattice<LAT>;
+  if (beyond_wall<LAT>(c, i, -1, p))
+    return pop_byte<S, L::Q>(p.n, p.nbx, k, L::opp(i), c.x, (long long)c.y + (long long)p.ny * c.z);
   const int sx = wrap_add(c.x, -L::cx(i), p.nx);
   const int sy = wrap_add(c.y, -L::cy(i), p.ny);
   const int sz = wrap_add(c.z, -L::cz(i), p.nz);
@@ -114,7 +142,8 @@ __device__ __forceinline__ void store_pops(void* fout, const SiteCoord& c, int k
 
 // ---------------------------------------------------------------- init ----
 // Rest equilibrium f_i(r, 0) = w_i rho0(r), written in pull storage: slot
-// (i, r) holds the value that arrives at r + v_i.  The shifted codec stores
+// (i, r) holds the value that arrives at r + v_i (at r itself when a wall
+// lies between: the value pulled back across the wall).  The shifted codec stores
 // the FP16 deviations of the moving slots, and in the rest slot of r the
 // ledger that makes the site's stored total equal rho0(r) (to 2^-25 s).
 template <class S, int LAT>
@@ -138,7 +167,7 @@ __global__ void __launch_bounds__(kBlock) k_init(const double* __restrict__ rho0
         // the slot pulled into r carries w_i rho0(r); the slot written here
         // carries w_i rho0(r + v_i)
         target -= double(encode_move<LAT>(p.sh, k, i, float(L::w(i) * r0)));
-        const double rn = rho0[(long long)k * p.S + neighbour<LAT>(c, i, +1, p)];
+        const double rn = rho0[(long long)k * p.S + stream_target<LAT>(c, i, p)];
         *reinterpret_cast<_Float16*>(out + own_byte<S, LAT>(c, k, i, p)) =
             encode_move<LAT>(p.sh, k, i, float(L::w(i) * rn));
       }
@@ -147,7 +176,7 @@ __global__ void __launch_bounds__(kBlock) k_init(const double* __restrict__ rho0
     } else {
 #pragma unroll
       for (int i = 0; i < L::Q; ++i) {
-        const long long src = neighbour<LAT>(c, i, +1, p);
+        const long long src = stream_target<LAT>(c, i, p);
         *reinterpret_cast<T*>(out + own_byte<S, LAT>(c, k, i, p)) = T(L::w(i) * rho0[(long long)k * p.S + src]);
       }
     }

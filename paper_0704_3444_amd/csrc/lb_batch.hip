@@ -261,6 +261,7 @@ size_t site_bytes(int storage) { return storage == LB_F64 ? 72 : (storage == LB_
 int check_run(const lb_batch* b, const lb_params* p, size_t* bytes) {
   if (!p) return fail(LB_EINVAL, "params is NULL");
   if (p->lattice != LB_D2Q9) return fail(LB_ENOTSUP, "batches take D2Q9 runs");
+  if (p->walls != 0) return fail(LB_ENOTSUP, "batches take periodic runs (walls need the split path)");
   if (p->storage != b->bp.storage) return fail(LB_EINVAL, "the run's storage differs from the batch's");
   if (p->n_comp > b->bp.max_comp) return fail(LB_ENOTSUP, "the run has more components than the batch's max_comp");
   const size_t need = lb_workspace_bytes(p);

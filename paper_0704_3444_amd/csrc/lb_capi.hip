@@ -78,6 +78,16 @@ int validate(const lb_params* p, std::string* why) {
       if (a == b && v != 0.0) return bad("chi^{sigma sigma} must be 0");
     }
   if (p->check_every < 0) return bad("check_every must be >= 0");
+  if (p->walls & ~7) return bad("walls: only bits 0 (x), 1 (y) and 2 (z)");
+  {
+    int D2 = 0, Q2 = 0;
+    lattice_dims(p->lattice, &Q2, &D2);
+    if (p->walls >> D2) return bad("walls: an axis beyond the lattice's dimension");
+    const int64_t side[3] = {p->nx, p->ny, p->nz};
+    for (int a = 0; a < 3; ++a)
+      if (((p->walls >> a) & 1) && side[a] < 2) return bad("walls: a closed axis needs at least 2 layers");
+  }
+  if (p->reserved != 0) return bad("reserved must be 0");
   return LB_OK;
 }
 
@@ -137,6 +147,7 @@ void fill_params(const lb_params* p, lbm::Params<T>* q) {
   int Q, D;
   lattice_dims(p->lattice, &Q, &D);
   q->nq = p->n_comp * Q;
+  q->walls = p->walls;
   q->inv_tau = T(1.0 / p->tau[0]);
   q->cforce = T(1.0 - 0.5 / p->tau[0]);
   q->theta = T(p->theta);
@@ -346,7 +357,8 @@ int init_impl(const lb_params* p, const double* rho0, void* workspace, size_t wo
   c.pf.sh = c.pd.sh = shift_ref_of(p, rho0, S);
 
   // the fused kernels address one population copy with 32-bit byte offsets
-  const bool small = fbytes < (size_t(1) << 32);
+  // (walls: the split path only)
+  const bool small = fbytes < (size_t(1) << 32) && p->walls == 0;
   lbm::FusedStepFn tile = small ? lbm::fused_step_for(p->lattice, p->storage, p->n_comp) : nullptr;
   lbm::FusedStepFn sweep =
       small && p->lattice == LB_D2Q9 && p->nx % 64 == 0 ? lbm::sweep_step_for(p->storage, p->n_comp) : nullptr;
@@ -358,14 +370,14 @@ int init_impl(const lb_params* p, const double* rho0, void* workspace, size_t wo
       c.path = LB_PATH_TILE;
       if (!tile) {
         lb_free(h);
-        return fail(LB_ENOTSUP, "no tile kernel for this lattice / storage / N / size");
+        return fail(LB_ENOTSUP, "no tile kernel for this lattice / storage / N / size / walls");
       }
       break;
     case LB_PATH_SWEEP:
       c.path = LB_PATH_SWEEP;
       if (!sweep) {
         lb_free(h);
-        return fail(LB_ENOTSUP, "the sweep kernel needs D2Q9, FP32 or shifted FP16, N <= 4 and nx a multiple of 64");
+        return fail(LB_ENOTSUP, "the sweep kernel needs D2Q9, FP32 or shifted FP16, N <= 4, nx a multiple of 64 and no walls");
       }
       break;
     default:

@@ -270,6 +270,7 @@ int lb_lines_create(lb_ctx* const* ctxs, int32_t n, lb_lines** out) {
     if (c.prm.nx % 64 != 0 || c.prm.nx / 64 > lbm::lines::kMaxSitesPerLane)
       return fail_with(LB_ENOTSUP, ("nx must be 64, 128, 192 or 256" + at).c_str());
     if (c.prm.n_comp > lbm::lines::kMaxLineComp) return fail_with(LB_ENOTSUP, ("N must be <= 4" + at).c_str());
+    if (c.prm.walls != 0) return fail_with(LB_ENOTSUP, ("groups hold periodic lines only" + at).c_str());
     if (c.prm.n_comp != c0.prm.n_comp || c.prm.storage != c0.prm.storage || c.prm.nx != c0.prm.nx)
       return fail_with(LB_EINVAL, ("every run of a group needs the same N, storage and nx" + at).c_str());
     if (c.stream != c0.stream) return fail_with(LB_EINVAL, ("every run of a group needs the same stream" + at).c_str());

@@ -44,6 +44,8 @@ struct Params {
   long long S;    // nx * ny * nz
   int nbx;        // 64-site blocks per row, ceil(nx / 64)
   int nq;         // populations per site, N * Q
+  int walls;      // bit a: axis a closed by walls (split path only; 0 elsewhere)
+  int pad_;
   T inv_tau;      // BGK rate 1/tau
   T cforce;       // c = w / tau = 1 - 1/(2 tau)
   T theta;        // temperature of the free energy

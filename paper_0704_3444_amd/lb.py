@@ -41,6 +41,7 @@ class lb_params(C.Structure):
         ("tau", C.c_double * MAX_COMP), ("theta", C.c_double), ("kappa", C.c_double),
         ("m", C.c_double * MAX_COMP), ("chi", C.c_double * (MAX_COMP * MAX_COMP)),
         ("path", C.c_int32), ("check_every", C.c_int32), ("stream", C.c_void_p),
+        ("walls", C.c_int32), ("reserved", C.c_int32),
     ]
 
 
@@ -140,7 +141,7 @@ def _dptr(a: Optional[np.ndarray]):
 
 def make_params(cfg: dict, *, storage="f64", path="auto", check_every=0, stream=None) -> lb_params:
     """lb_params from a workload dict (keys lattice, n_comp, shape, tau,
-    theta, kappa, m, chi, force_form)."""
+    theta, kappa, m, chi, force_form, and optionally walls)."""
     p = lb_params()
     n = int(cfg["n_comp"])
     shape = list(cfg["shape"]) + [1] * (3 - len(cfg["shape"]))
@@ -158,6 +159,7 @@ def make_params(cfg: dict, *, storage="f64", path="auto", check_every=0, stream=
             p.chi[a * MAX_COMP + b] = chi[a, b]
     p.path, p.check_every = PATH[path], int(check_every)
     p.stream = stream
+    p.walls = int(cfg.get("walls", 0))
     return p
 
 

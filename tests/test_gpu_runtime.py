@@ -207,7 +207,7 @@ def poison_copy(s, cfg, storage, which):
     s.workspace[start:start + n].fill_(255)
 
 
-@pytest.mark.parametrize("case", ["d2q9", "ragged", "d3q19", "lines"])
+@pytest.mark.parametrize("case", ["d2q9", "ragged", "d3q19", "lines", "walls"])
 def test_every_slot_written_each_step(case):
     """The copy a step writes is filled with NaN before the step; after three
     steps the state equals that of an unpoisoned run bit for bit, so every
@@ -223,6 +223,10 @@ def test_every_slot_written_each_step(case):
         combos = [(p, st) for p in ("split", "tile") for st in storages(p)]
     elif case == "d3q19":
         cfg, rho0 = LI.ternary_d3q19(24)
+        combos = [("split", st) for st in storages("split")]
+    elif case == "walls":
+        cfg, rho0 = LI.ternary_immersion(37, ny=23)
+        cfg = dict(cfg, walls=0b011)
         combos = [("split", st) for st in storages("split")]
     else:
         cfg, rho0, _ = LI.binodal_runs("ternary_monomer")[9]

@@ -1,0 +1,71 @@
+"""Walls (not in the paper; lb_params.walls) on the split path against the
+oracle's walls, every lattice and storage, and the paths and groups that
+refuse them.  The oracle's walls are pinned by tests/test_oracle_walls.py."""
+import numpy as np
+import pytest
+
+import lbinputs as LI
+from gpu_helpers import TOL, errors, run_gpu, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    ("D1Q3", (70,), 0b001, 2),
+    ("D2Q9", (40, 28), 0b010, 3),
+    ("D2Q9", (37, 23), 0b011, 2),
+    ("D3Q19", (12, 10, 9), 0b100, 3),
+    ("D3Q19", (9, 8, 7), 0b111, 2),
+]
+
+
+def walled(lattice, shape, walls, n, seed):
+    chi = np.full((n, n), 1.6) - 1.6 * np.eye(n)
+    cfg = LI.params(lattice, n, shape, tau=0.9, kappa=0.03, chi=chi) | {"walls": walls}
+    return cfg, LI.noisy_uniform(cfg, [1.0 / n] * n, 0.1 / n, seed)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_walls_match_oracle(case, storage):
+    lattice, shape, walls, n = CASES[case]
+    cfg, rho0 = walled(lattice, shape, walls, n, 40 + case)
+    g = run_gpu(cfg, rho0, 200, storage=storage, path="auto")
+    assert g["path"] == "split"
+    o = run_oracle(cfg, rho0, 200)
+    e = errors(g, o, cfg["theta"])
+    print(f"[walls] {lattice} {shape} walls={walls:03b} {storage}: {e}", flush=True)
+    for k in ("rho", "f", "U", "mu"):
+        assert e[k] < TOL[storage], (k, e)
+    assert e["mass"] < (1e-13 if storage == "f64" else 1e-6), e
+
+
+def test_walls_keep_mass_in_shifted_fp16():
+    cfg, rho0 = walled("D2Q9", (48, 32), 0b011, 3, 50)
+    g = run_gpu(cfg, rho0, 500, storage="f16s", path="auto", fields=True)
+    drift = float(np.max(np.abs(g["mass"] / rho0.sum(axis=1) - 1)))
+    assert drift < 1e-6, drift
+
+
+def test_walls_refused_where_not_built():
+    from paper_0704_3444_amd import Batch, LBError, Lines, Simulation
+    from paper_0704_3444_amd.lb import LB_EINVAL, LB_ENOTSUP
+
+    cfg, rho0 = walled("D2Q9", (64, 32), 0b010, 2, 60)
+    for path in ("tile", "sweep"):
+        with pytest.raises(LBError) as ei:
+            Simulation(cfg, rho0, storage="f32", path=path)
+        assert ei.value.code == LB_ENOTSUP
+    with pytest.raises(LBError) as ei:
+        Simulation(dict(cfg, walls=0b100), rho0)  # D2Q9 has no z axis
+    assert ei.value.code == LB_EINVAL
+    b = Batch(storage="f32", max_comp=2, max_slots=2, arena_bytes=16 << 20)
+    with pytest.raises(LBError) as ei:
+        b.add(cfg, rho0, 10)
+    assert ei.value.code == LB_ENOTSUP
+    b.close()
+    lc, lr, _ = LI.binodal_runs("binary_monomer")[0]
+    s = Simulation(dict(lc, walls=1), lr)
+    with pytest.raises(LBError) as ei:
+        Lines([s])
+    assert ei.value.code == LB_ENOTSUP
+    s.close()
