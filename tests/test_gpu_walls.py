@@ -69,3 +69,26 @@ def test_walls_refused_where_not_built():
         Lines([s])
     assert ei.value.code == LB_ENOTSUP
     s.close()
+
+
+def test_immersion_film_on_a_wall():
+    """The immersion geometry with a substrate: the ternary film of the
+    benchmark workload (x < nx/2) against a wall at x = 0 and the bath
+    closed by a wall at x = nx - 1.  Against the oracle after 100 steps
+    (FP32 bar); healthy, with every component's mass kept, after 3000."""
+    from paper_0704_3444_amd import Simulation
+
+    cfg, rho0 = LI.ternary_immersion(128, ny=32)
+    cfg = dict(cfg, walls=0b001)
+    g = run_gpu(cfg, rho0, 100, storage="f32", path="auto")
+    o = run_oracle(cfg, rho0, 100)
+    e = errors(g, o, cfg["theta"])
+    print(f"[walls] immersion film on a wall, 100 steps, f32: {e}", flush=True)
+    for k in ("rho", "f", "U", "mu"):
+        assert e[k] < TOL["f32"], (k, e)
+    sim = Simulation(cfg, rho0, storage="f32")
+    sim.step(3000)
+    m = sim.moments(fields=False)
+    sim.close()
+    assert m["status"] == 0
+    assert float(np.max(np.abs(m["mass"] / rho0.sum(axis=1) - 1))) < 1e-6
