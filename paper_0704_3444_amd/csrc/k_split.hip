@@ -6,7 +6,9 @@
 // pull; for N <= 4 the component count is a template parameter of the
 // potential and the collision).  It is the path for D1Q3 and D3Q19 and the cross-check of the
 // fused D2Q9 kernel.  The same kernels, instantiated in FP64, produce the
-// observables of lb_moments.  k_diag/k_diag_final form the FP64 mass and
+// observables of lb_moments.  It is also the path that takes walls (a
+// closed axis: bounce-back in the pull, mirrored layers in the stencils).
+// k_diag/k_diag_final form the FP64 mass and
 // momentum sums and the density health flag with a fixed reduction order.
 // Every kernel is templated on the storage codec S (storage.hpp): T is its
 // working precision; stored slots are decoded on load and encoded on store.
