@@ -20,11 +20,18 @@ implementation's readings of the paper:
   separation grows with chi, and next to the critical point the phases
   approach the binodal;
 * every stable run stays within 0.1 of the binodal."""
+import json
+import os
+
 import numpy as np
 import pytest
 
 import lbinputs as LI
 from gpu_helpers import run_oracle
+
+GOLD = {k: v["value"] for k, v in json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                                                  "sec4_printed_values.json"))).items()
+        if not k.startswith("_")}
 
 pytestmark = pytest.mark.gpu
 
@@ -191,7 +198,9 @@ def test_polymer_profiles():
         st = profile_stats(r["rho"], r["mu"])
         print(f"[replication] Fig. 2 profile {label}: drho/rho bulk {st['drho_bulk']:.1e} range {st['drho_range']:.1e}; "
               f"mu^A bulk {st['mu0_bulk']:.1e} range {st['mu0_range']:.1e}; mu^B bulk {st['mu1_bulk']:.1e} "
-              f"range {st['mu1_range']:.1e} (paper: < 1e-5; 2e-2, 4e-2; < 1e-4, 1e-3)", flush=True)
+              f"range {st['mu1_range']:.1e} (paper: < {GOLD['fig2_drho_over_rho_below']:.0e}; "
+              f"{GOLD['fig2_muA_bulk_difference']:.0e}, {GOLD['fig2_muA_interface_variation']:.0e}; "
+              f"< {GOLD['fig2_muB_bulk_below']:.0e}, {GOLD['fig2_muB_interface_variation']:.0e})", flush=True)
         assert st["mu0_range"] > st["mu1_range"] and st["drho_range"] < 1e-2
     cfg3, rho3 = LI.profile_run("ternary_polymer_profile")
     r3 = phase.run_lines([(cfg3, rho3, "")], 200000)[0]
@@ -206,4 +215,6 @@ def test_polymer_profiles():
     print(f"[replication] Fig. 4 profile after 200000 steps: phases {np.round(ph['rich'], 4)} | "
           f"{np.round(ph['poor'], 4)}; drho/rho bulk {st['drho_bulk']:.1e} range {st['drho_range']:.1e}; "
           f"mu^A bulk {st['mu0_bulk']:.1e}; mu^B bulk {st['mu1_bulk']:.1e}; mu^C bulk {st['mu2_bulk']:.1e} "
-          f"(paper: < 1e-4 bulk, < 1e-2 interface; 2e-2; < 1e-4; < 1e-4)", flush=True)
+          f"(paper: < {GOLD['fig4_drho_over_rho_bulk_below']:.0e} bulk, < "
+          f"{GOLD['fig4_drho_over_rho_interface_below']:.0e} interface; {GOLD['fig4_muA_difference']:.0e}; "
+          f"< {GOLD['fig4_muBC_difference_below']:.0e}; < {GOLD['fig4_muBC_difference_below']:.0e})", flush=True)
