@@ -292,6 +292,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-phase", action="store_true")
     ap.add_argument("--only-phase", action="store_true", help="time only the phase sweeps (for profiling them)")
+    ap.add_argument("--walls", type=int, default=0, help="close axes by walls (bit a: axis a; split path only)")
     ap.add_argument("--serving-requests", type=int, default=256)
     args = ap.parse_args()
 
@@ -318,6 +319,8 @@ def main():
         return
 
     cfg, rho0 = workload(args.workload)
+    if args.walls:
+        cfg = dict(cfg, walls=args.walls)
     shape = list(cfg["shape"]) + [1] * (3 - len(cfg["shape"]))
     S = int(np.prod(shape))
     N = int(cfg["n_comp"])
@@ -375,7 +378,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if args.storage == "f64" else "f32", "data": "synthetic",
         "config": {"workload": args.workload, "lattice": cfg["lattice"], "shape": shape[: len(cfg["shape"])],
-                   "n_comp": N, "storage": args.storage, "path": path, "force_form": cfg["force_form"]},
+                   "n_comp": N, "storage": args.storage, "path": path, "force_form": cfg["force_form"],
+                   "walls": args.walls},
         "hbm_frac": round(achieved / HBM_PEAK_GBS, 4),
         "wall_s": round(wall, 4), "mass_drift": mass_drift, "status": health["status"],
         "roofline": roofline, "cpu_baseline": cpu, "f16s": f16s, "serving": serving, "phase_sweeps": phase_sweeps,
