@@ -282,7 +282,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=150)
     ap.add_argument("--storage", default="f32", choices=["f32", "f64", "f16s"])
     ap.add_argument("--workload", default="ternary_d2q9_2048")
     ap.add_argument("--path", default="auto", choices=["auto", "sweep", "tile", "split"])

@@ -148,11 +148,11 @@ int lb_init(const lb_params* p, const double* rho0, void* workspace, size_t work
  * moments, chemical potentials, force, equilibrium, forcing term, BGK
  * collision and streaming.  Asynchronous on the context's stream.
  * On the strip-sweep path (lb_path_in_use) of a grid of at least 2^20
- * sites, the first call with at least 80 steps (not during stream capture)
- * times up to 8 segment lengths of the sweep on its first steps (twice
- * each: one step to switch, then 4 between events on the stream), waits
- * for those events (a few milliseconds) and takes its remaining steps, and
- * all later ones, with the fastest.  Every segment length gives the same
+ * sites, the first call with at least 128 steps (not during stream
+ * capture) takes 48 steps, then times up to 8 segment lengths of the sweep
+ * (twice each: one step to switch, then 4 between events on the stream),
+ * waits for those events (a few milliseconds) and takes its remaining
+ * steps, and all later ones, with the fastest.  Every segment length gives the same
  * results bit for bit. */
 int lb_step(lb_ctx* c, int64_t nsteps);
 

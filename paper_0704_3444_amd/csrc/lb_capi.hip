@@ -240,7 +240,7 @@ int advance(Ctx& c, int64_t n) {
   };
   int64_t k = 0;
   lbm::SweepTuner& tu = c.tune;
-  const int64_t trial_steps = int64_t(tu.nc) * tu.passes * (1 + tu.steps_per);
+  const int64_t trial_steps = tu.warm + int64_t(tu.nc) * tu.passes * (1 + tu.steps_per);
   if (c.path == LB_PATH_SWEEP && !tu.done && tu.nc > 0 && n >= trial_steps) {
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     const bool capturing = hipStreamIsCapturing(c.stream, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone;
@@ -256,6 +256,8 @@ int advance(Ctx& c, int64_t n) {
         (void)hipGetLastError();
         tu.done = true;
       } else {
+        c.sweep_rows = 0;
+        for (int j = 0; j < tu.warm; ++j, ++k) step();
         for (int q = 0; q < tu.passes; ++q) {
           for (int i = 0; i < tu.nc; ++i) {
             const int e = 2 * (q * tu.nc + i);

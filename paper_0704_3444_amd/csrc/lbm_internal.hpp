@@ -19,13 +19,16 @@ FusedStepFn sweep_step_for(int storage, int n_comp);               // strip swee
 int sweep_candidates(const Ctx& c, int* cand);
 
 // Choice of the sweep's segment length during stepping: the first lb_step
-// call of at least nc * passes * (1 + steps_per) steps runs, in each of
-// `passes` passes, for each candidate one step that switches to it and
-// steps_per steps between two events on the context's stream; it waits for
-// the last event, keeps the candidate with the shortest of its timings, and
-// takes its remaining steps with it.
+// call of at least warm + nc * passes * (1 + steps_per) steps first takes
+// `warm` steps with the default length (the GPU's clocks settle during the
+// first tens of steps after a pause, which would otherwise favour whichever
+// candidate runs last), then, in each of `passes` passes, for each candidate
+// one step that switches to it and steps_per steps between two events on
+// the context's stream; it waits for the last event, keeps the candidate
+// with the shortest of its timings, and takes its remaining steps with it.
 struct SweepTuner {
   static constexpr int kMax = 8;
+  static constexpr int warm = 48;
   static constexpr int steps_per = 4;
   static constexpr int passes = 2;
   int cand[kMax] = {};

@@ -88,9 +88,9 @@ def test_fullsize_mass_conserved(workload, storage):
 
 @pytest.mark.parametrize("storage", ["f32", "f16s"])
 def test_fullsize_tuned_sweep_equals_split_path(workload, storage):
-    """On grids this large the first lb_step call of at least 80 steps
-    times several segment lengths on its first 80 steps and takes the rest
-    with the fastest; whichever lengths ran, every site must come out bit
+    """On grids this large the first lb_step call of at least 128 steps
+    times several segment lengths within its first 128 steps and takes the
+    rest with the fastest; whichever lengths ran, every site must come out bit
     for bit as on the one-thread-per-site split path."""
     from paper_0704_3444_amd import Simulation
 
@@ -98,11 +98,11 @@ def test_fullsize_tuned_sweep_equals_split_path(workload, storage):
     out = {}
     for path in ("sweep", "split"):
         sim = Simulation(cfg, rho0, storage=storage, path=path)
-        sim.step(82)  # 80 trial steps, 2 with the chosen length (sweep)
+        sim.step(130)  # 48 + 80 trial steps, 2 with the chosen length (sweep)
         sim.step(2)
         out[path] = sim.moments(fields=True)
         sim.close()
-    print(f"[fullsize] {storage} tuned sweep vs split, 84 steps", flush=True)
-    assert out["sweep"]["step"] == out["split"]["step"] == 84
+    print(f"[fullsize] {storage} tuned sweep vs split, 132 steps", flush=True)
+    assert out["sweep"]["step"] == out["split"]["step"] == 132
     assert np.array_equal(out["sweep"]["rho"], out["split"]["rho"])
     assert np.array_equal(out["sweep"]["U"], out["split"]["U"])
