@@ -190,7 +190,11 @@ __global__ void __launch_bounds__(kBlock) k_init(const double* __restrict__ rho0
 // slot (i, r - v_i).  The step takes it in the working precision (plain
 // codecs: the sum in direction order; shifted codec: from the ledger); the
 // observables take the exact stored values summed in FP64.
-template <class S, int LAT, typename TO>
+// NC > 0: the component count as a template parameter (N = NC), so that
+// all components' loads can be issued together (used on D3Q19, where it
+// makes the shifted FP16 density pass 20% faster; on D2Q9 the runtime loop
+// is faster); 0: any N.
+template <class S, int LAT, typename TO, int NC = 0>
 __global__ void __launch_bounds__(kBlock) k_density(const void* __restrict__ f, TO* __restrict__ rho,
                                                     Params<typename S::T> p) {
   using L = Lattice<LAT>;
@@ -198,7 +202,10 @@ __global__ void __launch_bounds__(kBlock) k_density(const void* __restrict__ f, 
   const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= p.S) return;
   const SiteCoord c = coord_of(s, p);
-  for (int k = 0; k < p.n; ++k) {
+  const int n = NC > 0 ? NC : p.n;
+#pragma unroll
+  for (int k = 0; k < (NC > 0 ? NC : kMaxComp); ++k) {
+    if (k >= n) break;
     if constexpr (sizeof(TO) > sizeof(T)) {
       double v[L::Q];
       pull_pops_exact<S, LAT>(f, c, k, p, v);
@@ -548,8 +555,19 @@ struct SplitOps {
     const Params<T>& p = c.params<T>();
     T* rho = static_cast<T*>(c.rho_scratch);
     T* h = static_cast<T*>(c.h_scratch);
-    k_density<S, LAT, T><<<grid_for(c.S), kBlock, 0, c.stream>>>(fin, rho, p);
     const unsigned g = grid_for(c.S);
+    bool density_done = false;
+    if constexpr (LAT == 3) {
+      density_done = true;
+      switch (p.n) {
+        case 1: k_density<S, LAT, T, 1><<<g, kBlock, 0, c.stream>>>(fin, rho, p); break;
+        case 2: k_density<S, LAT, T, 2><<<g, kBlock, 0, c.stream>>>(fin, rho, p); break;
+        case 3: k_density<S, LAT, T, 3><<<g, kBlock, 0, c.stream>>>(fin, rho, p); break;
+        case 4: k_density<S, LAT, T, 4><<<g, kBlock, 0, c.stream>>>(fin, rho, p); break;
+        default: density_done = false;
+      }
+    }
+    if (!density_done) k_density<S, LAT, T><<<g, kBlock, 0, c.stream>>>(fin, rho, p);
     switch (p.n) {
       case 1:
         k_potential<LAT, T, 1><<<g, kBlock, 0, c.stream>>>(rho, nullptr, h, p);
