@@ -44,10 +44,20 @@ struct Run {
   int pad[2];
 };
 
-// Value of v held by lane (lane + d) mod 64, d = -1 or +1.
-template <typename T>
-__device__ __forceinline__ T rotate(T v, int lane, int d) {
-  return __shfl(v, (lane + d) & 63, 64);
+// Value of v held by lane (lane + d) mod 64, d = -1 or +1: a DPP rotation
+// of the whole wavefront by one lane (wave_ror:1 brings lane l - 1 to lane
+// l, wave_rol:1 lane l + 1), 32 bits at a time.
+__device__ __forceinline__ int rotate32(int v, int d) {
+  return d < 0 ? __builtin_amdgcn_update_dpp(0, v, 0x13C, 0xF, 0xF, false)   // wave_ror:1
+               : __builtin_amdgcn_update_dpp(0, v, 0x134, 0xF, 0xF, false);  // wave_rol:1
+}
+__device__ __forceinline__ float rotate(float v, int, int d) {
+  return __int_as_float(rotate32(__float_as_int(v), d));
+}
+__device__ __forceinline__ double rotate(double v, int, int d) {
+  const long long b = __double_as_longlong(v);
+  const int lo = rotate32(int(b & 0xffffffffll), d), hi = rotate32(int(b >> 32), d);
+  return __longlong_as_double((long long)(unsigned(lo)) | ((long long)hi << 32));
 }
 
 template <typename T>
