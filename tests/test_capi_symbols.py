@@ -4,6 +4,8 @@ import ctypes
 import os
 import re
 
+import numpy as np
+
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -54,6 +56,25 @@ def test_host_side_validation_without_device():
     with pytest.raises(lb.LBError):
         lb.lb_workspace_bytes(p)
     assert lb.load().lb_strerror(-5).decode().startswith("non-finite")
+
+
+def test_walls_validated_on_the_host():
+    """Walls are checked with the other parameters (no device call)."""
+    import lbinputs as LI
+    from paper_0704_3444_amd import lb
+
+    cfg, _ = LI.binary_spinodal(16)
+    assert lb.lb_workspace_bytes(lb.make_params(dict(cfg, walls=0b011))) > 0
+    line = LI.params("D1Q3", 2, (1,), chi=np.zeros((2, 2))) | {"walls": 1}  # a closed axis of one layer
+    bad = [lb.make_params(dict(cfg, walls=w)) for w in (0b100, 0b1000, -1)]  # no z axis on D2Q9; unknown bits
+    bad.append(lb.make_params(line))
+    p = lb.make_params(cfg)
+    p.reserved = 1
+    bad.append(p)
+    for q in bad:
+        with pytest.raises(lb.LBError) as ei:
+            lb.lb_workspace_bytes(q)
+        assert ei.value.code == lb.LB_EINVAL
 
 
 def test_lattice_tables_match_isotropy():
