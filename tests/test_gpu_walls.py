@@ -39,6 +39,22 @@ def test_walls_match_oracle(case, storage):
     assert e["mass"] < (1e-13 if storage == "f64" else 1e-6), e
 
 
+@pytest.mark.parametrize("case", [1, 2, 4])
+def test_walls_shifted_fp16_match_oracle(case):
+    """Shifted FP16 storage with walls: bounced populations move stored
+    FP16 values unchanged, so the accuracy is that of the periodic box
+    (about 1e-6 relative near the mean composition, 200 steps)."""
+    lattice, shape, walls, n = CASES[case]
+    cfg, rho0 = walled(lattice, shape, walls, n, 40 + case)
+    g = run_gpu(cfg, rho0, 200, storage="f16s", path="auto")
+    o = run_oracle(cfg, rho0, 200)
+    e = errors(g, o, cfg["theta"])
+    print(f"[walls] {lattice} {shape} walls={walls:03b} f16s: {e}", flush=True)
+    for k in ("rho", "U", "mu"):
+        assert e[k] < 1e-5, (k, e)
+    assert e["mass"] < 1e-7, e
+
+
 def test_walls_keep_mass_in_shifted_fp16():
     cfg, rho0 = walled("D2Q9", (48, 32), 0b011, 3, 50)
     g = run_gpu(cfg, rho0, 500, storage="f16s", path="auto", fields=True)
