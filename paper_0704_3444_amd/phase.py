@@ -94,3 +94,38 @@ def coexisting_phases(rho: np.ndarray, min_contrast: float = 0.02) -> Optional[d
             res["domains"] = len(doms)
     res["spread"] = spread
     return res
+
+
+def main(argv=None) -> None:
+    """Run one of the binodal run sets of Sec. IV and print the coexisting
+    compositions of every run:  python -m paper_0704_3444_amd.phase
+    binary_monomer [--steps N]."""
+    import argparse
+    import os
+    import sys
+
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import lbinputs
+
+    names = ("binary_monomer", "binary_polymer", "ternary_monomer", "ternary_polymer", "ternary_monomer_plait",
+             "ternary_polymer_plait")
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("experiment", choices=names)
+    ap.add_argument("--steps", type=int, default=0, help="steps per run (default: the paper's 50 000 or 200 000)")
+    ap.add_argument("--storage", default="f64", choices=("f64", "f32"))
+    args = ap.parse_args(argv)
+    runs = lbinputs.binodal_runs(args.experiment)
+    steps = args.steps or (50000 if args.experiment.startswith("binary") else 200000)
+    for (cfg, rho0, label), r in zip(runs, run_lines(runs, steps, storage=args.storage)):
+        ph = coexisting_phases(r["rho"]) if r["healthy"] else None
+        if not r["healthy"]:
+            print(f"{label:24s} unstable")
+        elif ph is None:
+            print(f"{label:24s} not separated")
+        else:
+            print(f"{label:24s} phi {np.round(ph['rich'], 5)} | {np.round(ph['poor'], 5)}  "
+                  f"plateau spread {ph['spread']:.1e}  A-rich domains {ph['domains']}")
+
+
+if __name__ == "__main__":
+    main()
