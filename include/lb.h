@@ -309,9 +309,10 @@ void lb_batch_free(lb_batch* b);
  * (lb_moments, lb_get_f, checkpoints) and keep their step counters.
  *
  * Requirements on the contexts: lattice LB_D1Q3, storage LB_F64 or LB_F32,
- * nx = 64, 128, 192 or 256, N <= 4, periodic (no walls); within a group the same N, storage, nx
- * and stream; no context twice.  Parameters of Eq. (ssLB) and Eq. (lgf)
- * (tau, theta, m, chi, kappa, force form) may differ between runs.
+ * nx = 64, 128, 192 or 256, N <= 4, periodic (no walls); within a group
+ * the same N, storage, nx and stream; no context twice.  Parameters of
+ * Eq. (ssLB) and Eq. (lgf) (tau, theta, m, chi, kappa, force form) may
+ * differ between runs.
  * ------------------------------------------------------------------------ */
 typedef struct lb_lines lb_lines;
 
