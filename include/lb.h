@@ -319,18 +319,23 @@ typedef struct lb_lines lb_lines;
 /* Form a group of n contexts (ctxs[0..n-1], host array of handles; the
  * library keeps the handles, not the array).  Uploads a table of the runs'
  * parameters and population addresses to device memory and waits for it.
- * The contexts must have taken steps of the same parity (e.g. all freshly
- * made) and must outlive the group.  Errors: LB_EINVAL (NULL, duplicates,
- * mixed N / storage / nx / stream / parity), LB_ENOTSUP (lattice, storage,
- * nx or N outside the requirements), LB_ENOMEM, LB_EDEVICE. */
+ * Every context holds two population copies; the current one must be the
+ * same of the two in every context (as after numbers of lb_step steps of
+ * the same parity, e.g. all freshly made).  The contexts must outlive the
+ * group.  Errors: LB_EINVAL (NULL, duplicates, mixed N / storage / nx /
+ * stream / current copy), LB_ENOTSUP (lattice, storage, nx or N outside the
+ * requirements), LB_ENOMEM, LB_EDEVICE. */
 int lb_lines_create(lb_ctx* const* ctxs, int32_t n, lb_lines** out);
 
 /* Advance every run of the group by nsteps steps, asynchronously on the
  * group's stream; each context's step counter grows by nsteps.  A density
  * that is not finite and > 0 in any step sets the context's health flag
  * (lb_moments then returns LB_ENUMERIC); the periodic checks of
- * check_every are not run.  Errors: LB_EINVAL (nsteps < 0, or a context
- * stepped outside the group since), LB_EDEVICE. */
+ * check_every are not run.  A call moves every context to its other copy.
+ * Steps taken outside the group in between are allowed when they leave
+ * each context on the copy the group left it on (an even number of lb_step
+ * steps).  Errors: LB_EINVAL (nsteps < 0, or a context whose current copy
+ * has changed since the group's last call), LB_EDEVICE. */
 int lb_lines_step(lb_lines* g, int64_t nsteps);
 
 /* Release the group (not its contexts); waits for the group's stream.  NULL

@@ -51,10 +51,10 @@ __device__ __forceinline__ int rotate32(int v, int d) {
   return d < 0 ? __builtin_amdgcn_update_dpp(0, v, 0x13C, 0xF, 0xF, false)   // wave_ror:1
                : __builtin_amdgcn_update_dpp(0, v, 0x134, 0xF, 0xF, false);  // wave_rol:1
 }
-__device__ __forceinline__ float rotate(float v, int, int d) {
+__device__ __forceinline__ float rotate(float v, int d) {
   return __int_as_float(rotate32(__float_as_int(v), d));
 }
-__device__ __forceinline__ double rotate(double v, int, int d) {
+__device__ __forceinline__ double rotate(double v, int d) {
   const long long b = __double_as_longlong(v);
   const int lo = rotate32(int(b & 0xffffffffll), d), hi = rotate32(int(b >> 32), d);
   return __longlong_as_double((long long)(unsigned(lo)) | ((long long)hi << 32));
@@ -107,8 +107,8 @@ __global__ void __launch_bounds__(64) k_lines(const Run<typename S::T>* __restri
     T rl[NC][P], rr[NC][P];
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
-      const T from_left = rotate(rho[k][P - 1], lane, -1);
-      const T from_right = rotate(rho[k][0], lane, +1);
+      const T from_left = rotate(rho[k][P - 1], -1);
+      const T from_right = rotate(rho[k][0], +1);
 #pragma unroll
       for (int j = 0; j < P; ++j) {
         rl[k][j] = j > 0 ? rho[k][j - 1] : from_left;
@@ -132,8 +132,8 @@ __global__ void __launch_bounds__(64) k_lines(const Run<typename S::T>* __restri
     T hl[NC][P], hr[NC][P];
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
-      const T from_left = rotate(h[k][P - 1], lane, -1);
-      const T from_right = rotate(h[k][0], lane, +1);
+      const T from_left = rotate(h[k][P - 1], -1);
+      const T from_right = rotate(h[k][0], +1);
 #pragma unroll
       for (int j = 0; j < P; ++j) {
         hl[k][j] = j > 0 ? h[k][j - 1] : from_left;
@@ -169,8 +169,8 @@ __global__ void __launch_bounds__(64) k_lines(const Run<typename S::T>* __restri
     // streaming: f_1 (v = +1) moves one site right, f_2 one site left
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
-      const T in1 = rotate(f[k][P - 1][1], lane, -1);
-      const T in2 = rotate(f[k][0][2], lane, +1);
+      const T in1 = rotate(f[k][P - 1][1], -1);
+      const T in2 = rotate(f[k][0][2], +1);
 #pragma unroll
       for (int j = P - 1; j > 0; --j) f[k][j][1] = f[k][j - 1][1];
       f[k][0][1] = in1;
@@ -284,7 +284,7 @@ int lb_lines_create(lb_ctx* const* ctxs, int32_t n, lb_lines** out) {
     if (c.prm.n_comp != c0.prm.n_comp || c.prm.storage != c0.prm.storage || c.prm.nx != c0.prm.nx)
       return fail_with(LB_EINVAL, ("every run of a group needs the same N, storage and nx" + at).c_str());
     if (c.stream != c0.stream) return fail_with(LB_EINVAL, ("every run of a group needs the same stream" + at).c_str());
-    if (c.cur != c0.cur) return fail_with(LB_EINVAL, ("every run of a group must have taken steps of the same parity" + at).c_str());
+    if (c.cur != c0.cur) return fail_with(LB_EINVAL, ("every run of a group must be on the same one of its two population copies" + at).c_str());
     for (int q = 0; q < r; ++q)
       if (ctxs[q] == h) return fail_with(LB_EINVAL, ("a context appears twice" + at).c_str());
   }
@@ -323,7 +323,7 @@ int lb_lines_step(lb_lines* g, int64_t nsteps) {
   if (nsteps < 0) return fail_with(LB_EINVAL, "nsteps must be >= 0");
   for (size_t r = 0; r < g->ctxs.size(); ++r)
     if (g->ctxs[r]->c.cur != g->cur)
-      return fail_with(LB_EINVAL, ("context " + std::to_string(r) + " was stepped outside the group").c_str());
+      return fail_with(LB_EINVAL, ("context " + std::to_string(r) + " has changed copies outside the group").c_str());
   if (nsteps == 0) return LB_OK;
   g->launch(g->runs, int(g->ctxs.size()), g->cur, static_cast<long long>(nsteps), g->stream);
   hipError_t e = hipGetLastError();

@@ -135,3 +135,24 @@ def test_group_argument_checks():
     g.close()
     for s in (a, b, c, d, e, f16):
         s.close()
+
+
+def test_even_outside_steps_keep_the_group_usable():
+    """Two lb_step steps between group calls leave the run on the copy the
+    group expects: the group goes on, and the run equals one stepped alone."""
+    from paper_0704_3444_amd import Lines, Simulation
+
+    p, r = line_cfg(2, 128, 31)
+    a, b = Simulation(p, r), Simulation(*line_cfg(2, 128, 32))
+    ref = Simulation(p, r)
+    g = Lines([a, b])
+    g.step(10)
+    a.step(2)
+    b.step(2)
+    g.step(5)
+    ref.step(17)
+    assert np.array_equal(a.get_f(), ref.get_f())
+    assert a.moments()["step"] == 17
+    g.close()
+    for s in (a, b, ref):
+        s.close()
