@@ -435,7 +435,12 @@ __global__ void __launch_bounds__(256) k_sweep_d2q9(const void* fin_v, void* fou
     put_rho_halo(ra, stage);
     if (k + 1 < rounds) {
       asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // the slot is read before it is staged again
+      // shifted FP16: the wave issues its staging loads at raised priority,
+      // ahead of the other waves' arithmetic (2.5% faster at 2048^2; the same
+      // for FP32 is 4% slower)
+      if constexpr (S::kShift) __builtin_amdgcn_s_setprio(1);
       stage_row<S, NC>(fin, p, gat, lane, x0, wrap_mod(ra + 4, ny), stage);
+      if constexpr (S::kShift) __builtin_amdgcn_s_setprio(0);
     }
     lds_barrier();
     put_h4(ya + 4 * k + 3);
