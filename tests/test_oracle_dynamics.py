@@ -123,6 +123,32 @@ def test_d3q19_diffusion():
     assert abs(-g / k ** 2 / D - 1) < 1e-2
 
 
+@pytest.mark.parametrize("lattice,direction", [("D2Q9", "y"), ("D2Q9", "x+y"), ("D2Q9", "x-y"), ("D3Q19", "z"),
+                                               ("D3Q19", "y+z")])
+@pytest.mark.parametrize("form", ["log", "expanded"])
+def test_diffusion_constant_off_axis_both_forms(lattice, direction, form):
+    """D = w theta (Eq. (woche)) along y, z and diagonals, for both lines of
+    Eq. (definef), at theta = 0.2.  At theta = 1/3 the ideal-mixing part of
+    the log-form potential cancels (1/3) ln rho^s and the force vanishes for
+    a binary at uniform total density, so the component gradients of the
+    force would go untested; at theta = 0.2 the force carries
+    -(1 - theta/c_s^2) of the lattice's own diffusion, and a force that
+    misses its y or z component diffuses at w/3 instead of w theta."""
+    L, tau, theta = 32, 1.0, 0.2
+    shape = (L, L) if lattice == "D2Q9" else (4, L, L)
+    S = int(np.prod(shape))
+    s = np.arange(S)
+    x, y = s % shape[0], (s // shape[0]) % shape[1]
+    z = s // (shape[0] * shape[1]) if lattice == "D3Q19" else 0 * s
+    coord = {"y": y, "z": z, "x+y": x + y, "x-y": x - y, "y+z": y + z}[direction]
+    nk2 = 1 if direction in ("y", "z") else 2  # |wave vector|^2 / k^2
+    p = binary(lattice, shape, tau=tau, theta=theta, form=form)
+    k = 2 * np.pi / L
+    g = measure_rate(p, 0.5, 0.05, coord, k, 100, 600)
+    D = (tau - 0.5) * theta
+    assert abs(-g / (nk2 * k ** 2) / D - 1) < 2e-2, (-g / (nk2 * k ** 2), D)
+
+
 def spinodal_case(lattice="D2Q9", shape=(24, 20), n=2, seed=5):
     if n == 2:
         p = binary(lattice, shape, kappa=0.01, chi=2.4)
