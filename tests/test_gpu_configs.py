@@ -76,7 +76,7 @@ def test_binary64_full_length_matches_oracle():
             g = run_gpu(cfg, rho0, 2000, storage=storage, path=path)
             e = errors(g, o, cfg["theta"])
             print(f"[configs] binary 64^2 2000 steps {storage} {path}: {e}", flush=True)
-            for k in ("rho", "f", "U", "mu"):
+            for k in ("rho", "f", "U_cs", "mu"):
                 assert e[k] < tol, (storage, path, k, e)
             assert e["mass"] < (1e-12 if storage == "f64" else 1e-6), (storage, path, e)
 

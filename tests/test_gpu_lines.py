@@ -75,9 +75,9 @@ def test_group_matches_oracle(storage):
         g.step(200)
         out = s.moments()
         out["f"] = s.get_f()
-        e = errors(out, run_oracle(p, r, 200), p["theta"])
+        e = errors(out, run_oracle(p, r, 200), p["theta"], lattice=p["lattice"])
         print(f"[lines] {storage} N={p['n_comp']} vs oracle, 200 steps: {e}", flush=True)
-        for k in ("rho", "f", "U", "mu"):
+        for k in ("rho", "f", "U_cs", "mu", "mom"):
             assert e[k] < TOL[storage], (k, e)
         g.close()
         s.close()

@@ -17,7 +17,7 @@ import numpy as np
 import pytest
 
 import lbinputs as LI
-from gpu_helpers import TOL, errors, paths_for, run_gpu, run_oracle
+from gpu_helpers import SAME_STATE_TOL, TOL, errors, oracle_observe_of, paths_for, run_gpu, run_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -48,13 +48,13 @@ def _cases():
 CASES = _cases()
 
 # f16s bars per case and quantity (3x the error measured at 200/300/100 steps)
-_NEAR_UNIFORM = {"rho": 1e-5, "f": 2e-5, "U": 1e-5, "mu": 2e-6, "P": 3e-5}
+_NEAR_UNIFORM = {"rho": 1e-5, "f": 2e-5, "U_cs": 1e-5, "mu": 2e-6, "P": 3e-5, "mom": 1e-4}
 F16S_TOL = {
     "binary64_spinodal": _NEAR_UNIFORM,
     "binary64_stable": _NEAR_UNIFORM,
-    "ternary_immersion_96x80": {"rho": 5e-2, "f": 5e-3, "U": 1e-3, "mu": 1.5e-2, "P": 4e-3},
-    "ternary_immersion_128x77": {"rho": 6e-2, "f": 5e-3, "U": 2.5e-3, "mu": 1.5e-2, "P": 4e-3},
-    "d1q3_polymer_130": {"rho": 1.5e-3, "f": 3e-4, "U": 4e-4, "mu": 1.2e-5, "P": 1e-12},
+    "ternary_immersion_96x80": {"rho": 5e-2, "f": 5e-3, "U_cs": 1e-3, "mu": 1.5e-2, "P": 4e-3, "mom": 1e-3},
+    "ternary_immersion_128x77": {"rho": 6e-2, "f": 5e-3, "U_cs": 2.5e-3, "mu": 1.5e-2, "P": 4e-3, "mom": 1e-3},
+    "d1q3_polymer_130": {"rho": 1.5e-3, "f": 3e-4, "U_cs": 4e-4, "mu": 1.2e-5, "P": 1e-12, "mom": 1e-3},
     "d3q19_ternary_12x10x9": _NEAR_UNIFORM,
     "five_40": _NEAR_UNIFORM,
 }
@@ -69,11 +69,16 @@ def test_gpu_matches_oracle(name, cfg, rho0, steps, storage):
         print(f"[parity] {name} storage={storage} path={path} steps={steps} shape={cfg['shape']}", flush=True)
         g = run_gpu(cfg, rho0, steps, storage=storage, path=path)
         assert g["path"] == path
-        e = errors(g, o, cfg["theta"])
+        e = errors(g, o, cfg["theta"], lattice=cfg["lattice"])
         print(f"[parity] {name} {storage} {path} errors {e}", flush=True)
-        for k in ("rho", "f", "U", "mu", "P"):
+        for k in ("rho", "f", "U_cs", "mu", "P", "mom"):
             tol = F16S_TOL[name][k] if storage == "f16s" else TOL[storage]
             assert e[k] < tol, (path, k, e)
+        # the observables of the GPU's own final state, by the oracle's formulas
+        es = errors(g, oracle_observe_of(cfg, rho0, g["f"]), cfg["theta"], lattice=cfg["lattice"])
+        print(f"[parity] {name} {storage} {path} same-state observables {es}", flush=True)
+        for k in ("rho", "U", "mu", "P", "mom", "mass"):
+            assert es[k] < SAME_STATE_TOL, (path, "same-state", k, es)
         assert e["mass"] < (1e-13 if storage == "f64" else 1e-6), (path, e)
 
 
@@ -117,8 +122,8 @@ def test_degenerate_and_ragged_boxes(shape):
         tol = _NEAR_UNIFORM["rho"] if storage == "f16s" else TOL[storage]
         for path in paths_for(p, storage):
             g = run_gpu(p, r, 20, storage=storage, path=path)
-            e = errors(g, o)
-            assert e["rho"] < tol and e["f"] < 2 * tol, (shape, S, storage, path, e)
+            e = errors(g, o, lattice=p["lattice"])
+            assert e["rho"] < tol and e["f"] < 2 * tol and e["mom"] < 10 * tol, (shape, S, storage, path, e)
 
 
 @pytest.mark.parametrize("n", [1, 2, 4, 6, 8])
@@ -169,3 +174,43 @@ def test_f16s_mass_exact_and_zero_steps():
         drift = np.abs(m1 / m0 - 1).max()
         print(f"[f16s-mass] {path} drift over 2000 steps {drift:.3e}", flush=True)
         assert drift < 1e-14, (path, drift)
+
+
+@pytest.mark.parametrize("lattice", ["D2Q9", "D3Q19"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16s"])
+def test_mirror_symmetric_start_keeps_momentum_zero(lattice, storage):
+    """A start that is mirror symmetric along every axis (rho0(r) = rho0(-r),
+    periodic) stays so; the total first moment then vanishes on each axis
+    (Sec. III first moments).  The GPU's FP64 sum must stay at rounding level
+    relative to the total mass times c_s, on every path, while the oracle's
+    does the same.  Each step's rounding is not mirror symmetric, so the
+    bars follow from its random accumulation, about
+    sqrt(steps S N Q) u max(f) / (M c_s) with u the storage's rounding unit
+    (FP32: 2e-8 on the 64 x 48 binary box; shifted FP16: 2^-11 of the
+    stored deviations, about 4e-7), with a 10x margin.  A kernel that breaks
+    the mirror symmetry gives an O(1e-3) or larger value."""
+    from gpu_helpers import CS
+
+    if lattice == "D2Q9":
+        p, _ = LI.binary_spinodal(64, chi=1.6)
+        p["shape"] = (64, 48)
+    else:
+        p, _ = LI.ternary_d3q19(12, chi=2.0)
+        p["shape"] = (12, 10, 8)
+    dims = list(p["shape"]) + [1] * (3 - len(p["shape"]))
+    r = LI.noisy_uniform(p, [1.0 / p["n_comp"]] * p["n_comp"], 0.01, 21)
+    r = r.reshape(p["n_comp"], dims[2], dims[1], dims[0])
+    for ax in (1, 2, 3):  # symmetrise: average with the mirror image x -> -x (mod n) along each axis
+        r = 0.5 * (r + np.roll(np.flip(r, axis=ax), 1, axis=ax))
+    r = np.ascontiguousarray(r.reshape(p["n_comp"], -1))
+    steps = 200
+    o = run_oracle(p, r, steps)
+    scale = float(r.sum()) * CS
+    bar = {"f64": 1e-13, "f32": 2e-7, "f16s": 4e-6}[storage]
+    assert np.abs(o["mom"]).max() / scale < 1e-13
+    for path in paths_for(p, storage):
+        g = run_gpu(p, r, steps, storage=storage, path=path, fields=False)
+        rel = np.abs(g["mom"]).max() / scale
+        print(f"[mirror] {lattice} {storage} {path}: |Pi|/(M c_s) = {rel:.3e} (oracle "
+              f"{np.abs(o['mom']).max() / scale:.3e})", flush=True)
+        assert rel < bar, (path, g["mom"])

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import lbinputs as LI
-from gpu_helpers import TOL, errors, run_gpu, run_oracle
+from gpu_helpers import SAME_STATE_TOL, TOL, errors, oracle_observe_of, run_gpu, run_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -32,11 +32,15 @@ def test_walls_match_oracle(case, storage):
     g = run_gpu(cfg, rho0, 200, storage=storage, path="auto")
     assert g["path"] == "split"
     o = run_oracle(cfg, rho0, 200)
-    e = errors(g, o, cfg["theta"])
+    e = errors(g, o, cfg["theta"], lattice=lattice)
     print(f"[walls] {lattice} {shape} walls={walls:03b} {storage}: {e}", flush=True)
-    for k in ("rho", "f", "U", "mu"):
+    for k in ("rho", "f", "U_cs", "mu", "mom"):
         assert e[k] < TOL[storage], (k, e)
     assert e["mass"] < (1e-13 if storage == "f64" else 1e-6), e
+    es = errors(g, oracle_observe_of(cfg, rho0, g["f"]), cfg["theta"], lattice=lattice)
+    print(f"[walls] {lattice} {shape} walls={walls:03b} {storage} same-state observables: {es}", flush=True)
+    for k in ("rho", "U", "mu", "P", "mom", "mass"):
+        assert es[k] < SAME_STATE_TOL, (k, es)
 
 
 @pytest.mark.parametrize("case", [1, 2, 4])
@@ -50,7 +54,7 @@ def test_walls_shifted_fp16_match_oracle(case):
     o = run_oracle(cfg, rho0, 200)
     e = errors(g, o, cfg["theta"])
     print(f"[walls] {lattice} {shape} walls={walls:03b} f16s: {e}", flush=True)
-    for k in ("rho", "U", "mu"):
+    for k in ("rho", "U_cs", "mu"):
         assert e[k] < 1e-5, (k, e)
     assert e["mass"] < 1e-7, e
 
@@ -100,7 +104,7 @@ def test_immersion_film_on_a_wall():
     o = run_oracle(cfg, rho0, 100)
     e = errors(g, o, cfg["theta"])
     print(f"[walls] immersion film on a wall, 100 steps, f32: {e}", flush=True)
-    for k in ("rho", "f", "U", "mu"):
+    for k in ("rho", "f", "U_cs", "mu"):
         assert e[k] < TOL["f32"], (k, e)
     sim = Simulation(cfg, rho0, storage="f32")
     sim.step(3000)
