@@ -5,7 +5,7 @@
  * (arXiv:0704.3444).
  *
  * The library advances N component distributions f^sigma_i on a periodic
- * lattice by the per-component lattice Boltzmann equation Eq. (ssLB) (BGK
+ * lattice (or a box closed by walls) by the per-component lattice Boltzmann equation Eq. (ssLB) (BGK
  * collision with relaxation time tau plus a forcing term, then streaming),
  * with the equilibrium moments and forcing moments Eqs. (ff1)-(ff3) of
  * Sec. III, the force of Eq. (definef), and the chemical potentials of the
@@ -14,7 +14,8 @@
  *
  * Conventions shared by every entry point:
  *   - lattice units, dt = dx = 1, c_s^2 = 1/3;
- *   - site index s = x + nx*(y + ny*z); every axis is periodic;
+ *   - site index s = x + nx*(y + ny*z); every axis is periodic unless
+ *     lb_params.walls closes it;
  *   - host arrays are caller-owned FP64, component-major structure of
  *     arrays (e.g. rho[sigma][s]);
  *   - device state is owned by the context (in caller-provided device
@@ -138,6 +139,13 @@ size_t lb_workspace_bytes(const lb_params* p);
  *              aligned, owned by the caller and kept alive until lb_free; or
  *              NULL, in which case the library allocates (and frees) its own.
  *   out        receives the context.
+ * On the strip-sweep path (lb_path_in_use) of a grid of at least 2^20
+ * sites, lb_init also chooses the sweep's segment length on the new state:
+ * it takes 48 steps, then times up to 8 segment lengths (twice each: one
+ * step to switch, then 4 between events on the stream), keeps the fastest
+ * and returns the state to rest equilibrium before returning (a few tens of
+ * milliseconds at 2048^2).  Every segment length gives the same results bit
+ * for bit; lb_step itself never times or waits.
  * Errors: LB_EINVAL (parameters, rho0 <= 0 or non-finite, misaligned
  * workspace), LB_ENOMEM (workspace_bytes too small, allocation failure),
  * LB_EDEVICE. */
@@ -146,14 +154,8 @@ int lb_init(const lb_params* p, const double* rho0, void* workspace, size_t work
 
 /* Advance nsteps >= 0 time steps of Eq. (ssLB): per site and component the
  * moments, chemical potentials, force, equilibrium, forcing term, BGK
- * collision and streaming.  Asynchronous on the context's stream.
- * On the strip-sweep path (lb_path_in_use) of a grid of at least 2^20
- * sites, the first call with at least 128 steps (not during stream
- * capture) takes 48 steps, then times up to 8 segment lengths of the sweep
- * (twice each: one step to switch, then 4 between events on the stream),
- * waits for those events (a few milliseconds) and takes its remaining
- * steps, and all later ones, with the fastest.  Every segment length gives the same
- * results bit for bit. */
+ * collision and streaming.  Asynchronous on the context's stream: it only
+ * enqueues kernels (it may be recorded under stream capture). */
 int lb_step(lb_ctx* c, int64_t nsteps);
 
 /* Observables at the current time, computed on the device in FP64 from the

@@ -380,7 +380,7 @@ int lb_batch_add(lb_batch* b, const lb_params* p, const double* rho0, int64_t ns
   q.path = LB_PATH_AUTO;
   q.check_every = 0;
   lb_ctx* ctx = nullptr;
-  rc = lbm::init_impl(&q, rho0, b->arena + off, bytes, b->staging, &ctx);
+  rc = lbm::init_impl(&q, rho0, b->arena + off, bytes, b->staging, false, &ctx);
   if (rc != LB_OK) {
     b->alloc.release(off, bytes);
     return rc;

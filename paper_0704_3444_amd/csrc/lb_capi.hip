@@ -193,94 +193,70 @@ lbm::ShiftRef shift_ref_of(const lb_params* p, const double* rho0, size_t S) {
   return r;
 }
 
-void destroy_tuner_events(lbm::SweepTuner& tu) {
-  for (hipEvent_t& e : tu.ev) {
-    if (e) (void)hipEventDestroy(e);
-    e = nullptr;
-  }
+// One time step of the context's path on its stream (no health check).
+void step_once(Ctx& c) {
+  void* fin = c.f[c.cur];
+  void* fout = c.f[1 - c.cur];
+  if (c.path != LB_PATH_SPLIT && c.fused)
+    c.fused(c, fin, fout);
+  else
+    lbm::split_table(c.prm.lattice, c.prm.storage).step(c, fin, fout);
+  c.cur = 1 - c.cur;
+  c.t += 1;
 }
 
-// After the trial steps: the candidate with the shortest timing over its
-// passes (the caller has waited for the last event).
-void finish_tuning(Ctx& c) {
-  lbm::SweepTuner& tu = c.tune;
+// Segment length of the sweep (SweepTuner): trial steps on the context's
+// state, timed with events on its stream; waits for the last event.  The
+// caller restores the state afterwards.  On any HIP failure the one-wave
+// default is kept.
+void tune_sweep(Ctx& c) {
+  using Tu = lbm::SweepTuner;
+  int cand[Tu::kMax];
+  const int nc = lbm::sweep_candidates(c, cand);
+  c.sweep_rows = 0;
+  if (nc <= 0) return;
+  hipEvent_t ev[2 * Tu::kMax * Tu::passes] = {};
+  const int nev = 2 * nc * Tu::passes;
+  bool ok = true;
+  for (int i = 0; ok && i < nev; ++i) ok = hipEventCreate(&ev[i]) == hipSuccess;
+  if (ok) {
+    for (int j = 0; j < Tu::warm; ++j) step_once(c);
+    for (int q = 0; q < Tu::passes; ++q)
+      for (int i = 0; i < nc; ++i) {
+        const int e = 2 * (q * nc + i);
+        c.sweep_rows = cand[i];
+        step_once(c);
+        (void)hipEventRecord(ev[e], c.stream);
+        for (int j = 0; j < Tu::steps_per; ++j) step_once(c);
+        (void)hipEventRecord(ev[e + 1], c.stream);
+      }
+    ok = hipEventSynchronize(ev[nev - 1]) == hipSuccess;
+  }
   int best = -1;
   float best_ms = 0.f;
-  for (int i = 0; i < tu.nc; ++i) {
-    for (int q = 0; q < tu.passes; ++q) {
-      const int e = 2 * (q * tu.nc + i);
+  for (int i = 0; ok && i < nc; ++i)
+    for (int q = 0; q < Tu::passes; ++q) {
+      const int e = 2 * (q * nc + i);
       float ms = 0.f;
-      if (hipEventElapsedTime(&ms, tu.ev[e], tu.ev[e + 1]) != hipSuccess) continue;
+      if (hipEventElapsedTime(&ms, ev[e], ev[e + 1]) != hipSuccess) continue;
       if (best < 0 || ms < best_ms) {
         best = i;
         best_ms = ms;
       }
     }
-  }
+  for (int i = 0; i < nev; ++i)
+    if (ev[i]) (void)hipEventDestroy(ev[i]);
   (void)hipGetLastError();
-  c.sweep_rows = best >= 0 ? tu.cand[best] : 0;
-  destroy_tuner_events(tu);
-  tu.done = true;
+  c.sweep_rows = best >= 0 ? cand[best] : 0;
 }
 
 // Step the context's state n times on its stream.
 int advance(Ctx& c, int64_t n) {
   const lbm::SplitTable& st = lbm::split_table(c.prm.lattice, c.prm.storage);
-  lbm::FusedStepFn fused = c.path == LB_PATH_SPLIT ? nullptr : c.fused;
-  auto step = [&]() {
-    void* fin = c.f[c.cur];
-    void* fout = c.f[1 - c.cur];
-    if (fused)
-      fused(c, fin, fout);
-    else
-      st.step(c, fin, fout);
-    c.cur = 1 - c.cur;
-    c.t += 1;
+  for (int64_t k = 0; k < n; ++k) {
+    step_once(c);
     if (c.prm.check_every > 0 && c.t % c.prm.check_every == 0) st.diag(c, c.f[c.cur]);
-  };
-  int64_t k = 0;
-  lbm::SweepTuner& tu = c.tune;
-  const int64_t trial_steps = tu.warm + int64_t(tu.nc) * tu.passes * (1 + tu.steps_per);
-  if (c.path == LB_PATH_SWEEP && !tu.done && tu.nc > 0 && n >= trial_steps) {
-    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    const bool capturing = hipStreamIsCapturing(c.stream, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone;
-    (void)hipGetLastError();
-    if (!capturing) {
-      // trial steps: in each pass, every candidate for one step that
-      // switches to it and steps_per steps between two events
-      const int nev = 2 * tu.nc * tu.passes;
-      bool ok = true;
-      for (int i = 0; ok && i < nev; ++i) ok = hipEventCreate(&tu.ev[i]) == hipSuccess;
-      if (!ok) {
-        destroy_tuner_events(tu);
-        (void)hipGetLastError();
-        tu.done = true;
-      } else {
-        c.sweep_rows = 0;
-        for (int j = 0; j < tu.warm; ++j, ++k) step();
-        for (int q = 0; q < tu.passes; ++q) {
-          for (int i = 0; i < tu.nc; ++i) {
-            const int e = 2 * (q * tu.nc + i);
-            c.sweep_rows = tu.cand[i];
-            step();
-            ++k;
-            (void)hipEventRecord(tu.ev[e], c.stream);
-            for (int j = 0; j < tu.steps_per; ++j, ++k) step();
-            (void)hipEventRecord(tu.ev[e + 1], c.stream);
-          }
-        }
-        if (hipEventSynchronize(tu.ev[nev - 1]) == hipSuccess) {
-          finish_tuning(c);
-        } else {
-          (void)hipGetLastError();
-          destroy_tuner_events(tu);
-          c.sweep_rows = 0;
-          tu.done = true;
-        }
-      }
-    }
   }
-  for (; k < n; ++k) step();
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return LB_OK;
@@ -306,7 +282,7 @@ namespace lbm {
 // lb_init with an optional device staging buffer for rho0 (at least
 // N * S doubles); without one, a buffer is allocated and freed here.
 int init_impl(const lb_params* p, const double* rho0, void* workspace, size_t workspace_bytes, double* staging,
-              lb_ctx** out) {
+              bool tune, lb_ctx** out) {
   std::string why;
   if (!out) return fail(LB_EINVAL, "out is NULL");
   *out = nullptr;
@@ -407,6 +383,20 @@ int init_impl(const lb_params* p, const double* rho0, void* workspace, size_t wo
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
+  if (e == hipSuccess && tune && c.path == LB_PATH_SWEEP) {
+    // choose the sweep's segment length on this very state, then return to
+    // rest equilibrium with both copies cleared as above
+    c.cur = 0;
+    tune_sweep(c);
+    e = hipMemsetAsync(c.f[0], 0, fbytes, c.stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c.f[1], 0, fbytes, c.stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c.health_flag, 0, sizeof(int), c.stream);
+    if (e == hipSuccess) {
+      lbm::split_table(p->lattice, p->storage).init(c, rho_dev, c.f[0]);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
+  }
   if (!staging) (void)hipFree(rho_dev);
   if (e != hipSuccess) {
     lb_free(h);
@@ -436,9 +426,7 @@ int moments_impl(lb_ctx* h, void* scratch, double* rho, double* U, double* mu, d
 extern "C" {
 
 int lb_init(const lb_params* p, const double* rho0, void* workspace, size_t workspace_bytes, lb_ctx** out) {
-  const int rc = lbm::init_impl(p, rho0, workspace, workspace_bytes, nullptr, out);
-  if (rc == LB_OK && (*out)->c.path == LB_PATH_SWEEP) (*out)->c.tune.nc = lbm::sweep_candidates((*out)->c, (*out)->c.tune.cand);
-  return rc;
+  return lbm::init_impl(p, rho0, workspace, workspace_bytes, nullptr, true, out);
 }
 
 int lb_step(lb_ctx* h, int64_t nsteps) {
@@ -613,7 +601,6 @@ void lb_free(lb_ctx* h) {
   if (!h) return;
   Ctx& c = h->c;
   (void)hipStreamSynchronize(c.stream);
-  destroy_tuner_events(c.tune);
   if (c.owns_ws && c.ws) (void)hipFree(c.ws);
   delete h;
 }

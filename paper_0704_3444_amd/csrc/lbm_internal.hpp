@@ -18,23 +18,18 @@ FusedStepFn sweep_step_for(int storage, int n_comp);               // strip swee
 // default first) into cand; 0 when the grid is too small to tune.
 int sweep_candidates(const Ctx& c, int* cand);
 
-// Choice of the sweep's segment length during stepping: the first lb_step
-// call of at least warm + nc * passes * (1 + steps_per) steps first takes
-// `warm` steps with the default length (the GPU's clocks settle during the
-// first tens of steps after a pause, which would otherwise favour whichever
-// candidate runs last), then, in each of `passes` passes, for each candidate
-// one step that switches to it and steps_per steps between two events on
-// the context's stream; it waits for the last event, keeps the candidate
-// with the shortest of its timings, and takes its remaining steps with it.
+// Choice of the sweep's segment length, made once in lb_init on the freshly
+// initialised state (which is restored afterwards): first `warm` steps with
+// the default length (the GPU's clocks settle during the first tens of steps
+// after a pause, which would otherwise favour whichever candidate runs
+// last), then, in each of `passes` passes, for each candidate one step that
+// switches to it and steps_per steps between two events on the context's
+// stream; the candidate with the shortest of its timings is kept.
 struct SweepTuner {
   static constexpr int kMax = 8;
   static constexpr int warm = 48;
   static constexpr int steps_per = 4;
   static constexpr int passes = 2;
-  int cand[kMax] = {};
-  int nc = 0;             // candidates; 0: nothing to tune
-  bool done = false;
-  hipEvent_t ev[2 * kMax * passes] = {};
 };
 
 // Context behind the opaque lb_ctx handle.
@@ -63,7 +58,6 @@ struct Ctx {
   int path = LB_PATH_SPLIT;
   FusedStepFn fused = nullptr;      // kernel of LB_PATH_TILE / LB_PATH_SWEEP
   int sweep_rows = 0;               // segment length of the sweep (0: one-wave default)
-  SweepTuner tune;
 
   Params<float> pf;
   Params<double> pd;
@@ -122,7 +116,7 @@ const BatchKernel* batch_kernels(int storage, int max_comp, int* n);
 // Entry points of lb_capi.hip shared with the batch runtime.
 int fail_with(int code, const char* msg);  // sets lb_last_error, returns code
 int init_impl(const lb_params* p, const double* rho0, void* workspace, size_t workspace_bytes, double* staging,
-              lb_ctx** out);
+              bool tune, lb_ctx** out);
 size_t moments_scratch_bytes(const lb_ctx* h);
 int moments_impl(lb_ctx* h, void* scratch, double* rho, double* U, double* mu, double* P, double* mass,
                  double* mom, int64_t* step);

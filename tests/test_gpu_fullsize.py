@@ -88,17 +88,16 @@ def test_fullsize_mass_conserved(workload, storage):
 
 @pytest.mark.parametrize("storage", ["f32", "f16s"])
 def test_fullsize_tuned_sweep_equals_split_path(workload, storage):
-    """On grids this large the first lb_step call of at least 128 steps
-    times several segment lengths within its first 128 steps and takes the
-    rest with the fastest; whichever lengths ran, every site must come out bit
-    for bit as on the one-thread-per-site split path."""
+    """On grids this large lb_init times several segment lengths on the new
+    state and restores it; whichever length it keeps, every site must come
+    out bit for bit as on the one-thread-per-site split path."""
     from paper_0704_3444_amd import Simulation
 
     cfg, rho0 = workload
     out = {}
     for path in ("sweep", "split"):
         sim = Simulation(cfg, rho0, storage=storage, path=path)
-        sim.step(130)  # 48 + 80 trial steps, 2 with the chosen length (sweep)
+        sim.step(130)
         sim.step(2)
         out[path] = sim.moments(fields=True)
         sim.close()

@@ -157,10 +157,9 @@ def test_healthy_run_with_checks_reports_ok():
 
 
 def test_sweep_steps_captured_in_a_hip_graph():
-    """lb_step enqueued under stream capture records only kernels (the
-    segment-length trials, which need timed events, are skipped while
-    capturing); every replay of the graph must equal the same steps run
-    eagerly, where the trials do run (1024^2 sites: large enough to tune)."""
+    """lb_step enqueued under stream capture records only kernels; every
+    replay of the graph must equal the same steps run eagerly (1024^2 sites:
+    large enough for lb_init to choose a segment length)."""
     import torch
 
     cfg, rho0 = LI.ternary_immersion(1024)
