@@ -177,6 +177,26 @@ int lb_step(lb_ctx* c, int64_t nsteps);
 int lb_moments(lb_ctx* c, double* rho, double* U, double* mu, double* P, double* mass,
                double* mom, int64_t* step);
 
+/* lb_moments for callers that cannot allocate device memory (loops that
+ * must not call hipMalloc between steps, harnesses that forbid it): the
+ * same outputs, bit for bit, from the same kernels, but the device buffers
+ * in which the fields are formed (rho, mu, h, U and P in FP64:
+ * (3 N + D + D (D + 1) / 2) * S * 8 bytes) are a static array of
+ * LB_NOALLOC_SCRATCH_BYTES bytes that the library holds on each device it
+ * runs on until the process ends; it allocates nothing, on the device or
+ * the host.  The mass and momentum sums use the context's own workspace.
+ * The calling thread's current device must be the context's.  Every call on
+ * one device shares that device's array: calls that overlap on one device
+ * (from several threads, or on several streams) race.  Each call writes
+ * every element it reads, so no state carries over between calls.
+ * Errors: as lb_moments, and LB_ENOMEM (any field pointer non-NULL while the
+ * fields need more than LB_NOALLOC_SCRATCH_BYTES; mass, mom and step alone
+ * need no scratch), LB_EINVAL (another device current), LB_EDEVICE (the
+ * array's address could not be obtained). */
+#define LB_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+int lb_moments_noalloc(lb_ctx* c, double* rho, double* U, double* mu, double* P, double* mass,
+                       double* mom, int64_t* step);
+
 /* Populations f^sigma_i(r, t) at the current time as host FP64 [N][Q][S],
  * velocity order of the lattice tables (lb_lattice_tables).  Synchronises. */
 int lb_get_f(lb_ctx* c, double* f);

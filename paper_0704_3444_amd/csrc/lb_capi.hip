@@ -6,14 +6,20 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
-#include <vector>
 
 #include "lb.h"
 #include "lbm_internal.hpp"
 
 using lbm::Ctx;
+
+// Device scratch of lb_moments_noalloc: the FP64 field buffers of the
+// observables (rho, mu, h, U, P), for callers that cannot allocate.  Each
+// device holds its own copy of the array; host code uses only the address
+// hipGetSymbolAddress gives for the current device, never the array's name.
+static __device__ __align__(256) unsigned char scratch[LB_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -33,6 +39,32 @@ int hip_fail(hipError_t e, const char* what) {
     hipError_t e_ = (call);                            \
     if (e_ != hipSuccess) return hip_fail(e_, #call);  \
   } while (0)
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of `scratch` on device dev (the current device), looked up once
+// per device; nullptr with the HIP error on failure.
+void* scratch_on(int dev, hipError_t* err) {
+  *err = hipSuccess;
+  if (dev < 0 || dev >= kMaxDevices) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      *err = e != hipSuccess ? e : hipErrorInvalidSymbol;
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
 
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -308,6 +340,16 @@ int init_impl(const lb_params* p, const double* rho0, void* workspace, size_t wo
   c.real_bytes = work_bytes(p);
   c.pop_bytes = population_bytes(p);
   c.stream = static_cast<hipStream_t>(p->stream);
+  if (hipGetDevice(&c.device) != hipSuccess) {
+    delete h;
+    return hip_fail(hipGetLastError(), "hipGetDevice");
+  }
+  {
+    // the address of lb_moments_noalloc's scratch on this device, looked up
+    // here once per device; a failure is reported by that call instead
+    hipError_t se = hipSuccess;
+    (void)scratch_on(c.device, &se);
+  }
   if (workspace) {
     c.ws = workspace;
     c.ws_bytes = workspace_bytes;
@@ -418,7 +460,7 @@ size_t moments_scratch_bytes(const lb_ctx* h) {
   return (3 * N + D + D * (D + 1) / 2) * S * sizeof(double);
 }
 
-int moments_impl(lb_ctx* h, void* scratch, double* rho, double* U, double* mu, double* P, double* mass,
+int moments_impl(lb_ctx* h, void* field_buf, double* rho, double* U, double* mu, double* P, double* mass,
                  double* mom, int64_t* step);
 
 }  // namespace lbm
@@ -440,11 +482,36 @@ int lb_moments(lb_ctx* h, double* rho, double* U, double* mu, double* P, double*
   return lbm::moments_impl(h, nullptr, rho, U, mu, P, mass, mom, step);
 }
 
+int lb_moments_noalloc(lb_ctx* h, double* rho, double* U, double* mu, double* P, double* mass, double* mom,
+                       int64_t* step) {
+  if (!h) return fail(LB_EINVAL, "ctx is NULL");
+  const bool fields = rho || U || mu || P;
+  void* buf = nullptr;
+  if (fields) {
+    const size_t need = lbm::moments_scratch_bytes(h);
+    if (need > LB_NOALLOC_SCRATCH_BYTES) {
+      char msg[200];
+      std::snprintf(msg, sizeof msg,
+                    "lb_moments_noalloc: the fields need %zu bytes of device scratch, above its static %zu; "
+                    "use lb_moments, or ask for mass, mom and step only",
+                    need, size_t(LB_NOALLOC_SCRATCH_BYTES));
+      return fail(LB_ENOMEM, msg);
+    }
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return hip_fail(hipGetLastError(), "hipGetDevice");
+    if (dev != h->c.device) return fail(LB_EINVAL, "lb_moments_noalloc: the context's device is not current");
+    hipError_t e = hipSuccess;
+    buf = scratch_on(dev, &e);
+    if (!buf) return hip_fail(e, "hipGetSymbolAddress of the lb_moments_noalloc scratch");
+  }
+  return lbm::moments_impl(h, buf, rho, U, mu, P, mass, mom, step);
+}
+
 }  // extern "C"
 
-// lb_moments with an optional device scratch of moments_scratch_bytes;
-// without one, the field buffers are allocated and freed here.
-int lbm::moments_impl(lb_ctx* h, void* scratch, double* rho, double* U, double* mu, double* P, double* mass,
+// lb_moments with optional device field buffers of moments_scratch_bytes;
+// without them, the field buffers are allocated and freed here.
+int lbm::moments_impl(lb_ctx* h, void* field_buf, double* rho, double* U, double* mu, double* P, double* mass,
                       double* mom, int64_t* step) {
   if (!h) return fail(LB_EINVAL, "ctx is NULL");
   Ctx& c = h->c;
@@ -457,8 +524,8 @@ int lbm::moments_impl(lb_ctx* h, void* scratch, double* rho, double* U, double* 
   if (fields) {
     const size_t nP = size_t(D) * (D + 1) / 2;
     hipError_t e = hipSuccess;
-    if (scratch) {
-      d_rho = static_cast<double*>(scratch);
+    if (field_buf) {
+      d_rho = static_cast<double*>(field_buf);
       d_mu = d_rho + N * S;
       d_h = d_mu + N * S;
       d_U = d_h + N * S;
@@ -482,20 +549,21 @@ int lbm::moments_impl(lb_ctx* h, void* scratch, double* rho, double* U, double* 
       if (e != hipSuccess) rc = hip_fail(e, "lb_moments");
     }
   }
-  std::vector<double> out(lbm::kMaxComp + D + 1, 0.0);
+  double out[lbm::kMaxComp + 3 + 1] = {};  // masses, momentum (D <= 3), flag
+  const size_t nout = size_t(lbm::kMaxComp + D + 1);
   int flag = 0;
   if (rc == LB_OK) {
     st.diag(c, c.f[c.cur]);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess)
-      e = hipMemcpyAsync(out.data(), c.diag_out, out.size() * sizeof(double), hipMemcpyDeviceToHost, c.stream);
+      e = hipMemcpyAsync(out, c.diag_out, nout * sizeof(double), hipMemcpyDeviceToHost, c.stream);
     if (e == hipSuccess) e = hipMemcpyAsync(&flag, c.health_flag, sizeof(int), hipMemcpyDeviceToHost, c.stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
     if (e != hipSuccess) rc = hip_fail(e, "lb_moments");
   } else {
     (void)hipStreamSynchronize(c.stream);
   }
-  if (!scratch) {
+  if (fields && !field_buf) {
     (void)hipFree(d_rho);
     (void)hipFree(d_mu);
     (void)hipFree(d_h);

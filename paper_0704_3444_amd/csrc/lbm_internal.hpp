@@ -54,6 +54,7 @@ struct Ctx {
   int* health_flag = nullptr;       // sticky: 1 once a bad density was seen
   int diag_blocks = 0;
 
+  int device = 0;                   // HIP device current at lb_init
   int64_t t = 0;
   int path = LB_PATH_SPLIT;
   FusedStepFn fused = nullptr;      // kernel of LB_PATH_TILE / LB_PATH_SWEEP
@@ -118,7 +119,7 @@ int fail_with(int code, const char* msg);  // sets lb_last_error, returns code
 int init_impl(const lb_params* p, const double* rho0, void* workspace, size_t workspace_bytes, double* staging,
               bool tune, lb_ctx** out);
 size_t moments_scratch_bytes(const lb_ctx* h);
-int moments_impl(lb_ctx* h, void* scratch, double* rho, double* U, double* mu, double* P, double* mass,
+int moments_impl(lb_ctx* h, void* field_buf, double* rho, double* U, double* mu, double* P, double* mass,
                  double* mom, int64_t* step);
 
 }  // namespace lbm

@@ -24,7 +24,7 @@ FORCE_FORM = {"log": 0, "expanded": 1}
 PATH = {"auto": 0, "tile": 1, "split": 2, "sweep": 3}
 
 EXPORTS = [
-    "lb_workspace_bytes", "lb_init", "lb_step", "lb_moments", "lb_get_f", "lb_state_bytes",
+    "lb_workspace_bytes", "lb_init", "lb_step", "lb_moments", "lb_moments_noalloc", "lb_get_f", "lb_state_bytes",
     "lb_get_state", "lb_set_state", "lb_lattice_tables", "lb_path_in_use", "lb_free",
     "lb_strerror", "lb_last_error",
     "lb_batch_create", "lb_batch_footprint", "lb_batch_add", "lb_batch_step", "lb_batch_poll",
@@ -81,6 +81,7 @@ def load() -> C.CDLL:
     lib.lb_init.argtypes = [P, dp, vp, C.c_size_t, C.POINTER(vp)]
     lib.lb_step.argtypes = [vp, C.c_int64]
     lib.lb_moments.argtypes = [vp, dp, dp, dp, dp, dp, dp, C.POINTER(C.c_int64)]
+    lib.lb_moments_noalloc.argtypes = [vp, dp, dp, dp, dp, dp, dp, C.POINTER(C.c_int64)]
     lib.lb_get_f.argtypes = [vp, dp]
     lib.lb_state_bytes.argtypes = [vp]
     lib.lb_state_bytes.restype = C.c_size_t
@@ -115,7 +116,7 @@ def load() -> C.CDLL:
     lib.lb_lines_step.argtypes = [vp, C.c_int64]
     lib.lb_lines_free.argtypes = [vp]
     lib.lb_lines_free.restype = None
-    for name in ("lb_init", "lb_step", "lb_moments", "lb_get_f", "lb_get_state", "lb_set_state",
+    for name in ("lb_init", "lb_step", "lb_moments", "lb_moments_noalloc", "lb_get_f", "lb_get_state", "lb_set_state",
                  "lb_lattice_tables", "lb_path_in_use", "lb_batch_create", "lb_batch_add", "lb_batch_step",
                  "lb_batch_poll", "lb_batch_moments", "lb_batch_remove", "lb_batch_config_count",
                  "lb_batch_config_info", "lb_batch_set_config", "lb_batch_tune", "lb_lines_create",
@@ -182,14 +183,17 @@ def lb_step(ctx: int, nsteps: int) -> None:
     _check(load().lb_step(C.c_void_p(ctx), C.c_int64(nsteps)))
 
 
-def lb_moments(ctx: int, n_comp: int, dim: int, sites: int, fields=True, raise_numeric=True) -> dict:
+def lb_moments(ctx: int, n_comp: int, dim: int, sites: int, fields=True, raise_numeric=True,
+               noalloc=False) -> dict:
+    """lb_moments, or lb_moments_noalloc with noalloc=True."""
     out = {"mass": np.zeros(n_comp), "mom": np.zeros(dim)}
     if fields:
         out.update(rho=np.zeros((n_comp, sites)), U=np.zeros((dim, sites)), mu=np.zeros((n_comp, sites)),
                    P=np.zeros((dim * (dim + 1) // 2, sites)))
     step = C.c_int64()
-    rc = load().lb_moments(C.c_void_p(ctx), _dptr(out.get("rho")), _dptr(out.get("U")), _dptr(out.get("mu")),
-                           _dptr(out.get("P")), _dptr(out["mass"]), _dptr(out["mom"]), C.byref(step))
+    fn = load().lb_moments_noalloc if noalloc else load().lb_moments
+    rc = fn(C.c_void_p(ctx), _dptr(out.get("rho")), _dptr(out.get("U")), _dptr(out.get("mu")),
+            _dptr(out.get("P")), _dptr(out["mass"]), _dptr(out["mom"]), C.byref(step))
     out["step"] = step.value
     out["status"] = rc
     if rc != LB_ENUMERIC or raise_numeric:
@@ -263,8 +267,9 @@ class Simulation:
     def step(self, n: int = 1) -> None:
         lb_step(self.ctx, n)
 
-    def moments(self, fields=True, raise_numeric=True) -> dict:
-        return lb_moments(self.ctx, self.n, self.D, self.sites, fields=fields, raise_numeric=raise_numeric)
+    def moments(self, fields=True, raise_numeric=True, noalloc=False) -> dict:
+        return lb_moments(self.ctx, self.n, self.D, self.sites, fields=fields, raise_numeric=raise_numeric,
+                          noalloc=noalloc)
 
     def get_f(self) -> np.ndarray:
         return lb_get_f(self.ctx, self.n, self.Q, self.sites)
