@@ -34,16 +34,24 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS×components at 2048² ternary, % HBM peak; serving p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ["paper_0704_3444_amd/csrc/k_sweep2d.hip", "paper_0704_3444_amd/csrc/k_fused2d.hip",
-                  "paper_0704_3444_amd/csrc/physics.hpp", "paper_0704_3444_amd/csrc/lattice.hpp",
+# sources of each fused kernel: a traffic summary holds for the sources it was
+# taken with (their hash is in the summary)
+COMMON_SOURCES = ["paper_0704_3444_amd/csrc/physics.hpp", "paper_0704_3444_amd/csrc/lattice.hpp",
                   "paper_0704_3444_amd/csrc/storage.hpp"]
+KERNEL_SOURCES = {
+    ("D2Q9", "sweep"): ["paper_0704_3444_amd/csrc/k_sweep2d.hip"] + COMMON_SOURCES,
+    ("D2Q9", "tile"): ["paper_0704_3444_amd/csrc/k_fused2d.hip"] + COMMON_SOURCES,
+    ("D3Q19", "sweep"): ["paper_0704_3444_amd/csrc/k_sweep3d.hip"] + COMMON_SOURCES,
+}
+KERNEL_NAMES = {("D2Q9", "sweep"): "k_sweep_d2q9", ("D2Q9", "tile"): "k_fused_d2q9",
+                ("D3Q19", "sweep"): "k_sweep_d3q19"}
 # bytes of one stored population: (rest slot, moving slot)
 STORE_BYTES = {"f64": (8, 8), "f32": (4, 4), "f16s": (4, 2)}
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(lattice, kpath) -> str:
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in KERNEL_SOURCES.get((lattice, kpath), COMMON_SOURCES):
         with open(os.path.join(ROOT, rel), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -62,15 +70,15 @@ def workload(name):
     return table[name]()
 
 
-def measured_traffic(name, storage, kpath):
+def measured_traffic(name, storage, kpath, lattice):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when the kernel sources changed since the counters were taken."""
+    None when the kernel's sources changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", f"traffic_{name}_{storage}_{kpath}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    if rec.get("source_sha") != kernel_source_hash():
+    if rec.get("source_sha") != kernel_source_hash(lattice, kpath):
         return None
     return rec.get("bytes_per_launch")
 
@@ -335,21 +343,22 @@ def main():
     kernels_per_step = 3 if path == "split" else 1
     alg_bytes = alg_bytes_per_step(N, S, Q, args.storage)
     achieved = alg_bytes / (ms_per_step / 1e3) / 1e9
-    traffic = measured_traffic(args.workload, args.storage, path)
+    traffic = measured_traffic(args.workload, args.storage, path, cfg["lattice"])
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": {"sweep": "k_sweep_d2q9", "tile": "k_fused_d2q9"}.get(path, "k_density+k_potential+k_collide"),
+                "kernel": KERNEL_NAMES.get((cfg["lattice"], path), "k_density+k_potential+k_collide"),
                 "algorithmic_bytes_per_launch": alg_bytes, "launches_per_step": kernels_per_step,
                 "avg_launch_ms": round(ms_per_step / kernels_per_step, 5)}
 
     f16s = None
-    if not args.no_f16s and args.storage == "f32" and cfg["lattice"] == "D2Q9":
+    if not args.no_f16s and args.storage == "f32" and cfg["lattice"] in ("D2Q9", "D3Q19"):
         h = time_steps(cfg, rho0, "f16s", args.path, args.steps, args.warmup, stream)
         hb = alg_bytes_per_step(N, S, Q, "f16s")
         f16s = {"value": round(h["value"], 1), "ms_per_step": round(h["ms_per_step"], 5), "path": h["path"],
                 "speedup_vs_f32": round(h["value"] / value, 3),
                 "hbm_frac": round(hb / (h["ms_per_step"] / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-                "algorithmic_bytes_per_launch": hb, "traffic": measured_traffic(args.workload, "f16s", h["path"]),
+                "algorithmic_bytes_per_launch": hb,
+                "traffic": measured_traffic(args.workload, "f16s", h["path"], cfg["lattice"]),
                 "mass_drift": h["mass_drift"], "status": h["health"]["status"]}
 
     serving = None

@@ -87,9 +87,12 @@ typedef enum lb_force_form { LB_FORCE_LOG = 0, LB_FORCE_EXPANDED = 1 } lb_force_
  *                  density halo (any nx, every storage, periodic box).
  *   LB_PATH_SPLIT: three kernels per step (density, potential, collide and
  *                  stream); every lattice, periodic box or walls.
- *   LB_PATH_SWEEP: fused one-kernel D2Q9 step that sweeps 64-column strips
- *                  row by row (LB_F32 or LB_F16S, N <= 4, nx a multiple of
- *                  64, periodic box).
+ *   LB_PATH_SWEEP: fused one-kernel step that sweeps the box: on D2Q9
+ *                  64-column strips row by row (LB_F32 or LB_F16S, N <= 4,
+ *                  nx a multiple of 64), on D3Q19 pencils of 64 x 4 sites
+ *                  plane by plane (LB_F32 or LB_F16S, N <= 3, nx a multiple
+ *                  of 64, ny of 4); periodic boxes, population copies below
+ *                  4 GiB.
  * Asking for a path that does not support the run gives LB_ENOTSUP. */
 typedef enum lb_path { LB_PATH_AUTO = 0, LB_PATH_TILE = 1, LB_PATH_SPLIT = 2, LB_PATH_SWEEP = 3 } lb_path;
 

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = ["lb_capi.hip", "lb_batch.hip", "lb_lines.hip", "k_split.hip", "k_fused2d.hip", "k_sweep2d.hip"]
+SOURCES = ["lb_capi.hip", "lb_batch.hip", "lb_lines.hip", "k_split.hip", "k_fused2d.hip", "k_sweep2d.hip", "k_sweep3d.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

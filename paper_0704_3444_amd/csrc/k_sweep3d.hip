@@ -1,0 +1,592 @@
+// Plane-sweep D3Q19 step: one launch per time step, every population read
+// from memory once and written once.
+//
+// A workgroup owns a pencil of 64 x-sites (one 64-site block of the
+// population layout) by kTY rows and a segment of z-planes, which it sweeps
+// upwards.  It has one wave per (row, component) unit of the pencil, 4 N
+// waves.  The collision of plane z needs the potentials h of planes z - 1 ..
+// z + 1 and the densities of planes z - 1 .. z + 1; h of plane z + 1 needs
+// the Laplacian of the densities, so densities run two planes ahead of the
+// collision.  One iteration, for the collision of plane zc:
+//   1. every wave pulls the 19 populations of its unit in plane zc + 2 into
+//      registers (decoded), writes the unit's density and first moments to
+//      LDS rings, and keeps the populations: each wave holds three planes of
+//      its unit (zc, zc + 1, zc + 2), so each population is loaded once;
+//      it also sums the densities of one unit of the two halo rows above and
+//      below the pencil and of 8 sites of the halo columns (two on either
+//      side), which the neighbouring pencils load as their own (mostly L2
+//      hits);
+//   2. (barrier) chemical potentials and h of plane zc + 1 on the rows and
+//      columns the force stencil reaches, into an LDS ring;
+//   3. (barrier) force, equilibrium, forcing term and collision of plane zc
+//      from the registers; non-temporal stores in place (the next step's pull
+//      streams them).
+// Each site's arithmetic is the split path's (the same physics.hpp functions
+// with the same operands in the same order), so the two agree bit for bit.
+// Workgroups are banded per XCD so that neighbouring pencils share an L2.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <type_traits>
+
+#include "lbm_internal.hpp"
+#include "physics.hpp"
+#include "storage.hpp"
+
+namespace lbm {
+namespace sweep3 {
+
+constexpr int kXcds = 8;
+constexpr int kW = 64;          // pencil width = block width = wave size
+constexpr int kTY = 4;          // rows per pencil
+constexpr int kRP = 5;          // density planes in LDS (zc - 2 .. zc + 2 live)
+constexpr int kHP = 3;          // h planes in LDS (zc - 1 .. zc + 1 live)
+constexpr int kJP = 4;          // first-moment planes in LDS (zc - 1 .. zc + 2 live)
+constexpr int kRR = kTY + 4;    // density rows: y0 - 2 .. y0 + kTY + 1
+constexpr int kRC = kW + 4;     // density columns: x0 - 2 .. x0 + 65
+constexpr int kHR = kTY + 2;    // h rows: y0 - 1 .. y0 + kTY
+constexpr int kHC = kW + 2;     // h columns: x0 - 1 .. x0 + 64
+
+// Workgroup barrier that publishes this wave's LDS writes without waiting
+// for its global loads and stores in flight (no wave reads global memory
+// that another wave of the step writes).
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+__device__ __forceinline__ int wrap_mod(int v, int n) {
+  const int r = v % n;
+  return r < 0 ? r + n : r;
+}
+
+// Ring slot of virtual plane z (z >= za - 2).
+template <int R>
+__device__ __forceinline__ int slot(int z, int za) {
+  return (z - za + 2 * R) % R;
+}
+
+// Pieces of the halo columns, per density row of a wave (2 rows): for every
+// direction i the 16 bytes at the end of run i of the block left of the
+// pencil and at the start of run i of the block right of it (the columns
+// x0 - 4 .. x0 - 1 and x0 + 64 .. x0 + 67 of a 4-byte run), and, for the 5
+// directions with v_x = -1 and the 5 with v_x = +1, the first and the last 16
+// bytes of run i of the pencil's own block (columns x0 and x0 + 63, pulled
+// into x0 - 1 and x0 + 64).  Piece index within a row: left 0 .. 18, right
+// 19 .. 37, own start 38 .. 42, own end 43 .. 47.
+constexpr int kPiecesPerRow = 48;
+constexpr int kPieces = 2 * kPiecesPerRow;
+constexpr int kXMinus[5] = {2, 8, 10, 12, 14};  // D3Q19 directions with v_x = -1
+constexpr int kXPlus[5] = {1, 7, 9, 11, 13};    // and with v_x = +1
+
+// Per-wave staging of one plane, filled by direct global-to-LDS loads one
+// plane ahead: the halo-row unit (19 pulled values per lane; raw 32-bit
+// words, a shifted FP16 moving value in the half the lane's parity selects)
+// and the halo-column pieces.
+struct Stage {
+  uint32_t unit[19][kW];
+  uint32_t piece[kPieces][4];
+};
+
+template <class S, int NC>
+struct Smem {
+  float rho[kRP][NC][kRR][kRC];
+  float h[kHP][NC][kHR][kHC];
+  float j[kJP][3][NC][kTY][kW];
+  Stage st[kTY * NC];
+};
+
+// Byte offset of population i of component c at site (x, y, z), 32-bit
+// (the fused paths are taken only for copies below 4 GiB).
+template <class S, int NC>
+__device__ __forceinline__ uint32_t pop_off(const Params<float>& p, int c, int i, int x, int y, int z) {
+  using B = BlockLayout<S, 19>;
+  const uint32_t row = uint32_t(y) + uint32_t(p.ny) * uint32_t(z);
+  return (row * uint32_t(p.nbx) + uint32_t(x >> 6)) * uint32_t(NC * B::kComp) + B::run(c, i) + B::in_run(i, x);
+}
+
+// Per-lane part of a population's byte offset: the block of column x
+// (taken from the lane's source column) and the position in the run, for
+// the rest run (4-byte slots) and for moving runs.  The row part is the
+// same for the whole wave.
+struct LanePart {
+  uint32_t rest;     // column x, rest run
+  uint32_t move[3];  // moving runs, source column x - d for d = -1, 0, +1 (index d + 1)
+};
+
+template <class S, int NC>
+__device__ __forceinline__ LanePart lane_part(const Params<float>& p, int x) {
+  using B = BlockLayout<S, 19>;
+  constexpr uint32_t comp = NC * B::kComp;
+  LanePart lp;
+  lp.rest = uint32_t(x >> 6) * comp + B::in_run(0, x);
+#pragma unroll
+  for (int d = -1; d <= 1; ++d) {
+    const int sx = wrap_add(x, -d, p.nx);
+    lp.move[d + 1] = uint32_t(sx >> 6) * comp + B::in_run(1, sx);
+  }
+  return lp;
+}
+
+// Raw buffer resource over a population copy of `bytes` bytes (gfx9
+// family: 4th descriptor word 0x00020000, stride 0, byte offsets).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+// Shift reference of component c alone (slot 0), picked by selects from the
+// kernel arguments so that it stays in registers.
+template <class S, int NC>
+__device__ __forceinline__ ShiftRef ref_of(const Params<float>& p, int c) {
+  ShiftRef r = {};
+  if constexpr (S::kShift) {
+    r.rbar[0] = p.sh.rbar[0];
+    r.scale[0] = p.sh.scale[0];
+    r.inv_scale[0] = p.sh.inv_scale[0];
+    r.csum[0] = p.sh.csum[0];
+#pragma unroll
+    for (int q = 1; q < NC; ++q) {
+      r.rbar[0] = c == q ? p.sh.rbar[q] : r.rbar[0];
+      r.scale[0] = c == q ? p.sh.scale[q] : r.scale[0];
+      r.inv_scale[0] = c == q ? p.sh.inv_scale[q] : r.inv_scale[0];
+      r.csum[0] = c == q ? p.sh.csum[q] : r.csum[0];
+    }
+  }
+  return r;
+}
+
+// Raw bits of one slot as a float register: FP32 values as they are, the
+// FP16 moving values zero-extended (converted only when consumed, so that
+// issuing the loads does not wait for them).
+template <class S>
+__device__ __forceinline__ float load_raw(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff, int i) {
+  if (i == 0 || sizeof(typename S::Move) == 4)
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, 0));
+  return __builtin_bit_cast(float, uint32_t(__builtin_amdgcn_raw_buffer_load_b16(rs, voff, soff, 0)));
+}
+
+// Slot value in the working precision from load_raw's register.
+template <class S>
+__device__ __forceinline__ float raw_value(float r, int i) {
+  if (i == 0 || sizeof(typename S::Move) == 4) return r;
+  return float(__builtin_bit_cast(_Float16, uint16_t(__builtin_bit_cast(uint32_t, r))));
+}
+
+// Slot value from a staged 32-bit word: for a shifted FP16 moving slot the
+// half of the word at byte offset 2 (odd) or 0 (even) of the slot's column.
+template <class S>
+__device__ __forceinline__ float staged_value(uint32_t w, int i, bool odd) {
+  if (i == 0 || sizeof(typename S::Move) == 4) return __builtin_bit_cast(float, w);
+  return float(__builtin_bit_cast(_Float16, uint16_t(odd ? (w >> 16) : (w & 0xffffu))));
+}
+
+template <int V>
+using I = std::integral_constant<int, V>;
+
+// Slot value of run i at column x0 + src (src in -3 .. 66, but not 1 .. 62)
+// from the halo-column pieces of one density row (Stage::piece).
+template <class S>
+__device__ __forceinline__ float piece_value(const char* row_pieces, int i, int src) {
+  using B = BlockLayout<S, 19>;
+  const int esz = i == 0 ? int(B::kRest) : int(B::kMove);
+  const int per = 16 / esz;  // slots per piece
+  int q, e;
+  if (src < 0) {
+    q = i, e = src + per;
+  } else if (src >= kW) {
+    q = 19 + i, e = src - kW;
+  } else if (src == 0) {  // pulled into x0 - 1 by a direction with v_x = -1
+    int k = 0;
+#pragma unroll
+    for (int m = 0; m < 5; ++m) k = kXMinus[m] == i ? m : k;
+    q = 38 + k, e = 0;
+  } else {  // src == 63: pulled into x0 + 64 by a direction with v_x = +1
+    int k = 0;
+#pragma unroll
+    for (int m = 0; m < 5; ++m) k = kXPlus[m] == i ? m : k;
+    q = 43 + k, e = per - 1;
+  }
+  const char* a = row_pieces + q * 16 + e * esz;
+  if (i == 0 || sizeof(typename S::Move) == 4) return *reinterpret_cast<const float*>(a);
+  return float(*reinterpret_cast<const _Float16*>(a));
+}
+
+// 16 bytes per lane from byte offset voff of the buffer into LDS at dst +
+// 16 lane (a direct load: no registers hold the data in flight).  Kept out
+// of the kernel body: there the 16-byte form of the builtin made the host
+// pass drop the kernel's instantiation without a diagnostic.
+__device__ __forceinline__ void load_lds16(__amdgpu_buffer_rsrc_t rs, __attribute__((address_space(3))) char* dst,
+                                           uint32_t voff) {
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, dst, 16, voff, 0u, 0, 0);
+}
+
+// s_waitcnt vmcnt(N), the other counters untouched, as a compiler memory
+// barrier.
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+
+template <class S, int NC>
+__global__ void __launch_bounds__(64 * kTY * NC) k_sweep_d3q19(const void* fin_v, void* fout_v, Params<float> p,
+                                                               int strips, int ytiles, int seg, int ntiles,
+                                                               int tiles_per_xcd) {
+  using L = Lattice<3>;
+  using T = float;
+  using B = BlockLayout<S, 19>;
+  __shared__ Smem<S, NC> sm;
+  const uint32_t copy_bytes = uint32_t(p.ny) * uint32_t(p.nz) * uint32_t(p.nbx) * uint32_t(NC * B::kComp);
+  const __amdgpu_buffer_rsrc_t fin = buffer_of(fin_v, copy_bytes);
+  const __amdgpu_buffer_rsrc_t fout = buffer_of(fout_v, copy_bytes);
+
+  const int b = blockIdx.x;
+  const int t = (b % kXcds) * tiles_per_xcd + b / kXcds;
+  if (t >= ntiles) return;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int r = w / NC;  // own row 0 .. kTY - 1
+  const int c = w % NC;  // component of all this wave's units
+  // tile order: strip fastest, then y-tile, then z-segment
+  const int x0 = (t % strips) * kW;
+  const int y0 = ((t / strips) % ytiles) * kTY;
+  const int za = (t / (strips * ytiles)) * seg;
+  const int zb = min(za + seg, p.nz);
+  const int nplanes = zb - za;
+
+  // coordinates of this wave's own unit, halo-row unit and halo-column sites
+  const int x = x0 + lane;
+  const int y_own = y0 + r;
+  const int hrow = r < 2 ? r : kTY + r;  // density row of the halo unit: 0, 1, kTY + 2, kTY + 3
+  const int y_halo = wrap_mod(y0 - 2 + hrow, p.ny);
+  // halo columns: lanes 0 .. 3 take columns x0 - 2, x0 - 1, x0 + 64, x0 + 65
+  // of the density rows 2 r and 2 r + 1
+  const int xcol_lds = lane < 2 ? lane : kW + lane;  // 0, 1, 66, 67 for lanes 0 .. 3
+  const LanePart lp_own = lane_part<S, NC>(p, x);
+  const ShiftRef sh = ref_of<S, NC>(p, c);
+  const uint32_t stride = uint32_t(p.nbx) * uint32_t(NC * B::kComp);  // bytes per row of blocks
+  // the piece each lane loads in the two 16-byte loads of the halo columns:
+  // density row 2 r + prow[j], source row offsets (pdy, pdz), and the part of
+  // its byte offset that does not depend on the row
+  int prow[2], pdy[2], pdz[2];
+  uint32_t pcol[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int q = j * kW + lane;
+    const int qq = q < kPieces ? q : 0;
+    const int idx = qq % kPiecesPerRow;
+    int i, bx;
+    bool at_end;
+    if (idx < 19) {
+      i = idx, bx = wrap_mod(x0 - 1, p.nx) >> 6, at_end = true;
+    } else if (idx < 38) {
+      i = idx - 19, bx = wrap_mod(x0 + kW, p.nx) >> 6, at_end = false;
+    } else if (idx < 43) {
+      i = kXMinus[idx - 38], bx = x0 >> 6, at_end = false;
+    } else {
+      i = kXPlus[idx - 43], bx = x0 >> 6, at_end = true;
+    }
+    const uint32_t esz = i == 0 ? B::kRest : B::kMove;
+    prow[j] = qq / kPiecesPerRow;
+    pdy[j] = L::cy(i);
+    pdz[j] = L::cz(i);
+    pcol[j] = uint32_t(bx) * uint32_t(NC * B::kComp) + B::run(c, i) + (at_end ? kW * esz - 16u : 0u);
+  }
+
+  // The staging slot's LDS address is passed through an empty asm
+  // statement: the compiler's own tracking of direct loads into LDS would
+  // otherwise add a vmcnt(0) before reads of the slot, which would also wait
+  // for the stores in flight; the explicit waits below order them instead.
+  __attribute__((address_space(3))) char* stg = (__attribute__((address_space(3))) char*)(&sm.st[w]);
+  asm volatile("" : "+s"(stg));
+
+  // byte offset of source row y - dy of plane z - dz
+  auto rowb = [&](int y, int z, int dy, int dz) __attribute__((always_inline)) {
+    return (uint32_t(wrap_add(y, -dy, p.ny)) + uint32_t(p.ny) * uint32_t(wrap_add(z, -dz, p.nz))) * stride;
+  };
+  // column part of a staged load's offset, aligned down to 4 bytes
+  auto col_off = [&](const LanePart& lp, int i) __attribute__((always_inline)) -> uint32_t {
+    return (i == 0 ? lp.rest : lp.move[L::cx(i) + 1]) & ~3u;
+  };
+
+  // The own unit's populations: X holds the raw slots of the plane in
+  // flight; D0, D1, D2 the decoded populations of planes zc, zc + 1, zc + 2
+  // (L0, L1, L2 their ledgers, shifted codec).  Each iteration decodes X
+  // into D2, loads the next plane into X and moves D1 -> D0, D2 -> D1, so
+  // that every set keeps one place in registers.
+  float X[19], D0[19], D1[19], D2[19], L0 = 0.f, L1 = 0.f, L2 = 0.f;
+
+  // Issue the loads of virtual plane z: the halo-row unit and the
+  // halo-column pieces into this wave's staging, then the own unit into
+  // register set Pn.  Exactly 19 vector memory loads follow the staging
+  // loads (the own unit's), so a wait for at most 19 operations in flight
+  // covers the staging whatever follows.
+  auto issue = [&](int z, float (&Pn)[19]) __attribute__((always_inline)) {
+    const int zw = wrap_mod(z, p.nz);
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // this wave's reads of the staging are done
+#pragma unroll
+    for (int i = 0; i < 19; ++i)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(fin, stg + i * (kW * 4), 4, col_off(lp_own, i),
+                                               rowb(y_halo, zw, L::cy(i), L::cz(i)) + B::run(c, i), 0, 0);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      if (j * kW + lane < kPieces) {
+        const int yr = wrap_mod(y0 - 2 + 2 * r + prow[j], p.ny);
+        load_lds16(fin, stg + (19 * kW * 4 + j * kW * 16), rowb(yr, zw, pdy[j], pdz[j]) + pcol[j]);
+      }
+    }
+    asm volatile("" ::: "memory");  // the own unit's loads after the staging loads
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+      const uint32_t so = rowb(y_own, zw, L::cy(i), L::cz(i)) + B::run(c, i);
+      const uint32_t vo = i == 0 ? lp_own.rest : lp_own.move[L::cx(i) + 1];
+      Pn[i] = load_raw<S>(fin, vo, so, i);
+    }
+  };
+
+  // Step 1 for virtual plane z, loads issued by issue(z, Xr): densities of
+  // the own unit (decoded from Xr into Dd, with its ledger Ld, and when keep
+  // its first moments), of the halo-row unit and of the halo-column sites.
+  auto consume = [&](int z, const float (&Xr)[19], float (&Dd)[19], float& Ld, bool keep)
+                     __attribute__((always_inline)) {
+    const int rs = slot<kRP>(z, za);
+    {
+      float led = 0.f;
+#pragma unroll
+      for (int i = 0; i < 19; ++i) {
+        const float v = raw_value<S>(Xr[i], i);
+        led = i == 0 ? v : led + v;
+        Dd[i] = decode<S, 3>(sh, 0, i, v);
+      }
+      sm.rho[rs][c][r + 2][lane + 2] = site_density<S, 19>(sh, 0, Dd, led);
+      Ld = led;
+      if (keep) {
+        float ax = 0.f, ay = 0.f, az = 0.f;
+#pragma unroll
+        for (int i = 1; i < 19; ++i) {
+          if (L::cx(i)) ax += T(L::cx(i)) * Dd[i];
+          if (L::cy(i)) ay += T(L::cy(i)) * Dd[i];
+          if (L::cz(i)) az += T(L::cz(i)) * Dd[i];
+        }
+        const int js = slot<kJP>(z, za);
+        sm.j[js][0][c][r][lane] = ax;
+        sm.j[js][1][c][r][lane] = ay;
+        sm.j[js][2][c][r][lane] = az;
+      }
+    }
+    wait_vm<19>();  // the staging loads have landed
+    const uint32_t* su = reinterpret_cast<const uint32_t*>(&sm.st[w].unit[0][0]);
+    {
+      float f[19], led = 0.f;
+#pragma unroll
+      for (int i = 0; i < 19; ++i) {
+        const bool odd = ((lane - L::cx(i)) & 1) != 0;
+        const float v = staged_value<S>(su[i * kW + lane], i, odd);
+        led = i == 0 ? v : led + v;
+        f[i] = decode<S, 3>(sh, 0, i, v);
+      }
+      sm.rho[rs][c][hrow][lane + 2] = site_density<S, 19>(sh, 0, f, led);
+    }
+    if (lane < 4) {
+      const char* pieces = reinterpret_cast<const char*>(&sm.st[w].piece[0][0]);
+      const int xs = lane < 2 ? lane - 2 : kW + lane - 2;  // column - x0: -2, -1, 64, 65
+#pragma unroll
+      for (int pass = 0; pass < 2; ++pass) {
+        float f[19], led = 0.f;
+#pragma unroll
+        for (int i = 0; i < 19; ++i) {
+          const float v = piece_value<S>(pieces + pass * kPiecesPerRow * 16, i, xs - L::cx(i));
+          led = i == 0 ? v : led + v;
+          f[i] = decode<S, 3>(sh, 0, i, v);
+        }
+        sm.rho[rs][c][2 * r + pass][xcol_lds] = site_density<S, 19>(sh, 0, f, led);
+      }
+    }
+  };
+
+  // Step 2 for virtual plane z: potentials h on the kHR x kHC sites around
+  // the pencil, all components at once.
+  auto potentials = [&](int z) __attribute__((always_inline)) {
+    const int s0 = slot<kRP>(z - 1, za), s1 = slot<kRP>(z, za), s2 = slot<kRP>(z + 1, za);
+    const int hs = slot<kHP>(z, za);
+    for (int q = threadIdx.x; q < kHR * kHC; q += 64 * kTY * NC) {
+      const int hr = q / kHC, hc = q - hr * kHC;
+      const int pr = hr + 1, pc = hc + 1;  // density row and column of the site
+      T rr[NC], lap[NC], mu[NC], hh[NC];
+#pragma unroll
+      for (int k = 0; k < NC; ++k) {
+        rr[k] = sm.rho[s1][k][pr][pc];
+        lap[k] = lattice_laplacian<3, T>(
+            [&](int i) {
+              const int sz = L::cz(i) > 0 ? s2 : (L::cz(i) < 0 ? s0 : s1);
+              return sm.rho[sz][k][pr + L::cy(i)][pc + L::cx(i)];
+            },
+            rr[k]);
+        // one component's 18 LDS reads at a time: issued together for all
+        // components they would hold 18 N registers next to the planes of
+        // populations
+        asm volatile("" ::: "memory");
+      }
+      site_potential<T, NC>(p, rr, lap, mu, hh);
+#pragma unroll
+      for (int k = 0; k < NC; ++k) sm.h[hs][k][hr][hc] = hh[k];
+    }
+  };
+
+  // Step 3 for virtual plane z from register set f: collision of this
+  // wave's unit and its 19 stores.
+  auto collide_store = [&](int z, float (&f)[19], float led) __attribute__((always_inline)) {
+    const int zw = wrap_mod(z, p.nz);
+    const int s0 = slot<kRP>(z - 1, za), s1 = slot<kRP>(z, za), s2 = slot<kRP>(z + 1, za);
+    const int h0 = slot<kHP>(z - 1, za), h1 = slot<kHP>(z, za), h2 = slot<kHP>(z + 1, za);
+    const int js = slot<kJP>(z, za);
+    T rt = T(0), ux = T(0), uy = T(0), uz = T(0);
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      ux += sm.j[js][0][k][r][lane];
+      uy += sm.j[js][1][k][r][lane];
+      uz += sm.j[js][2][k][r][lane];
+      rt += sm.rho[s1][k][r + 2][lane + 2];
+    }
+    const T inv_rt = rcp_(rt);
+    ux *= inv_rt;
+    uy *= inv_rt;
+    uz *= inv_rt;
+    const T rs = sm.rho[s1][c][r + 2][lane + 2];
+    // the force of lattice_force (physics.hpp), term by term, with the
+    // potential's and the density's neighbour reads in two groups
+    T hx, hy, hz;
+    lattice_wsum<3, T>(
+        [&](int i) {
+          const int hp = L::cz(i) > 0 ? h2 : (L::cz(i) < 0 ? h0 : h1);
+          return sm.h[hp][c][r + 1 + L::cy(i)][lane + 1 + L::cx(i)];
+        },
+        hx, hy, hz);
+    asm volatile("" ::: "memory");
+    T qx = T(0), qy = T(0), qz = T(0);
+    if (!p.log_form)
+      lattice_wsum<3, T>(
+          [&](int i) {
+            const int sz = L::cz(i) > 0 ? s2 : (L::cz(i) < 0 ? s0 : s1);
+            return sm.rho[sz][c][r + 2 + L::cy(i)][lane + 2 + L::cx(i)];
+          },
+          qx, qy, qz);
+    const T Ax = -p.cforce * fma_(rs, T(3) * hx, -qx);
+    const T Ay = -p.cforce * fma_(rs, T(3) * hy, -qy);
+    const T Az = -p.cforce * fma_(rs, T(3) * hz, -qz);
+    const T inv_rs = rcp_(rs);
+    const T jx = sm.j[js][0][c][r][lane], jy = sm.j[js][1][c][r][lane], jz = sm.j[js][2][c][r][lane];
+    collide<3, T>(f, rs, ux, uy, uz, Ax, Ay, Az, jx * inv_rs, jy * inv_rs, jz * inv_rs, p.inv_tau);
+    // non-temporal buffer stores (policy bit nt): the row and run part of
+    // each slot's offset in an SGPR, the lane's column part in a VGPR
+    const uint32_t row = rowb(y_own, zw, 0, 0);
+    if constexpr (S::kShift) {
+      T rest = led;
+#pragma unroll
+      for (int i = 1; i < 19; ++i) {
+        const _Float16 d = encode_move<3>(sh, 0, i, f[i]);
+        rest -= float(d);
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, d), fout, lp_own.move[1],
+                                              row + B::run(c, i), 2);
+      }
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, rest), fout, lp_own.rest, row + B::run(c, 0),
+                                            2);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 19; ++i)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, f[i]), fout, lp_own.rest,
+                                              row + B::run(c, i), 2);
+    }
+  };
+
+  // ---- prologue: densities of planes za - 2 .. za + 2 (the last three kept
+  // in D0, D1 and D2), potentials of planes za - 1 and za
+  issue(za - 2, X);
+  consume(za - 2, X, D2, L2, false);
+  issue(za - 1, X);
+  consume(za - 1, X, D2, L2, false);
+  issue(za, X);
+  consume(za, X, D0, L0, true);
+  issue(za + 1, X);
+  consume(za + 1, X, D1, L1, true);
+  issue(za + 2, X);
+  consume(za + 2, X, D2, L2, true);
+  lds_barrier();
+  potentials(za - 1);
+  potentials(za);
+
+  // ---- iterations: potentials of plane zc + 1; plane zc + 3 is loaded into
+  // X before the stores of the collision of plane zc (D0), and consumed into
+  // D2 after them, so that the waits for X leave exactly those stores in
+  // flight (X is never in flight at the top of the loop)
+  for (int k = 0; k < nplanes; ++k) {
+    const int zc = za + k;
+    lds_barrier();
+    potentials(zc + 1);
+    lds_barrier();
+    issue(zc + 3, X);
+    collide_store(zc, D0, L0);
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+      D0[i] = D1[i];
+      D1[i] = D2[i];
+    }
+    L0 = L1;
+    L1 = L2;
+    consume(zc + 3, X, D2, L2, true);
+  }
+}
+
+}  // namespace sweep3
+
+// Resident workgroups of the D3Q19 sweep on the current device.
+template <class S, int NC>
+static int sweep3_slots() {
+  static const int slots = [] {
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sweep3::k_sweep_d3q19<S, NC>, 64 * sweep3::kTY * NC,
+                                                     0) != hipSuccess ||
+        per_cu < 1)
+      per_cu = 1;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+      cus = 256;
+    return per_cu * cus;
+  }();
+  return slots;
+}
+
+// Planes per z-segment: about one workgroup per resident slot, so that the
+// grid runs in one wave of workgroups; each segment re-reads 4 planes of
+// densities at its start.
+template <class S, int NC>
+static void launch_sweep3(const Ctx& c, const void* fin, void* fout) {
+  const Params<float>& p = c.params<float>();
+  const int strips = p.nx / sweep3::kW;
+  const int ytiles = p.ny / sweep3::kTY;
+  const int pencils = strips * ytiles;
+  const int slots = sweep3_slots<S, NC>();
+  const int segs = std::max(1, std::min(p.nz, (slots + pencils - 1) / pencils));
+  const int seg = (p.nz + segs - 1) / segs;
+  const int ntiles = pencils * ((p.nz + seg - 1) / seg);
+  const int per_xcd = (ntiles + sweep3::kXcds - 1) / sweep3::kXcds;
+  sweep3::k_sweep_d3q19<S, NC><<<per_xcd * sweep3::kXcds, 64 * sweep3::kTY * NC, 0, c.stream>>>(
+      fin, fout, p, strips, ytiles, seg, ntiles, per_xcd);
+}
+
+template <class S>
+static FusedStepFn sweep3_for_n(int n_comp) {
+  switch (n_comp) {
+    case 1: return launch_sweep3<S, 1>;
+    case 2: return launch_sweep3<S, 2>;
+    case 3: return launch_sweep3<S, 3>;
+    default: return nullptr;  // N = 4 would need 16 waves of at most 128 VGPRs: it spills
+  }
+}
+
+// D3Q19 plane sweep: FP32 or shifted FP16, N <= 3; the caller checks nx % 64
+// == 0, ny % 4 == 0, no walls and a copy below 4 GiB.
+FusedStepFn sweep3d_step_for(int storage, int n_comp) {
+  if (storage == StoreF32::kId) return sweep3_for_n<StoreF32>(n_comp);
+  if (storage == StoreF16S::kId) return sweep3_for_n<StoreF16S>(n_comp);
+  return nullptr;
+}
+
+}  // namespace lbm

@@ -382,6 +382,8 @@ int init_impl(const lb_params* p, const double* rho0, void* workspace, size_t wo
   lbm::FusedStepFn tile = small ? lbm::fused_step_for(p->lattice, p->storage, p->n_comp) : nullptr;
   lbm::FusedStepFn sweep =
       small && p->lattice == LB_D2Q9 && p->nx % 64 == 0 ? lbm::sweep_step_for(p->storage, p->n_comp) : nullptr;
+  if (small && p->lattice == LB_D3Q19 && p->nx % 64 == 0 && p->ny % 4 == 0)
+    sweep = lbm::sweep3d_step_for(p->storage, p->n_comp);
   switch (p->path) {
     case LB_PATH_AUTO:
       c.path = sweep ? LB_PATH_SWEEP : (tile ? LB_PATH_TILE : LB_PATH_SPLIT);
@@ -397,7 +399,7 @@ int init_impl(const lb_params* p, const double* rho0, void* workspace, size_t wo
       c.path = LB_PATH_SWEEP;
       if (!sweep) {
         lb_free(h);
-        return fail(LB_ENOTSUP, "the sweep kernel needs D2Q9, FP32 or shifted FP16, N <= 4, nx a multiple of 64 and no walls");
+        return fail(LB_ENOTSUP, "the sweep kernels need D2Q9 or D3Q19 (ny a multiple of 4), FP32 or shifted FP16, N <= 4, nx a multiple of 64 and no walls");
       }
       break;
     default:
@@ -425,7 +427,7 @@ int init_impl(const lb_params* p, const double* rho0, void* workspace, size_t wo
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
-  if (e == hipSuccess && tune && c.path == LB_PATH_SWEEP) {
+  if (e == hipSuccess && tune && c.path == LB_PATH_SWEEP && p->lattice == LB_D2Q9) {
     // choose the sweep's segment length on this very state, then return to
     // rest equilibrium with both copies cleared as above
     c.cur = 0;

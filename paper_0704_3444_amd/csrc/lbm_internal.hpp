@@ -14,6 +14,7 @@ struct Ctx;
 using FusedStepFn = void (*)(const Ctx&, const void* fin, void* fout);
 FusedStepFn fused_step_for(int lattice, int storage, int n_comp);  // tile kernel, D2Q9
 FusedStepFn sweep_step_for(int storage, int n_comp);               // strip sweep, D2Q9, nx % 64 == 0
+FusedStepFn sweep3d_step_for(int storage, int n_comp);             // plane sweep, D3Q19, nx % 64 == 0, ny % 4 == 0
 // Segment lengths of the sweep to time for this context (up to 8, the
 // default first) into cand; 0 when the grid is too small to tune.
 int sweep_candidates(const Ctx& c, int* cand);

@@ -12,12 +12,19 @@ TOL = {"f64": 1e-12, "f32": 1e-5}
 def paths_for(cfg, storage):
     """Kernel paths that support a run: split always; the tile kernel for
     D2Q9 in every storage; the strip sweep for D2Q9 in FP32 or shifted FP16
-    with nx a multiple of 64 and N <= 4."""
+    with nx a multiple of 64 and N <= 4; the plane sweep for D3Q19 in FP32
+    or shifted FP16 with nx a multiple of 64, ny a multiple of 4 and N <= 3
+    (periodic boxes only)."""
     paths = ["split"]
+    if cfg.get("walls", 0):
+        return paths
     if cfg["lattice"] == "D2Q9":
         paths.append("tile")
         if storage in ("f32", "f16s") and cfg["shape"][0] % 64 == 0 and cfg["n_comp"] <= 4:
             paths.append("sweep")
+    if cfg["lattice"] == "D3Q19" and storage in ("f32", "f16s") and cfg["shape"][0] % 64 == 0 \
+            and cfg["shape"][1] % 4 == 0 and cfg["n_comp"] <= 3:
+        paths.append("sweep")
     return paths
 
 

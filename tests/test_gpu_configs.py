@@ -174,19 +174,32 @@ def test_slab_coexistence_matches_oracle():
 
 
 def test_ternary_d3q19_256_sampled_sites_and_mass():
-    """Ternary D3Q19 at 256^3 (split path, FP32): sampled sites after 2 steps
-    against the oracle at the FP32 bar, and mass over 50 steps."""
+    """Ternary D3Q19 at 256^3, FP32, on the path lb_step takes (the plane
+    sweep): sampled sites after 2 steps against the oracle at the FP32 bar,
+    every site bit for bit equal to the split path after 6 steps (the
+    sweep's z-segments and pencil edges at the real launch configuration),
+    and mass over 50 steps."""
     from paper_0704_3444_amd import Simulation
 
     cfg, rho0 = LI.ternary_d3q19(256)
-    n = 256
     sim = Simulation(cfg, rho0, storage="f32", path="auto")
+    assert sim.path == "sweep"
     sim.step(2)
     out = sim.moments(fields=True)
     sites = [(0, 0, 0), (255, 255, 255), (63, 64, 65), (128, 0, 255), (1, 254, 127), (200, 31, 7)]
     print(f"[configs] D3Q19 256^3 path={sim.path}: {len(sites)} sampled sites after 2 steps", flush=True)
     check_sampled(cfg, rho0, out, sites, 2, TOL["f32"])
-    sim.step(48)
+    del out
+    sim.step(4)
+    ref = Simulation(cfg, rho0, storage="f32", path="split")
+    ref.step(6)
+    a = sim.moments(fields=True)
+    b = ref.moments(fields=True)
+    ref.close()
+    print("[configs] D3Q19 256^3 sweep vs split after 6 steps", flush=True)
+    assert np.array_equal(a["rho"], b["rho"]) and np.array_equal(a["U"], b["U"])
+    del a, b
+    sim.step(44)
     m = sim.moments(fields=False)["mass"]
     sim.close()
     drift = float(np.max(np.abs(m / rho0.sum(axis=1) - 1)))

@@ -42,6 +42,15 @@ def _cases():
     cases.append(("d3q19_ternary_12x10x9", p, r, 100))
     p, r = LI.five_component(40, chi_base=4.0)
     cases.append(("five_40", p, r, 100))
+    # D3Q19 boxes the plane sweep takes (nx a multiple of 64, ny of 4)
+    p, _ = LI.ternary_d3q19(12, chi=3.0)
+    p["shape"] = (64, 12, 10)
+    r = LI.noisy_uniform(p, [1 / 3] * 3, 0.01, 1013)
+    cases.append(("d3q19_ternary_64x12x10", p, r, 200))
+    p, _ = LI.binary_spinodal(8)
+    p = dict(LI.params("D3Q19", 2, (128, 8, 6), kappa=0.01, chi=p["chi"]))
+    r = LI.noisy_uniform(p, [0.5, 0.5], 0.01, 1014)
+    cases.append(("d3q19_binary_128x8x6", p, r, 200))
     return cases
 
 
@@ -57,6 +66,8 @@ F16S_TOL = {
     "d1q3_polymer_130": {"rho": 1.5e-3, "f": 3e-4, "U_cs": 4e-4, "mu": 1.2e-5, "P": 1e-12, "mom": 1e-3},
     "d3q19_ternary_12x10x9": _NEAR_UNIFORM,
     "five_40": _NEAR_UNIFORM,
+    "d3q19_ternary_64x12x10": _NEAR_UNIFORM,
+    "d3q19_binary_128x8x6": _NEAR_UNIFORM,
 }
 
 
@@ -93,6 +104,28 @@ def test_fused_paths_equal_split(storage):
         d = np.abs(a["f"] - b["f"]).max() / np.abs(a["f"]).max()
         print(f"[fused-vs-split] {storage} {path} max rel diff {d:.3e}", flush=True)
         assert d == 0.0, (path, d)
+
+
+D3Q19_SWEEP_BOXES = [((64, 4, 1), 3), ((64, 4, 3), 3), ((64, 8, 2), 2), ((128, 8, 5), 3), ((64, 12, 7), 1),
+                     ((192, 4, 9), 2), ((64, 16, 33), 3)]
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16s"])
+@pytest.mark.parametrize("shape,n", D3Q19_SWEEP_BOXES, ids=[f"{s[0]}x{s[1]}x{s[2]}-N{n}" for s, n in D3Q19_SWEEP_BOXES])
+def test_d3q19_sweep_equals_split(shape, n, storage):
+    """The D3Q19 plane sweep against the split path, bit for bit, on boxes
+    where the halo rows, halo columns and the ring of z-planes wrap onto the
+    pencil itself (ny = 4, nx = 64, nz = 1 .. 3), a single z-plane, several
+    pencils and segments, N = 1 .. 3."""
+    chi = np.full((n, n), 1.5 if n > 1 else 0.0)
+    np.fill_diagonal(chi, 0.0)
+    p = LI.params("D3Q19", n, shape, kappa=0.02, chi=chi, m=[1.0 + (k == 1) for k in range(n)])
+    r = LI.noisy_uniform(p, [1.0 / n] * n, 0.02 / n, 17 + n)
+    a = run_gpu(p, r, 13, storage=storage, path="split")
+    b = run_gpu(p, r, 13, storage=storage, path="sweep")
+    assert b["path"] == "sweep"
+    print(f"[d3q19-sweep] {shape} N={n} {storage}: max |df| {np.abs(a['f'] - b['f']).max():.3e}", flush=True)
+    assert np.array_equal(a["f"], b["f"])
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])
