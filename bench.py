@@ -18,9 +18,11 @@ Three more objects on the same line (skipped with --no-f16s / --no-serving /
 `serving` runs a Poisson mix of 256 phase-separation requests (N 2 or 3,
 square boxes of side 64..512, 5000 steps each) through the
 continuous-batching loop and, for comparison, one request at a time, and
-reports p50/p99 latency and throughput of both; `phase_sweeps` times the
-four binodal run sets of Sec. IV (D1Q3 lines of 128 sites, the paper's step
-counts) through line groups, one launch per set.
+reports p50/p99 latency and throughput of both, plus the batch's capacity
+with all requests queued at t = 0; `phase_sweeps` times the four binodal run
+sets of Sec. IV (D1Q3 lines of 128 sites, the paper's step counts) through
+line groups, one launch per set, with throughput over the runs that stayed
+physical.
 """
 import argparse
 import hashlib
@@ -200,9 +202,11 @@ def run_phase_sweeps():
         group.close()
         n = runs[0][0]["n_comp"]
         L = runs[0][0]["shape"][0]
+        # throughput counts only the runs that stayed physical: a run whose
+        # density went non-finite or non-positive produced no result
         out[exp] = {"runs": len(runs), "steps": steps, "seconds": round(dt, 4),
                     "us_per_step": round(dt / steps * 1e6, 3),
-                    "value": round(len(runs) * L * n * steps / dt / 1e6, 1), "unit": "MLUPS×components",
+                    "value": round(healthy * L * n * steps / dt / 1e6, 1), "unit": "MLUPS×components",
                     "healthy_runs": healthy}
         for x in sims:
             x.close()
@@ -276,14 +280,55 @@ def run_serving(n_req):
     info16 = lb.lb_batch_config_info("f16s", 3, best16)
     batched16, bsum16 = serve.serve_batched(reqs, storage="f16s", config=best16, chunk=100, graph_steps=50)
     print(f"bench: serving batched, shifted FP16 storage {bsum16}", file=sys.stderr, flush=True)
+    # capacity: the same requests all queued at t = 0, so that the batch is
+    # never short of work (the Poisson mix above arrives more slowly than the
+    # batch serves it, and its throughput is the arrival rate)
+    saturated = [dict(r, arrival=0.0) for r in reqs]
+    sat, satsum = serve.serve_batched(saturated, config=best, chunk=100, graph_steps=50)
+    print(f"bench: serving batched, all requests at t = 0 {satsum}", file=sys.stderr, flush=True)
     serial, ssum = serve.serve_serial(reqs)
     print(f"bench: serving one at a time {ssum}", file=sys.stderr, flush=True)
-    bad = sum(x["status"] != 0 for x in batched + batched16 + serial)
+    bad = sum(x["status"] != 0 for x in batched + batched16 + sat + serial)
     return {"workload": f"poisson_mix_{n_req}", "rate_hz": 40.0, "steps_per_request": reqs[0]["nsteps"],
             "storage": "f32", "tuned_config": dict(info, index=best), "batched": bsum, "one_at_a_time": ssum,
             "speedup_throughput": round(bsum["mlups_x_comp"] / ssum["mlups_x_comp"], 3),
             "speedup_p99": round(ssum["p99_ms"] / bsum["p99_ms"], 3),
+            "batched_saturated": satsum,
+            "capacity_vs_one_at_a_time": round(satsum["mlups_x_comp"] / ssum["mlups_x_comp"], 3),
             "batched_f16s": dict(bsum16, tuned_config=dict(info16, index=best16)), "failed_requests": bad}
+
+
+def run_batch_only(n_req, steps, warmup, storage):
+    """One batch holding the first n_req requests of the serving mix, all
+    live, stepped `steps` times after `warmup` (for profiling the batched
+    kernel): HIP-event time per step and the algorithmic bytes of a step
+    (every population of every slot read and written once)."""
+    import numpy as np
+    import torch
+    import lbinputs as LI
+    from paper_0704_3444_amd import lb
+
+    reqs = LI.serving_mix(256)[:n_req]
+    batch = lb.Batch(storage=storage, max_comp=3, max_slots=n_req, arena_bytes=8 << 30, graph_steps=50)
+    alg = 0
+    try:
+        for r in reqs:
+            batch.add(r["cfg"], r["rho0"], 1 << 40)
+            alg += alg_bytes_per_step(int(r["cfg"]["n_comp"]), int(np.prod(r["cfg"]["shape"])), 9, storage)
+        batch.step(warmup)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        st = torch.cuda.current_stream()
+        a.record(st)
+        batch.step(steps)
+        b.record(st)
+        torch.cuda.synchronize()
+        batch.poll(0)
+        ms = a.elapsed_time(b) / steps
+    finally:
+        batch.close()
+    return {"requests": n_req, "storage": storage, "steps": steps, "ms_per_step": round(ms, 5),
+            "algorithmic_bytes_per_step": alg, "hbm_frac": round(alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
 def main():
@@ -300,6 +345,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-phase", action="store_true")
     ap.add_argument("--only-phase", action="store_true", help="time only the phase sweeps (for profiling them)")
+    ap.add_argument("--only-batch", type=int, default=0,
+                    help="time only one batch of this many serving requests (for profiling the batched kernel)")
     ap.add_argument("--walls", type=int, default=0, help="close axes by walls (bit a: axis a; split path only)")
     ap.add_argument("--serving-requests", type=int, default=256)
     args = ap.parse_args()
@@ -324,6 +371,11 @@ def main():
     if args.only_phase:
         torch.cuda.set_device(0)
         print(json.dumps({"phase_sweeps": run_phase_sweeps()}), flush=True)
+        return
+    if args.only_batch:
+        torch.cuda.set_device(0)
+        print(json.dumps({"batch": run_batch_only(args.only_batch, args.steps, args.warmup, args.storage)}),
+              flush=True)
         return
 
     cfg, rho0 = workload(args.workload)

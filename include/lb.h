@@ -5,8 +5,9 @@
  * (arXiv:0704.3444).
  *
  * The library advances N component distributions f^sigma_i on a periodic
- * lattice (or a box closed by walls) by the per-component lattice Boltzmann equation Eq. (ssLB) (BGK
- * collision with relaxation time tau plus a forcing term, then streaming),
+ * lattice (or a box closed by walls) by the per-component lattice Boltzmann
+ * equation Eq. (ssLB) (BGK collision with relaxation time tau plus a forcing
+ * term, then streaming),
  * with the equilibrium moments and forcing moments Eqs. (ff1)-(ff3) of
  * Sec. III, the force of Eq. (definef), and the chemical potentials of the
  * Flory-Huggins free energy Eq. (lgf) of Sec. IV (taken per mer, plus a
