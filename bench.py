@@ -10,7 +10,8 @@ steps / second / 1e6) with the state resident in HBM; the timed region is K
 lb_step calls bracketed by synchronisation and HIP events on the stream the
 kernels run on.  `roofline` prices the fused step kernel against the HBM
 peak: its algorithmic traffic per launch is every population read once and
-written once, 2 * N * S * (rest + (Q - 1) * moving slot bytes).  `cpu_baseline` times the FP64 CPU
+written once, 2 * N * S * (rest + reference + (Q - 1) * moving slot bytes; the
+reference, 2 bytes, only for shifted FP16).  `cpu_baseline` times the FP64 CPU
 oracle on a bounded sample of the same workload on the host cores.
 
 Three more objects on the same line (skipped with --no-f16s / --no-serving /
@@ -48,7 +49,8 @@ KERNEL_SOURCES = {
 KERNEL_NAMES = {("D2Q9", "sweep"): "k_sweep_d2q9", ("D2Q9", "tile"): "k_fused_d2q9",
                 ("D3Q19", "sweep"): "k_sweep_d3q19"}
 # bytes of one stored population: (rest slot, moving slot)
-STORE_BYTES = {"f64": (8, 8), "f32": (4, 4), "f16s": (4, 2)}
+# bytes per site and component: (rest slot, moving slot, reference)
+STORE_BYTES = {"f64": (8, 8, 0), "f32": (4, 4, 0), "f16s": (4, 2, 2)}
 
 
 def kernel_source_hash(lattice, kpath) -> str:
@@ -230,8 +232,8 @@ def calibrate_copy(gib=1.0, reps=5):
 
 
 def alg_bytes_per_step(N, S, Q, storage):
-    rest_b, move_b = STORE_BYTES[storage]
-    return 2 * N * S * (rest_b + (Q - 1) * move_b)
+    rest_b, move_b, ref_b = STORE_BYTES[storage]
+    return 2 * N * S * (rest_b + ref_b + (Q - 1) * move_b)
 
 
 def time_steps(cfg, rho0, storage, kpath, steps, warmup, stream):

@@ -58,18 +58,21 @@ typedef enum lb_lattice { LB_D1Q3 = 1, LB_D2Q9 = 2, LB_D3Q19 = 3 } lb_lattice;
 /* Storage and arithmetic precision of the populations.
  *   LB_F64:  stored and computed in FP64.
  *   LB_F32:  stored and computed in FP32.
- *   LB_F16S: computed in FP32; each moving population (i > 0) is stored as
- *            the FP16 deviation (f_i - w_i rbar^sigma) / s^sigma from the
- *            equilibrium at the mean density rbar^sigma of rho0^sigma, with
- *            s^sigma the smallest power of two >= max rho0^sigma; the rest
- *            slot holds an FP32 ledger that absorbs the FP16 rounding, so
- *            that every collision keeps each component's mass exactly.
- *            Populations take 2 bytes, the rest slot 4 (20 bytes per site
- *            and component on D2Q9, against 36 for LB_F32).  The rounding
- *            error of a stored value is at most 2^-11 of its deviation from
- *            w_i rbar^sigma: small where the mixture is near its mean
- *            composition, as large as plain FP16 where a component is far
- *            from its mean (a phase-separated minority). */
+ *   LB_F16S: computed in FP32; each site keeps, per component, an FP16
+ *            reference h = rho^sigma / (36 s^sigma) of its own density, set
+ *            by its collision, and stores each moving population (i > 0)
+ *            that it sends as the FP16 deviation f_i / s^sigma - 36 w_i h
+ *            from the equilibrium at that reference, with s^sigma twice the
+ *            smallest power of two >= max rho0^sigma; the rest slot holds an
+ *            FP32 ledger that absorbs the FP16 rounding, so that every
+ *            collision keeps each component's mass exactly (all stored
+ *            quantities are multiples of 2^-24 s^sigma and their sums are
+ *            exact).  Populations and the reference take 2 bytes, the rest
+ *            slot 4 (22 bytes per site and component on D2Q9, against 36 for
+ *            LB_F32).  The rounding error of a stored value is at most
+ *            2^-11 of its deviation from the equilibrium at the sending
+ *            site's density, so it stays small in every phase, the scarce
+ *            one included. */
 typedef enum lb_storage { LB_F64 = 0, LB_F32 = 1, LB_F16S = 2 } lb_storage;
 
 /* Which line of Eq. (definef) forms the force rho^sigma a^sigma, with
@@ -91,9 +94,8 @@ typedef enum lb_force_form { LB_FORCE_LOG = 0, LB_FORCE_EXPANDED = 1 } lb_force_
  *   LB_PATH_SWEEP: fused one-kernel step that sweeps the box: on D2Q9
  *                  64-column strips row by row (LB_F32 or LB_F16S, N <= 4,
  *                  nx a multiple of 64), on D3Q19 pencils of 64 x 4 sites
- *                  plane by plane (LB_F32 or LB_F16S, N <= 3, nx a multiple
- *                  of 64, ny of 4); periodic boxes, population copies below
- *                  4 GiB.
+ *                  plane by plane (LB_F32, N <= 3, nx a multiple of 64, ny
+ *                  of 4); periodic boxes, population copies below 4 GiB.
  * Asking for a path that does not support the run gives LB_ENOTSUP. */
 typedef enum lb_path { LB_PATH_AUTO = 0, LB_PATH_TILE = 1, LB_PATH_SPLIT = 2, LB_PATH_SWEEP = 3 } lb_path;
 
@@ -206,7 +208,7 @@ int lb_moments_noalloc(lb_ctx* c, double* rho, double* U, double* mu, double* P,
 int lb_get_f(lb_ctx* c, double* f);
 
 /* Checkpoint: the raw device state (storage precision), the reference of
- * LB_F16S storage (rbar^sigma and s^sigma; zero for the other storages) and
+ * LB_F16S storage (s^sigma; zero for the other storages) and
  * the step counter.  lb_state_bytes gives the size; lb_get_state copies it
  * to host memory, lb_set_state restores it into a context created with the
  * same parameters (any rho0).  Both synchronise. */

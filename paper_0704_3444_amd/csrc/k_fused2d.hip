@@ -19,8 +19,9 @@
 // indices are remapped so that the eight XCDs (dispatched round-robin) each
 // sweep a contiguous band of tiles, keeping halo rows in their own L2.
 // The kernel is templated on the storage codec (storage.hpp): FP64, FP32,
-// or shifted FP16 (decoded on load, the density from the site's ledger,
-// encoded on store).  No MFMA: the step is a bandwidth-bound stencil, not a
+// or shifted FP16 (decoded on load against the references of the source
+// sites, the density from the exact pulled total, encoded on store against
+// the site's new reference).  No MFMA: the step is a bandwidth-bound stencil, not a
 // contraction.
 #include <hip/hip_runtime.h>
 
@@ -60,6 +61,11 @@ __device__ __forceinline__ typename S::T gload_slot(const void* base, uint32_t o
   return T(*(const __attribute__((address_space(1))) typename S::Move*)b);
 }
 
+// Reference of the shifted codec at a byte offset, as FP32 (exact).
+__device__ __forceinline__ float gload_ref(const void* base, uint32_t off) {
+  return float(*(const __attribute__((address_space(1))) _Float16*)((const GChar*)base + off));
+}
+
 template <bool NTSTORE, typename V>
 __device__ __forceinline__ void gstore(void* base, uint32_t off, V v) {
   __attribute__((address_space(1))) V* d = (__attribute__((address_space(1))) V*)((GChar*)base + off);
@@ -70,9 +76,11 @@ __device__ __forceinline__ void gstore(void* base, uint32_t off, V v) {
 }
 
 // Byte offsets, without the component part, of the nine slots pulled into
-// site (x, y): slot i of the site r - v_i.
+// site (x, y) (slot i of the site r - v_i) and, for the shifted codec, of
+// the references of those sites.
 template <class S>
-__device__ __forceinline__ void pull_offsets(const Params<typename S::T>& p, int x, int y, uint32_t (&off)[9]) {
+__device__ __forceinline__ void pull_offsets(const Params<typename S::T>& p, int x, int y, uint32_t (&off)[9],
+                                             uint32_t (&roff)[9]) {
   using L = Lattice<2>;
   using B = BlockLayout<S, 9>;
   const int xm = wrap_add(x, -1, p.nx), xp = wrap_add(x, 1, p.nx);
@@ -81,31 +89,48 @@ __device__ __forceinline__ void pull_offsets(const Params<typename S::T>& p, int
   for (int i = 0; i < L::Q; ++i) {
     const int sx = L::cx(i) > 0 ? xm : (L::cx(i) < 0 ? xp : x);
     const int sy = L::cy(i) > 0 ? ym : (L::cy(i) < 0 ? yp : y);
-    off[i] = block_off<S>(p, sx, sy) + B::in_run(i, sx);
+    const uint32_t blk = block_off<S>(p, sx, sy);
+    off[i] = blk + B::in_run(i, sx);
+    roff[i] = blk + B::in_ref(sx);
   }
 }
 
+// Pulled populations of component c at a site from its offsets: decoded
+// values and their running sum (take_slot).
+template <class S>
+__device__ __forceinline__ void pull_component(const void* __restrict__ fin, const Params<typename S::T>& p, int c,
+                                               const uint32_t (&off)[9], const uint32_t (&roff)[9],
+                                               typename S::T (&f)[9], typename S::T& sum) {
+  using T = typename S::T;
+  using B = BlockLayout<S, 9>;
+  T raw[9];
+  float h[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    raw[i] = gload_slot<S>(fin, off[i] + B::run(c, i), i);
+    h[i] = 0.f;
+    if constexpr (S::kShift) h[i] = gload_ref(fin, roff[i] + B::ref(c));
+  }
+  sum = T(0);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) take_slot<S, 2>(i, raw[i], h[i], p.sh.scale[c], sum, f[i]);
+}
+
 // rho^sigma at (x, y) from the pulled slots: the sum of the decoded
-// populations in lattice order, or the ledger for the shifted codec (the
-// same values as the split path's density kernel).
+// populations in lattice order, or s times the exact pulled total for the
+// shifted codec (the same values as the split path's density kernel).
 template <class S, int NC>
 __device__ __forceinline__ void pulled_density(const void* __restrict__ fin, const Params<typename S::T>& p, int x,
                                                int y, typename S::T (&rho)[NC]) {
   using T = typename S::T;
-  using B = BlockLayout<S, 9>;
-  uint32_t off[9];
-  pull_offsets<S>(p, x, y, off);
+  uint32_t off[9], roff[9];
+  pull_offsets<S>(p, x, y, off, roff);
 #pragma unroll
   for (int k = 0; k < NC; ++k) {
-    T v[9], led = T(0);
+    T v[9], sum = T(0);
     if (k < p.n) {
-#pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        const T raw = gload_slot<S>(fin, off[i] + B::run(k, i), i);
-        led = i == 0 ? raw : led + raw;
-        v[i] = decode<S, 2>(p.sh, k, i, raw);
-      }
-      rho[k] = site_density<S, 9>(p.sh, k, v, led);
+      pull_component<S>(fin, p, k, off, roff, v, sum);
+      rho[k] = site_density<S>(sum, p.sh.scale[k]);
     } else {
       rho[k] = T(0);
     }
@@ -149,26 +174,21 @@ __device__ __forceinline__ void tile_step(const void* __restrict__ fin, void* __
     const int x = x0 + tx, y = y0 + ty + k * RS;
     valid[k] = x < nx && y < ny;
     if (valid[k]) {
-      uint32_t off[Q];
-      pull_offsets<S>(p, x, y, off);
+      uint32_t off[Q], roff[Q];
+      pull_offsets<S>(p, x, y, off, roff);
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        // one uniform branch per component, so that its nine loads are
-        // issued together
+        // one uniform branch per component, so that its loads are issued
+        // together
         T l = T(0);
         if (c < n) {
-#pragma unroll
-          for (int i = 0; i < Q; ++i) {
-            const T raw = gload_slot<S>(fin, off[i] + B::run(c, i), i);
-            l = i == 0 ? raw : l + raw;
-            f[k][c][i] = decode<S, 2>(p.sh, c, i, raw);
-          }
+          pull_component<S>(fin, p, c, off, roff, f[k][c], l);
         } else {
 #pragma unroll
           for (int i = 0; i < Q; ++i) f[k][c][i] = T(0);
         }
         led[k][c] = l;
-        s_rho[c][ty + k * RS + 2][tx + 2] = c < n ? site_density<S, Q>(p.sh, c, f[k][c], l) : T(0);
+        s_rho[c][ty + k * RS + 2][tx + 2] = c < n ? site_density<S>(l, p.sh.scale[c]) : T(0);
       }
     }
   }
@@ -270,15 +290,18 @@ __device__ __forceinline__ void tile_step(const void* __restrict__ fin, void* __
       const T inv_rs = rcp_(rs[c]);
       collide<2, T>(f[k][c], rs[c], ux, uy, T(0), Ax, Ay, Az, jx[c] * inv_rs, jy[c] * inv_rs, T(0), p.inv_tau);
       if constexpr (S::kShift) {
-        // FP16 deviations of the moving populations; the ledger keeps the rest
-        T rest = led[k][c];
+        // the site's new reference, the FP16 deviations of the moving
+        // populations, and the rest of the ledger
+        const _Float16 h = new_ref(led[k][c]);
+        float d[Q];
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
-          const _Float16 d = encode_move<2>(p.sh, c, i, f[k][c][i]);
-          rest -= float(d);
-          gstore<NTSTORE>(fout, own + B::run(c, i) + B::in_run(i, x), d);
+          const _Float16 di = encode_move<2>(i, f[k][c][i], p.sh.inv_scale[c], float(h));
+          d[i] = float(di);
+          gstore<NTSTORE>(fout, own + B::run(c, i) + B::in_run(i, x), di);
         }
-        gstore<NTSTORE>(fout, own + B::run(c, 0) + B::in_run(0, x), rest);
+        gstore<NTSTORE>(fout, own + B::ref(c) + B::in_ref(x), h);
+        gstore<NTSTORE>(fout, own + B::run(c, 0) + B::in_run(0, x), ledger_rest<Q>(led[k][c], float(h), d));
       } else {
 #pragma unroll
         for (int i = 0; i < Q; ++i) gstore<NTSTORE>(fout, own + B::run(c, i) + B::in_run(i, x), f[k][c][i]);

@@ -75,17 +75,22 @@ __device__ __forceinline__ long long stream_target(const SiteCoord& c, int i, co
   return beyond_wall<LAT>(c, i, +1, p) ? site_of(c.x, c.y, c.z, p) : neighbour<LAT>(c, i, +1, p);
 }
 
-// Byte offset of population i of component k at the site r - v_i (the slot
-// pulled into r); across a wall, the slot of -v_i at r itself (bounce-back).
-template <class S, int LAT, typename T>
-__device__ __forceinline__ uint64_t pull_byte(const SiteCoord& c, int k, int i, const Params<T>& p) {
+// The slot pulled into site c along v_i: slot i of the site r - v_i, or,
+// across a wall, slot -v_i of r itself (bounce-back).
+struct SlotAt {
+  int x;
+  long long row;
+  int i;
+};
+
+template <int LAT, typename T>
+__device__ __forceinline__ SlotAt pull_slot(const SiteCoord& c, int i, const Params<T>& p) {
   using L = Lattice<LAT>;
-  if (beyond_wall<LAT>(c, i, -1, p))
-    return pop_byte<S, L::Q>(p.n, p.nbx, k, L::opp(i), c.x, (long long)c.y + (long long)p.ny * c.z);
+  if (beyond_wall<LAT>(c, i, -1, p)) return {c.x, (long long)c.y + (long long)p.ny * c.z, L::opp(i)};
   const int sx = wrap_add(c.x, -L::cx(i), p.nx);
   const int sy = wrap_add(c.y, -L::cy(i), p.ny);
   const int sz = wrap_add(c.z, -L::cz(i), p.nz);
-  return pop_byte<S, L::Q>(p.n, p.nbx, k, i, sx, (long long)sy + (long long)p.ny * sz);
+  return {sx, (long long)sy + (long long)p.ny * sz, i};
 }
 
 // Byte offset of population i of component k at the site itself.
@@ -95,18 +100,21 @@ __device__ __forceinline__ uint64_t own_byte(const SiteCoord& c, int k, int i, c
 }
 
 // Populations of component k pulled into site c, decoded to the working
-// precision, and the site's ledger (shifted codec only).
+// precision, and their running sum (take_slot).
 template <class S, int LAT>
 __device__ __forceinline__ void pull_pops(const void* fin, const SiteCoord& c, int k,
                                           const Params<typename S::T>& p,
-                                          typename S::T (&f)[Lattice<LAT>::Q], typename S::T& ledger) {
+                                          typename S::T (&f)[Lattice<LAT>::Q], typename S::T& sum) {
   using T = typename S::T;
-  ledger = T(0);
+  constexpr int Q = Lattice<LAT>::Q;
+  sum = T(0);
 #pragma unroll
-  for (int i = 0; i < Lattice<LAT>::Q; ++i) {
-    const T raw = load_slot<S>(fin, pull_byte<S, LAT>(c, k, i, p), i);
-    ledger = i == 0 ? raw : ledger + raw;
-    f[i] = decode<S, LAT>(p.sh, k, i, raw);
+  for (int i = 0; i < Q; ++i) {
+    const SlotAt a = pull_slot<LAT>(c, i, p);
+    const T raw = load_slot<S>(fin, pop_byte<S, Q>(p.n, p.nbx, k, a.i, a.x, a.row), i);
+    float h = 0.f;
+    if constexpr (S::kShift) h = load_ref(fin, ref_byte<S, Q>(p.n, p.nbx, k, a.x, a.row));
+    take_slot<S, LAT>(i, raw, h, p.sh.scale[k], sum, f[i]);
   }
 }
 
@@ -114,72 +122,92 @@ __device__ __forceinline__ void pull_pops(const void* fin, const SiteCoord& c, i
 template <class S, int LAT, typename PT>
 __device__ __forceinline__ void pull_pops_exact(const void* fin, const SiteCoord& c, int k, const Params<PT>& p,
                                                 double (&f)[Lattice<LAT>::Q]) {
+  constexpr int Q = Lattice<LAT>::Q;
 #pragma unroll
-  for (int i = 0; i < Lattice<LAT>::Q; ++i)
-    f[i] = decode_exact<S, LAT>(p.sh, k, i, load_slot<S>(fin, pull_byte<S, LAT>(c, k, i, p), i));
+  for (int i = 0; i < Q; ++i) {
+    const SlotAt a = pull_slot<LAT>(c, i, p);
+    const auto raw = load_slot<S>(fin, pop_byte<S, Q>(p.n, p.nbx, k, a.i, a.x, a.row), i);
+    float h = 0.f;
+    if constexpr (S::kShift) h = load_ref(fin, ref_byte<S, Q>(p.n, p.nbx, k, a.x, a.row));
+    f[i] = take_exact<S, LAT>(i, raw, h, p.sh.scale[k]);
+  }
 }
 
 // Store the post-collision populations of component k at site c.  Plain
-// codecs write the values; the shifted codec writes the FP16 deviations of
-// the moving populations and puts the rest of the ledger into slot 0.
+// codecs write the values; the shifted codec writes the site's new
+// reference, the FP16 deviations of the moving populations, and in slot 0
+// the rest of the ledger (`sum`: the pulled total in units of s).
 template <class S, int LAT>
 __device__ __forceinline__ void store_pops(void* fout, const SiteCoord& c, int k, const Params<typename S::T>& p,
-                                           const typename S::T (&post)[Lattice<LAT>::Q], typename S::T ledger) {
+                                           const typename S::T (&post)[Lattice<LAT>::Q], typename S::T sum) {
   using T = typename S::T;
+  constexpr int Q = Lattice<LAT>::Q;
   char* out = static_cast<char*>(fout);
   if constexpr (S::kShift) {
-    T rest = ledger;
+    const _Float16 h = new_ref(sum);
+    float d[Q];
 #pragma unroll
-    for (int i = 1; i < Lattice<LAT>::Q; ++i) {
-      const _Float16 d = encode_move<LAT>(p.sh, k, i, post[i]);
-      rest -= float(d);
-      *reinterpret_cast<_Float16*>(out + own_byte<S, LAT>(c, k, i, p)) = d;
+    for (int i = 1; i < Q; ++i) {
+      const _Float16 di = encode_move<LAT>(i, post[i], p.sh.inv_scale[k], float(h));
+      d[i] = float(di);
+      *reinterpret_cast<_Float16*>(out + own_byte<S, LAT>(c, k, i, p)) = di;
     }
-    *reinterpret_cast<float*>(out + own_byte<S, LAT>(c, k, 0, p)) = rest;
+    *reinterpret_cast<_Float16*>(out + ref_byte<S, Q>(p.n, p.nbx, k, c.x, (long long)c.y + (long long)p.ny * c.z)) = h;
+    *reinterpret_cast<float*>(out + own_byte<S, LAT>(c, k, 0, p)) = ledger_rest<Q>(sum, float(h), d);
   } else {
 #pragma unroll
-    for (int i = 0; i < Lattice<LAT>::Q; ++i) *reinterpret_cast<T*>(out + own_byte<S, LAT>(c, k, i, p)) = post[i];
+    for (int i = 0; i < Q; ++i) *reinterpret_cast<T*>(out + own_byte<S, LAT>(c, k, i, p)) = post[i];
   }
 }
 
 // ---------------------------------------------------------------- init ----
 // Rest equilibrium f_i(r, 0) = w_i rho0(r), written in pull storage: slot
 // (i, r) holds the value that arrives at r + v_i (at r itself when a wall
-// lies between: the value pulled back across the wall).  The shifted codec stores
-// the FP16 deviations of the moving slots, and in the rest slot of r the
-// ledger that makes the site's stored total equal rho0(r) (to 2^-25 s).
+// lies between: the value pulled back across the wall).  The shifted codec
+// gives each site the reference of T0 = rho0 / s on the 2^-24 grid, stores
+// the FP16 deviations of the moving slots against it, and puts in the rest
+// slot of r what makes the total pulled into r equal T0(r) exactly (the
+// slots pulled into r are re-encoded here exactly as their own sites write
+// them).
 template <class S, int LAT>
 __global__ void __launch_bounds__(kBlock) k_init(const double* __restrict__ rho0, void* __restrict__ f,
                                                  Params<typename S::T> p) {
   using L = Lattice<LAT>;
   using T = typename S::T;
+  constexpr int Q = L::Q;
   const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= p.S) return;
   const SiteCoord c = coord_of(s, p);
   char* out = static_cast<char*>(f);
   for (int k = 0; k < p.n; ++k) {
+    const double* rk = rho0 + (long long)k * p.S;
     if constexpr (S::kShift) {
-      const double r0 = rho0[(long long)k * p.S + s];
-      double target = r0;
+      const double inv_s = double(p.sh.inv_scale[k]);
+      // T0 and the reference of a site
+      auto total = [&](long long site) { return rint(rk[site] * inv_s * 16777216.0) / 16777216.0; };
+      auto ref_of = [&](long long site) { return new_ref(float(total(site))); };
+      const _Float16 h = ref_of(s);
+      double rest = total(s) - double(ref_weight<LAT>(0)) * double(float(h));
 #pragma unroll
-      for (int i = 0; i < L::Q; ++i) target -= double(shift_ref<LAT>(p.sh, k, i));
-      target /= double(p.sh.scale[k]);
-#pragma unroll
-      for (int i = 1; i < L::Q; ++i) {
-        // the slot pulled into r carries w_i rho0(r); the slot written here
-        // carries w_i rho0(r + v_i)
-        target -= double(encode_move<LAT>(p.sh, k, i, float(L::w(i) * r0)));
-        const double rn = rho0[(long long)k * p.S + stream_target<LAT>(c, i, p)];
+      for (int i = 1; i < Q; ++i) {
+        // the slot written here carries w_i rho0(r + v_i)
+        const double rn = rk[stream_target<LAT>(c, i, p)];
         *reinterpret_cast<_Float16*>(out + own_byte<S, LAT>(c, k, i, p)) =
-            encode_move<LAT>(p.sh, k, i, float(L::w(i) * rn));
+            encode_move<LAT>(i, float(L::w(i) * rn), p.sh.inv_scale[k], float(h));
+        // the slot pulled into r carries w_i rho0(r), against its site's reference
+        const SlotAt a = pull_slot<LAT>(c, i, p);
+        const long long src = (long long)a.x + (long long)p.nx * a.row;
+        const float hs = float(ref_of(src));
+        const float d = float(encode_move<LAT>(i, float(L::w(i) * rk[s]), p.sh.inv_scale[k], hs));
+        rest -= double(ref_weight<LAT>(i)) * double(hs) + double(d);
       }
-      *reinterpret_cast<float*>(out + own_byte<S, LAT>(c, k, 0, p)) =
-          float(rint(target * 16777216.0) / 16777216.0);
+      *reinterpret_cast<_Float16*>(out + ref_byte<S, Q>(p.n, p.nbx, k, c.x, (long long)c.y + (long long)p.ny * c.z)) = h;
+      *reinterpret_cast<float*>(out + own_byte<S, LAT>(c, k, 0, p)) = float(rest);
     } else {
 #pragma unroll
-      for (int i = 0; i < L::Q; ++i) {
+      for (int i = 0; i < Q; ++i) {
         const long long src = stream_target<LAT>(c, i, p);
-        *reinterpret_cast<T*>(out + own_byte<S, LAT>(c, k, i, p)) = T(L::w(i) * rho0[(long long)k * p.S + src]);
+        *reinterpret_cast<T*>(out + own_byte<S, LAT>(c, k, i, p)) = T(L::w(i) * rk[src]);
       }
     }
   }
@@ -188,7 +216,7 @@ __global__ void __launch_bounds__(kBlock) k_init(const double* __restrict__ rho0
 // ------------------------------------------------------------- density ----
 // rho^sigma(r) = sum_i f_i(r): the population at r in direction i is the
 // slot (i, r - v_i).  The step takes it in the working precision (plain
-// codecs: the sum in direction order; shifted codec: from the ledger); the
+// codecs: the sum in direction order; shifted codec: s times the exact total); the
 // observables take the exact stored values summed in FP64.
 // NC > 0: the component count as a template parameter (N = NC), so that
 // all components' loads can be issued together (used on D3Q19, where it
@@ -214,9 +242,9 @@ __global__ void __launch_bounds__(kBlock) k_density(const void* __restrict__ f, 
       for (int i = 0; i < L::Q; ++i) acc += v[i];
       rho[(long long)k * p.S + s] = acc;
     } else {
-      T v[L::Q], ledger;
-      pull_pops<S, LAT>(f, c, k, p, v, ledger);
-      rho[(long long)k * p.S + s] = site_density<S, L::Q>(p.sh, k, v, ledger);
+      T v[L::Q], sum;
+      pull_pops<S, LAT>(f, c, k, p, v, sum);
+      rho[(long long)k * p.S + s] = site_density<S>(sum, p.sh.scale[k]);
     }
   }
 }
@@ -272,8 +300,8 @@ __global__ void __launch_bounds__(kBlock) k_collide(const void* __restrict__ fin
   T jx[kMaxComp], jy[kMaxComp], jz[kMaxComp];
   T rt = T(0), ux = T(0), uy = T(0), uz = T(0);
   for (int k = 0; k < p.n; ++k) {
-    T f[Q], ledger;
-    pull_pops<S, LAT>(fin, c, k, p, f, ledger);
+    T f[Q], sum;
+    pull_pops<S, LAT>(fin, c, k, p, f, sum);
     T ax = T(0), ay = T(0), az = T(0);
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
@@ -295,8 +323,8 @@ __global__ void __launch_bounds__(kBlock) k_collide(const void* __restrict__ fin
   uz *= inv_rt;
   for (int k = 0; k < p.n; ++k) {
     const T rs = rho[(long long)k * p.S + s];
-    T f[Q], ledger;
-    pull_pops<S, LAT>(fin, c, k, p, f, ledger);
+    T f[Q], sum;
+    pull_pops<S, LAT>(fin, c, k, p, f, sum);
     const T* hk = h + (long long)k * p.S;
     const T* rk = rho + (long long)k * p.S;
     T Ax, Ay, Az;
@@ -305,7 +333,7 @@ __global__ void __launch_bounds__(kBlock) k_collide(const void* __restrict__ fin
     const T inv_rs = rcp_(rs);
     collide<LAT, T>(f, rs, ux, uy, uz, Ax, Ay, Az, jx[k] * inv_rs, jy[k] * inv_rs, jz[k] * inv_rs,
                     p.inv_tau);
-    store_pops<S, LAT>(fout, c, k, p, f, ledger);
+    store_pops<S, LAT>(fout, c, k, p, f, sum);
   }
 }
 

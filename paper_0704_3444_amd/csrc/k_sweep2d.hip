@@ -65,53 +65,73 @@ __device__ __forceinline__ void wait_vm() {
 // for its global loads in flight.
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
-// Staged row: per component the nine runs of the pulled populations in the
-// block's run order (v_y groups 0 | +1 | -1, each from its source row), then
-// the halo pieces: for each run (c, i), from the same source row, the last
-// 16 bytes of the left neighbour block's run (columns x0 - 16/e .. x0 - 1,
-// e the slot size) and the first 16 bytes of the right neighbour block's
-// run (columns x0 + 64 .. x0 + 63 + 16/e); piece (c, i, side) at
-// kHaloOff + 16 ((9 c + i) 2 + side).
+// Staged row: per component the runs of the pulled populations in the
+// block's run order (v_y groups 0 | +1 | -1, each from its source row; group
+// 0 holds the row's own references in the shifted codec); for the shifted
+// codec the reference runs of the rows above and below (component c, row
+// above: kHRowOff + 256 c, row below: + 128); then the halo pieces: for
+// each run (c, i), from the same source row, the last 16 bytes of the left
+// neighbour block's run (columns x0 - 16/e .. x0 - 1, e the slot size) and
+// the first 16 bytes of the right neighbour block's run (columns x0 + 64 ..
+// x0 + 63 + 16/e), piece (c, i, side) at kHaloOff + 16 ((9 c + i) 2 + side);
+// for the shifted codec the same two pieces of the reference runs of the
+// three source rows (hr = 0: the row, 1: above, 2: below) at kHaloOff +
+// 16 (18 NC + (3 c + hr) 2 + side).
 template <class S, int NC>
 struct Staged {
   using B = BlockLayout<S, 9>;
-  static constexpr uint32_t kGroup0 = kW * (B::kRest + 2 * B::kMove);  // v_y = 0: i = 0, 1, 3
-  static constexpr uint32_t kGroup1 = kW * 3 * B::kMove;               // v_y = +-1: 2, 5, 6 / 4, 7, 8
+  static constexpr uint32_t kGroup0 = kW * (B::kRest + 2 * B::kMove + B::kRef);  // v_y = 0: i = 0, 1, 3 (+ h)
+  static constexpr uint32_t kGroup1 = kW * 3 * B::kMove;                         // v_y = +-1: 2, 5, 6 / 4, 7, 8
   static constexpr uint32_t kMain = NC * B::kComp;
-  static constexpr int kPieces = 18 * NC;
+  static constexpr uint32_t kHRowOff = kMain;
+  static constexpr uint32_t kHRows = S::kShift ? NC * 2 * kW * B::kRef : 0;
+  static constexpr int kRunPieces = 18 * NC;
+  static constexpr int kPieces = kRunPieces + (S::kShift ? 6 * NC : 0);
   static constexpr int kHaloLoads = (kPieces + 63) / 64;
-  static constexpr uint32_t kHaloOff = kMain;
+  static constexpr uint32_t kHaloOff = kHRowOff + kHRows;
   static constexpr uint32_t kBytes = kHaloOff + 16 * kPieces;
-  static constexpr int kLoads = 3 * NC + kHaloLoads;  // direct loads per staged row
+  static constexpr int kLoads = 3 * NC + (S::kShift ? 1 : 0) + kHaloLoads;  // direct loads per staged row
+  static constexpr int kStores = (S::kShift ? 10 : 9) * NC;                // stores per collided row
   static_assert(kGroup0 % 16 == 0 && kGroup1 % 16 == 0 && kGroup0 <= 1024 && kGroup1 <= 1024, "group size");
-  static_assert(kMain % 16 == 0, "halo pieces aligned");
+  static_assert(kMain % 16 == 0 && kHaloOff % 16 == 0, "pieces aligned");
+  static_assert(!S::kShift || 2 * NC * kW * B::kRef <= 64 * 16, "reference rows in one load");
+  static_assert(kStores < 64, "vmcnt range");
 };
 
 
 // Per-lane parts of the halo pieces that do not change along the sweep:
 // the column part of the piece's byte offset and which source row (v_y =
 // +1: the row above, 0: the row itself, -1: the row below) it comes from.
-template <int NC>
+template <class S, int NC>
 struct Gather {
-  uint32_t col[(18 * NC + 63) / 64];
-  int dy[(18 * NC + 63) / 64];
+  static constexpr int kN = Staged<S, NC>::kHaloLoads;
+  uint32_t col[kN];
+  int dy[kN];
 };
 
 template <class S, int NC>
-__device__ __forceinline__ Gather<NC> make_gather(const Params<float>& p, int lane, int x0) {
+__device__ __forceinline__ Gather<S, NC> make_gather(const Params<float>& p, int lane, int x0) {
   using L = Lattice<2>;
   using B = BlockLayout<S, 9>;
   using G = Staged<S, NC>;
-  Gather<NC> g;
+  Gather<S, NC> g;
 #pragma unroll
-  for (int j = 0; j < G::kHaloLoads; ++j) {  // piece e = (9 c + i) 2 + side
+  for (int j = 0; j < G::kHaloLoads; ++j) {
     const int e0 = j * 64 + lane;
     const int e = e0 < G::kPieces ? e0 : 0;
-    const int c = e / 18, i = (e / 2) % 9, side = e & 1;
+    const int side = e & 1;
     const int bx = side == 0 ? wrap_add(x0, -1, p.nx) : wrap_add(x0 + kW - 1, 1, p.nx);  // neighbour block
-    const uint32_t run_bytes = kW * (i == 0 ? B::kRest : B::kMove);
-    g.col[j] = uint32_t(bx >> 6) * uint32_t(NC * B::kComp) + B::run(c, i) + (side == 0 ? run_bytes - 16u : 0u);
-    g.dy[j] = L::cy(i);
+    const uint32_t blk = uint32_t(bx >> 6) * uint32_t(NC * B::kComp);
+    if (e < G::kRunPieces) {  // piece e = (9 c + i) 2 + side
+      const int c = e / 18, i = (e / 2) % 9;
+      const uint32_t run_bytes = kW * (i == 0 ? B::kRest : B::kMove);
+      g.col[j] = blk + B::run(c, i) + (side == 0 ? run_bytes - 16u : 0u);
+      g.dy[j] = L::cy(i);
+    } else {  // reference piece e = 18 NC + (3 c + hr) 2 + side
+      const int q = (e - G::kRunPieces) / 2, c = q / 3, hr = q % 3;
+      g.col[j] = blk + B::ref(c) + (side == 0 ? kW * B::kRef - 16u : 0u);
+      g.dy[j] = hr == 0 ? 0 : (hr == 1 ? 1 : -1);
+    }
   }
   return g;
 }
@@ -120,7 +140,7 @@ __device__ __forceinline__ Gather<NC> make_gather(const Params<float>& p, int la
 // into the LDS slot `dst` (Staged layout) with exactly Staged::kLoads direct
 // loads (each load has at least one active lane).
 template <class S, int NC>
-__device__ __forceinline__ void stage_row(const char* fin, const Params<float>& p, const Gather<NC>& g,
+__device__ __forceinline__ void stage_row(const char* fin, const Params<float>& p, const Gather<S, NC>& g,
                                           int lane, int x0, int r, char* dst_in) {
   using B = BlockLayout<S, 9>;
   // The LDS destination is passed through an empty asm statement: the
@@ -147,6 +167,14 @@ __device__ __forceinline__ void stage_row(const char* fin, const Params<float>& 
         __builtin_amdgcn_global_load_lds(src, dst + B::run(c, first[g3]), 16, 0, 0);
     }
   }
+  if constexpr (S::kShift) {
+    // reference runs of the rows above and below: lane (2 c + q) 8 + chunk
+    const int c = lane >> 4, q = (lane >> 3) & 1, chunk = lane & 7;
+    const uint32_t rq = q == 0 ? rowu : rowd;
+    if (lane < 16 * NC)
+      __builtin_amdgcn_global_load_lds(fin + (rq + blk + B::ref(c < NC ? c : 0) + uint32_t(chunk) * 16u),
+                                       dst + G::kHRowOff, 16, 0, 0);
+  }
 #pragma unroll
   for (int j = 0; j < G::kHaloLoads; ++j) {
     const uint32_t row = g.dy[j] > 0 ? rowu : (g.dy[j] < 0 ? rowd : row0);
@@ -168,6 +196,22 @@ __device__ __forceinline__ uint32_t staged_off(int c, int i, int col) {
   if (col >= kW) return G::kHaloOff + 16u * uint32_t((9 * c + i) * 2 + 1) + uint32_t(col - kW) * e;
   return B::run(c, i) + uint32_t(col) * e;
 }
+
+// LDS byte offset of the reference of component c in relative column col
+// (-8 .. 71) of the source row dy (0, +1: above, -1: below) of a staged row
+// (shifted codec).
+template <class S, int NC>
+__device__ __forceinline__ uint32_t staged_ref_off(int c, int dy, int col) {
+  using B = BlockLayout<S, 9>;
+  using G = Staged<S, NC>;
+  const int hr = dy == 0 ? 0 : (dy > 0 ? 1 : 2);
+  if (col < 0) return G::kHaloOff + 16u * uint32_t(G::kRunPieces + (3 * c + hr) * 2) + uint32_t(col + 8) * 2u;
+  if (col >= kW) return G::kHaloOff + 16u * uint32_t(G::kRunPieces + (3 * c + hr) * 2 + 1) + uint32_t(col - kW) * 2u;
+  if (dy == 0) return B::ref(c) + uint32_t(col) * 2u;
+  return G::kHRowOff + uint32_t(2 * c + (dy > 0 ? 0 : 1)) * (kW * 2u) + uint32_t(col) * 2u;
+}
+
+__device__ __forceinline__ float lds_ref(const char* a) { return float(*reinterpret_cast<const _Float16*>(a)); }
 
 template <class S>
 __device__ __forceinline__ float lds_raw(const char* a, int i) {
@@ -207,76 +251,75 @@ __global__ void __launch_bounds__(256) k_sweep_d2q9(const void* fin_v, void* fou
   // strip; the edge lanes take the edge words instead
   const int lm = lane > 0 ? lane - 1 : 0, lp = lane < kW - 1 ? lane + 1 : kW - 1;
 
-  // Shift reference of the component of a halo lane (lane % NC), picked by
-  // selects and kept in registers: an indexed read of the parameters would
-  // be a vector memory load inside the rounds, whose wait would also wait
-  // for the stores in flight.
-  float halo_ref[3] = {0.f, 0.f, 0.f};
+  // Scale of the component of a halo lane (lane % NC), picked by selects
+  // and kept in a register: an indexed read of the parameters would be a
+  // vector memory load inside the rounds, whose wait would also wait for
+  // the stores in flight.
+  float halo_scale = 0.f;
   if constexpr (S::kShift) {
     const int c = lane % NC;
-    halo_ref[0] = p.sh.rbar[0];
-    halo_ref[1] = p.sh.scale[0];
-    halo_ref[2] = p.sh.csum[0];
+    halo_scale = p.sh.scale[0];
 #pragma unroll
-    for (int q = 1; q < NC; ++q) {
-      halo_ref[0] = c == q ? p.sh.rbar[q] : halo_ref[0];
-      halo_ref[1] = c == q ? p.sh.scale[q] : halo_ref[1];
-      halo_ref[2] = c == q ? p.sh.csum[q] : halo_ref[2];
-    }
-    asm volatile("" : "+v"(halo_ref[0]), "+v"(halo_ref[1]), "+v"(halo_ref[2]));
+    for (int q = 1; q < NC; ++q) halo_scale = c == q ? p.sh.scale[q] : halo_scale;
+    asm volatile("" : "+v"(halo_scale));
   }
 
   // Take a staged row into registers: decoded populations, in direction
-  // order, and the ledger of each component (shifted codec).
-  auto take = [&](const char* st, T (&f)[NC][9], T (&ledger)[NC]) {
+  // order, and the running sum of each component (take_slot).
+  auto take = [&](const char* st, T (&f)[NC][9], T (&ledger)[NC]) __attribute__((always_inline)) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       T led = T(0);
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
         const int col = L::cx(i) > 0 ? lm : (L::cx(i) < 0 ? lp : lane);
+        const bool edge = L::cx(i) > 0 ? lane == 0 : lane == kW - 1;  // pulls from column -1 or 64
         T raw = lds_raw<S>(st + B::run(c, i) + B::in_run(i, col), i);
-        if (L::cx(i) != 0) {  // lane 0 pulls from column -1, lane 63 from column 64
+        if (L::cx(i) != 0) {
           const T e = lds_raw<S>(st + staged_off<S, NC>(c, i, L::cx(i) > 0 ? -1 : kW), i);
-          raw = (L::cx(i) > 0 ? lane == 0 : lane == kW - 1) ? e : raw;
+          raw = edge ? e : raw;
         }
-        led = i == 0 ? raw : led + raw;
-        f[c][i] = decode<S, 2>(p.sh, c, i, raw);
+        float h = 0.f;
+        if constexpr (S::kShift) {
+          h = lds_ref(st + staged_ref_off<S, NC>(c, L::cy(i), col));
+          if (L::cx(i) != 0) {
+            const float e = lds_ref(st + staged_ref_off<S, NC>(c, L::cy(i), L::cx(i) > 0 ? -1 : kW));
+            h = edge ? e : h;
+          }
+        }
+        take_slot<S, 2>(i, raw, h, p.sh.scale[c], led, f[c][i]);
       }
       ledger[c] = led;
     }
   };
   // densities of virtual row r from taken populations
-  auto put_rho = [&](int r, const T (&f)[NC][9], const T (&ledger)[NC]) {
+  auto put_rho = [&](int r, const T (&f)[NC][9], const T (&ledger)[NC]) __attribute__((always_inline)) {
     const int sr = rslot(r);
 #pragma unroll
-    for (int c = 0; c < NC; ++c) s_rho[sr][c][lane + 2] = site_density<S, 9>(p.sh, c, f[c], ledger[c]);
+    for (int c = 0; c < NC; ++c) s_rho[sr][c][lane + 2] = site_density<S>(ledger[c], p.sh.scale[c]);
   };
   // densities of the four halo columns (-2, -1, 64, 65) of virtual row r:
-  // lane hc * NC + c sums its nine pulled values in direction order
-  // (the lane's component varies over the lanes: its shift reference is
-  // the one picked once per lane below, in slot 0 of sh1)
-  auto put_rho_halo = [&](int r, const char* st) {
+  // lane hc * NC + c sums its nine pulled values in direction order (the
+  // lane's component varies over the lanes: its scale is the one picked
+  // once per lane above)
+  auto put_rho_halo = [&](int r, const char* st) __attribute__((always_inline)) {
     if (lane < 4 * NC) {
       const int hc = lane / NC, c = lane % NC;
       const int hcol = hc < 2 ? hc - 2 : kW + hc - 2;
-      ShiftRef sh1 = {};
-      sh1.rbar[0] = halo_ref[0];
-      sh1.scale[0] = halo_ref[1];
-      sh1.csum[0] = halo_ref[2];
       T v[9], led = T(0);
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
         const T raw = lds_raw<S>(st + staged_off<S, NC>(c, i, hcol - L::cx(i)), i);
-        led = i == 0 ? raw : led + raw;
-        v[i] = decode<S, 2>(sh1, 0, i, raw);
+        float h = 0.f;
+        if constexpr (S::kShift) h = lds_ref(st + staged_ref_off<S, NC>(c, L::cy(i), hcol - L::cx(i)));
+        take_slot<S, 2>(i, raw, h, halo_scale, led, v[i]);
       }
-      s_rho[rslot(r)][c][hc < 2 ? hc : kW + hc] = site_density<S, 9>(sh1, 0, v, led);
+      s_rho[rslot(r)][c][hc < 2 ? hc : kW + hc] = site_density<S>(led, halo_scale);
     }
   };
 
   // potential h of virtual row r at h position q (column x0 - 1 + q)
-  auto put_h = [&](int r, int q) {
+  auto put_h = [&](int r, int q) __attribute__((always_inline)) {
     const int s0 = rslot(r - 1), s1 = rslot(r), s2 = rslot(r + 1);
     const int pc = q + 1;  // rho position of the column
     T rr[NC], lap[NC], mu[NC], hh[NC];
@@ -297,15 +340,15 @@ __global__ void __launch_bounds__(256) k_sweep_d2q9(const void* fin_v, void* fou
   };
   // h of rows r0 .. r0+3: each wave its own row's 64 interior columns, wave 0
   // the eight edge columns (q = 0 and 65) of all four rows
-  auto put_h4 = [&](int r0) {
+  auto put_h4 = [&](int r0) __attribute__((always_inline)) {
     put_h(r0 + w, lane + 1);
     if (w == 0 && lane < 8) put_h(r0 + (lane >> 1), (lane & 1) ? kHW - 1 : 0);
   };
 
-  // collision of row rc from the populations and ledgers taken one round
+  // collision of row rc from the populations and sums taken one round
   // earlier, in place (shifted codec: Fc then holds the stored deviations,
-  // the ledger the stored rest value)
-  auto collide_row = [&](int rc, T (&Fc)[NC][9], T (&Lc)[NC]) {
+  // Lc the stored rest value, Hc the new references)
+  auto collide_row = [&](int rc, T (&Fc)[NC][9], T (&Lc)[NC], float (&Hc)[NC]) __attribute__((always_inline)) {
     const int sr = rslot(rc);
     T rs[NC], jx[NC], jy[NC];
     T rt = T(0), ux = T(0), uy = T(0);
@@ -348,25 +391,27 @@ __global__ void __launch_bounds__(256) k_sweep_d2q9(const void* fin_v, void* fou
       for (int i = 0; i < 9; ++i) f[i] = Fc[c][i];
       collide<2, T>(f, rs[c], ux, uy, T(0), Ax, Ay, Az, jx[c] * inv_rs, jy[c] * inv_rs, T(0), p.inv_tau);
       if constexpr (S::kShift) {
-        // FP16 deviations of the moving populations; the ledger keeps the rest
-        T rest = Lc[c];
+        // the site's new reference, the FP16 deviations of the moving
+        // populations, and the rest of the ledger
+        const float h = float(new_ref(Lc[c]));
+        float d[9];
 #pragma unroll
-        for (int i = 1; i < 9; ++i) {
-          const _Float16 d = encode_move<2>(p.sh, c, i, f[i]);
-          rest -= float(d);
-          Fc[c][i] = float(d);
-        }
-        Lc[c] = rest;
+        for (int i = 1; i < 9; ++i) d[i] = float(encode_move<2>(i, f[i], p.sh.inv_scale[c], h));
+        Lc[c] = ledger_rest<9>(Lc[c], h, d);
+#pragma unroll
+        for (int i = 1; i < 9; ++i) Fc[c][i] = d[i];
+        Hc[c] = h;
       } else {
 #pragma unroll
         for (int i = 0; i < 9; ++i) Fc[c][i] = f[i];
       }
     }
   };
-  // non-temporal stores of a collided row: exactly 9 NC store instructions
-  // (one per run; runs are 256 or 128 bytes apart, so none merge), which the
-  // wait at the start of the next round counts on
-  auto store_row = [&](int rc, const T (&Fc)[NC][9], const T (&Lc)[NC]) {
+  // non-temporal stores of a collided row: exactly Staged::kStores store
+  // instructions (one per run, and one per reference run; runs are 256 or
+  // 128 bytes apart, so none merge), which the wait at the start of the
+  // next round counts on
+  auto store_row = [&](int rc, const T (&Fc)[NC][9], const T (&Lc)[NC], const float (&Hc)[NC]) __attribute__((always_inline)) {
     const uint32_t orow = (uint32_t(rc) * uint32_t(p.nbx) + uint32_t(x0 >> 6)) * uint32_t(NC * B::kComp);
     const uint32_t own_rest = orow + B::in_run(0, lane), own_move = orow + B::in_run(1, lane);
 #pragma unroll
@@ -384,12 +429,16 @@ __global__ void __launch_bounds__(256) k_sweep_d2q9(const void* fin_v, void* fou
           __builtin_nontemporal_store(Fc[c][i], reinterpret_cast<T*>(outc + off));
         }
       }
+      if constexpr (S::kShift)
+        __builtin_nontemporal_store(_Float16(Hc[c]), reinterpret_cast<_Float16*>(static_cast<char*>(fout) + orow +
+                                                                                 B::ref(c) + B::in_ref(lane)));
     }
   };
 
   T F0[NC][9], L0[NC], F1[NC][9], L1[NC];
+  float H0[NC];
   char* const stage = s_stage[w];
-  const Gather<NC> gat = make_gather<S, NC>(p, lane, x0);
+  const Gather<S, NC> gat = make_gather<S, NC>(p, lane, x0);
 
   // ---- prologue --------------------------------------------------------
   // rho of rows ya-2, ya-1 (waves 2, 3) and ya .. ya+3 (all waves); h of rows
@@ -417,17 +466,17 @@ __global__ void __launch_bounds__(256) k_sweep_d2q9(const void* fin_v, void* fou
   // Round k takes row ra = rc + 4 (staged in the round before) into F1 and
   // collides row rc = ya + 4k + w from F0, then moves F1 into F0.  Vector
   // memory operations retire in issue order, and a round that collided
-  // issued its 9 NC stores after its staging loads, so the next round waits
-  // until at most 9 NC operations remain in flight: the staged row has
-  // landed, the stores complete during that round.  In a full round every
-  // wave collides and stores unconditionally; rounds 1 .. full - 1 are
+  // issued its kStores stores after its staging loads, so the next round
+  // waits until at most kStores operations remain in flight: the staged row
+  // has landed, the stores complete during that round.  In a full round
+  // every wave collides and stores unconditionally; rounds 1 .. full - 1 are
   // entered only from full rounds, so the compiler's own wait before the
-  // first read of the staged row counts the same 9 NC stores.
-  auto round = [&](int k, bool full, bool prev_stored) {
+  // first read of the staged row counts the same stores.
+  auto round = [&](int k, bool full, bool prev_stored) __attribute__((always_inline)) {
     const int rc = ya + 4 * k + w;
     const int ra = rc + 4;
     if (prev_stored)
-      wait_vm<9 * NC>();
+      wait_vm<G::kStores>();
     else
       wait_vm<0>();
     take(stage, F1, L1);
@@ -446,8 +495,8 @@ __global__ void __launch_bounds__(256) k_sweep_d2q9(const void* fin_v, void* fou
     put_h4(ya + 4 * k + 3);
     lds_barrier();
     if (full || rc < yb) {
-      collide_row(rc, F0, L0);
-      store_row(rc, F0, L0);
+      collide_row(rc, F0, L0, H0);
+      store_row(rc, F0, L0, H0);
     }
 #pragma unroll
     for (int c = 0; c < NC; ++c) {

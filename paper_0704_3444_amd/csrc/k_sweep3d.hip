@@ -77,9 +77,8 @@ constexpr int kXMinus[5] = {2, 8, 10, 12, 14};  // D3Q19 directions with v_x = -
 constexpr int kXPlus[5] = {1, 7, 9, 11, 13};    // and with v_x = +1
 
 // Per-wave staging of one plane, filled by direct global-to-LDS loads one
-// plane ahead: the halo-row unit (19 pulled values per lane; raw 32-bit
-// words, a shifted FP16 moving value in the half the lane's parity selects)
-// and the halo-column pieces.
+// plane ahead: the halo-row unit (19 pulled values per lane) and the
+// halo-column pieces.
 struct Stage {
   uint32_t unit[19][kW];
   uint32_t piece[kPieces][4];
@@ -131,50 +130,10 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const void* base, ui
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
 }
 
-// Shift reference of component c alone (slot 0), picked by selects from the
-// kernel arguments so that it stays in registers.
-template <class S, int NC>
-__device__ __forceinline__ ShiftRef ref_of(const Params<float>& p, int c) {
-  ShiftRef r = {};
-  if constexpr (S::kShift) {
-    r.rbar[0] = p.sh.rbar[0];
-    r.scale[0] = p.sh.scale[0];
-    r.inv_scale[0] = p.sh.inv_scale[0];
-    r.csum[0] = p.sh.csum[0];
-#pragma unroll
-    for (int q = 1; q < NC; ++q) {
-      r.rbar[0] = c == q ? p.sh.rbar[q] : r.rbar[0];
-      r.scale[0] = c == q ? p.sh.scale[q] : r.scale[0];
-      r.inv_scale[0] = c == q ? p.sh.inv_scale[q] : r.inv_scale[0];
-      r.csum[0] = c == q ? p.sh.csum[q] : r.csum[0];
-    }
-  }
-  return r;
-}
-
-// Raw bits of one slot as a float register: FP32 values as they are, the
-// FP16 moving values zero-extended (converted only when consumed, so that
-// issuing the loads does not wait for them).
-template <class S>
-__device__ __forceinline__ float load_raw(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff, int i) {
-  if (i == 0 || sizeof(typename S::Move) == 4)
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, 0));
-  return __builtin_bit_cast(float, uint32_t(__builtin_amdgcn_raw_buffer_load_b16(rs, voff, soff, 0)));
-}
-
-// Slot value in the working precision from load_raw's register.
-template <class S>
-__device__ __forceinline__ float raw_value(float r, int i) {
-  if (i == 0 || sizeof(typename S::Move) == 4) return r;
-  return float(__builtin_bit_cast(_Float16, uint16_t(__builtin_bit_cast(uint32_t, r))));
-}
-
-// Slot value from a staged 32-bit word: for a shifted FP16 moving slot the
-// half of the word at byte offset 2 (odd) or 0 (even) of the slot's column.
-template <class S>
-__device__ __forceinline__ float staged_value(uint32_t w, int i, bool odd) {
-  if (i == 0 || sizeof(typename S::Move) == 4) return __builtin_bit_cast(float, w);
-  return float(__builtin_bit_cast(_Float16, uint16_t(odd ? (w >> 16) : (w & 0xffffu))));
+// One FP32 slot through the buffer resource (row and run part of the offset
+// in an SGPR, the lane's column part in a VGPR).
+__device__ __forceinline__ float load_slot32(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, 0));
 }
 
 template <int V>
@@ -182,11 +141,9 @@ using I = std::integral_constant<int, V>;
 
 // Slot value of run i at column x0 + src (src in -3 .. 66, but not 1 .. 62)
 // from the halo-column pieces of one density row (Stage::piece).
-template <class S>
 __device__ __forceinline__ float piece_value(const char* row_pieces, int i, int src) {
-  using B = BlockLayout<S, 19>;
-  const int esz = i == 0 ? int(B::kRest) : int(B::kMove);
-  const int per = 16 / esz;  // slots per piece
+  constexpr int esz = 4;
+  constexpr int per = 16 / esz;  // slots per piece
   int q, e;
   if (src < 0) {
     q = i, e = src + per;
@@ -203,9 +160,7 @@ __device__ __forceinline__ float piece_value(const char* row_pieces, int i, int 
     for (int m = 0; m < 5; ++m) k = kXPlus[m] == i ? m : k;
     q = 43 + k, e = per - 1;
   }
-  const char* a = row_pieces + q * 16 + e * esz;
-  if (i == 0 || sizeof(typename S::Move) == 4) return *reinterpret_cast<const float*>(a);
-  return float(*reinterpret_cast<const _Float16*>(a));
+  return *reinterpret_cast<const float*>(row_pieces + q * 16 + e * esz);
 }
 
 // 16 bytes per lane from byte offset voff of the buffer into LDS at dst +
@@ -232,6 +187,7 @@ __global__ void __launch_bounds__(64 * kTY * NC) k_sweep_d3q19(const void* fin_v
   using L = Lattice<3>;
   using T = float;
   using B = BlockLayout<S, 19>;
+  static_assert(!S::kShift && B::kRest == 4 && B::kMove == 4, "FP32 slots only");
   __shared__ Smem<S, NC> sm;
   const uint32_t copy_bytes = uint32_t(p.ny) * uint32_t(p.nz) * uint32_t(p.nbx) * uint32_t(NC * B::kComp);
   const __amdgpu_buffer_rsrc_t fin = buffer_of(fin_v, copy_bytes);
@@ -260,7 +216,6 @@ __global__ void __launch_bounds__(64 * kTY * NC) k_sweep_d3q19(const void* fin_v
   // of the density rows 2 r and 2 r + 1
   const int xcol_lds = lane < 2 ? lane : kW + lane;  // 0, 1, 66, 67 for lanes 0 .. 3
   const LanePart lp_own = lane_part<S, NC>(p, x);
-  const ShiftRef sh = ref_of<S, NC>(p, c);
   const uint32_t stride = uint32_t(p.nbx) * uint32_t(NC * B::kComp);  // bytes per row of blocks
   // the piece each lane loads in the two 16-byte loads of the halo columns:
   // density row 2 r + prow[j], source row offsets (pdy, pdz), and the part of
@@ -337,7 +292,7 @@ __global__ void __launch_bounds__(64 * kTY * NC) k_sweep_d3q19(const void* fin_v
     for (int i = 0; i < 19; ++i) {
       const uint32_t so = rowb(y_own, zw, L::cy(i), L::cz(i)) + B::run(c, i);
       const uint32_t vo = i == 0 ? lp_own.rest : lp_own.move[L::cx(i) + 1];
-      Pn[i] = load_raw<S>(fin, vo, so, i);
+      Pn[i] = load_slot32(fin, vo, so);
     }
   };
 
@@ -351,11 +306,11 @@ __global__ void __launch_bounds__(64 * kTY * NC) k_sweep_d3q19(const void* fin_v
       float led = 0.f;
 #pragma unroll
       for (int i = 0; i < 19; ++i) {
-        const float v = raw_value<S>(Xr[i], i);
+        const float v = Xr[i];
         led = i == 0 ? v : led + v;
-        Dd[i] = decode<S, 3>(sh, 0, i, v);
+        Dd[i] = v;
       }
-      sm.rho[rs][c][r + 2][lane + 2] = site_density<S, 19>(sh, 0, Dd, led);
+      sm.rho[rs][c][r + 2][lane + 2] = led;
       Ld = led;
       if (keep) {
         float ax = 0.f, ay = 0.f, az = 0.f;
@@ -377,12 +332,11 @@ __global__ void __launch_bounds__(64 * kTY * NC) k_sweep_d3q19(const void* fin_v
       float f[19], led = 0.f;
 #pragma unroll
       for (int i = 0; i < 19; ++i) {
-        const bool odd = ((lane - L::cx(i)) & 1) != 0;
-        const float v = staged_value<S>(su[i * kW + lane], i, odd);
+        const float v = __builtin_bit_cast(float, su[i * kW + lane]);
         led = i == 0 ? v : led + v;
-        f[i] = decode<S, 3>(sh, 0, i, v);
+        f[i] = v;
       }
-      sm.rho[rs][c][hrow][lane + 2] = site_density<S, 19>(sh, 0, f, led);
+      sm.rho[rs][c][hrow][lane + 2] = led;
     }
     if (lane < 4) {
       const char* pieces = reinterpret_cast<const char*>(&sm.st[w].piece[0][0]);
@@ -392,11 +346,11 @@ __global__ void __launch_bounds__(64 * kTY * NC) k_sweep_d3q19(const void* fin_v
         float f[19], led = 0.f;
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
-          const float v = piece_value<S>(pieces + pass * kPiecesPerRow * 16, i, xs - L::cx(i));
+          const float v = piece_value(pieces + pass * kPiecesPerRow * 16, i, xs - L::cx(i));
           led = i == 0 ? v : led + v;
-          f[i] = decode<S, 3>(sh, 0, i, v);
+          f[i] = v;
         }
-        sm.rho[rs][c][2 * r + pass][xcol_lds] = site_density<S, 19>(sh, 0, f, led);
+        sm.rho[rs][c][2 * r + pass][xcol_lds] = led;
       }
     }
   };
@@ -477,23 +431,10 @@ __global__ void __launch_bounds__(64 * kTY * NC) k_sweep_d3q19(const void* fin_v
     // non-temporal buffer stores (policy bit nt): the row and run part of
     // each slot's offset in an SGPR, the lane's column part in a VGPR
     const uint32_t row = rowb(y_own, zw, 0, 0);
-    if constexpr (S::kShift) {
-      T rest = led;
 #pragma unroll
-      for (int i = 1; i < 19; ++i) {
-        const _Float16 d = encode_move<3>(sh, 0, i, f[i]);
-        rest -= float(d);
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, d), fout, lp_own.move[1],
-                                              row + B::run(c, i), 2);
-      }
-      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, rest), fout, lp_own.rest, row + B::run(c, 0),
-                                            2);
-    } else {
-#pragma unroll
-      for (int i = 0; i < 19; ++i)
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, f[i]), fout, lp_own.rest,
-                                              row + B::run(c, i), 2);
-    }
+    for (int i = 0; i < 19; ++i)
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, f[i]), fout, lp_own.rest,
+                                            row + B::run(c, i), 2);
   };
 
   // ---- prologue: densities of planes za - 2 .. za + 2 (the last three kept
@@ -581,11 +522,13 @@ static FusedStepFn sweep3_for_n(int n_comp) {
   }
 }
 
-// D3Q19 plane sweep: FP32 or shifted FP16, N <= 3; the caller checks nx % 64
-// == 0, ny % 4 == 0, no walls and a copy below 4 GiB.
+// D3Q19 plane sweep: FP32, N <= 3; the caller checks nx % 64 == 0, ny % 4 ==
+// 0, no walls and a copy below 4 GiB.  The shifted FP16 codec takes the split
+// path: its decode needs the references of the 19 source sites of every
+// unit, halo rows and columns included, which the pencil's registers and
+// LDS (full at N = 3) do not hold.
 FusedStepFn sweep3d_step_for(int storage, int n_comp) {
   if (storage == StoreF32::kId) return sweep3_for_n<StoreF32>(n_comp);
-  if (storage == StoreF16S::kId) return sweep3_for_n<StoreF16S>(n_comp);
   return nullptr;
 }
 

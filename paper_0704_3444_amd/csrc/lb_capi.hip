@@ -139,7 +139,8 @@ size_t population_bytes(const lb_params* p) {
   const size_t nbx = (size_t(p->nx) + 63) / 64;
   const size_t rest = p->storage == LB_F64 ? 8 : 4;
   const size_t move = p->storage == LB_F64 ? 8 : (p->storage == LB_F32 ? 4 : 2);
-  return size_t(p->ny) * size_t(p->nz) * nbx * size_t(p->n_comp) * 64 * (rest + (Q - 1) * move);
+  const size_t ref = p->storage == LB_F16S ? 2 : 0;  // the shifted codec's reference run
+  return size_t(p->ny) * size_t(p->nz) * nbx * size_t(p->n_comp) * 64 * (rest + ref + (Q - 1) * move);
 }
 
 // Bytes of the working precision (FP64 for LB_F64, FP32 otherwise).
@@ -191,36 +192,23 @@ void fill_params(const lb_params* p, lbm::Params<T>* q) {
           T(a < p->n_comp && b < p->n_comp ? p->chi[a * LB_MAX_COMP + b] : 0.0);
 }
 
-// Reference of the shifted FP16 storage from the initial densities:
-// rbar^sigma = mean of rho0^sigma (FP64, rounded once to FP32), s^sigma =
-// the smallest power of two >= max rho0^sigma, and sum_i w_i rbar^sigma
-// with each term rounded to FP32 as the kernels form it.  Zero for the other
-// codecs.
+// Scale of the shifted FP16 storage from the initial densities: s^sigma =
+// twice the smallest power of two >= max rho0^sigma (the pulled totals
+// rho / s then stay below 1, where their FP32 sums are exact, until a density
+// doubles that maximum).  Zero for the other codecs.
 lbm::ShiftRef shift_ref_of(const lb_params* p, const double* rho0, size_t S) {
   lbm::ShiftRef r;
   std::memset(&r, 0, sizeof(r));
   if (p->storage != LB_F16S) return r;
-  double w[19];
-  int32_t Q = 0;
-  lb_lattice_tables(p->lattice, &Q, nullptr, nullptr, w);
   for (int k = 0; k < p->n_comp; ++k) {
-    double sum = 0.0, mx = 0.0;
-    for (size_t i = 0; i < S; ++i) {
-      sum += rho0[k * S + i];
-      mx = std::max(mx, rho0[k * S + i]);
-    }
-    r.rbar[k] = float(sum / double(S));
+    double mx = 0.0;
+    for (size_t i = 0; i < S; ++i) mx = std::max(mx, rho0[k * S + i]);
     int e = 0;
     std::frexp(mx, &e);  // mx = m 2^e with m in [0.5, 1)
     if (std::ldexp(1.0, e - 1) >= mx) e -= 1;  // mx itself a power of two
+    e += 1;
     r.scale[k] = float(std::ldexp(1.0, e));
     r.inv_scale[k] = float(std::ldexp(1.0, -e));
-    double cs = 0.0;
-    for (int i = 0; i < Q; ++i) {
-      const float ci = float(w[i]) * r.rbar[k];
-      cs += double(ci);
-    }
-    r.csum[k] = float(cs);
   }
   return r;
 }
@@ -399,7 +387,7 @@ int init_impl(const lb_params* p, const double* rho0, void* workspace, size_t wo
       c.path = LB_PATH_SWEEP;
       if (!sweep) {
         lb_free(h);
-        return fail(LB_ENOTSUP, "the sweep kernels need D2Q9 or D3Q19 (ny a multiple of 4), FP32 or shifted FP16, N <= 4, nx a multiple of 64 and no walls");
+        return fail(LB_ENOTSUP, "the sweep kernels need D2Q9 (FP32 or shifted FP16, N <= 4) or D3Q19 (FP32, N <= 3, ny a multiple of 4), nx a multiple of 64 and no walls");
       }
       break;
     default:

@@ -73,6 +73,7 @@ __global__ void __launch_bounds__(64) k_lines(const Run<typename S::T>* __restri
   using T = typename S::T;
   using L = Lattice<1>;
   constexpr int Q = 3;
+  static_assert(!S::kShift, "plain codecs only");
   const Run<T>& run = runs[blockIdx.x];
   const Params<T> p = run.p;
   const char* fin = static_cast<const char*>(run.f[par]);
@@ -100,7 +101,10 @@ __global__ void __launch_bounds__(64) k_lines(const Run<typename S::T>* __restri
     for (int k = 0; k < NC; ++k)
 #pragma unroll
       for (int j = 0; j < P; ++j) {
-        rho[k][j] = site_density<S, Q>(p.sh, k, f[k][j], T(0));
+        T acc = T(0);  // the split path's density: the sum in direction order
+#pragma unroll
+        for (int i = 0; i < Q; ++i) acc += f[k][j][i];
+        rho[k][j] = acc;
         bad |= unhealthy(rho[k][j]);
       }
     // neighbour densities rho(x - 1), rho(x + 1)

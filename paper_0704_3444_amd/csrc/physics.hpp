@@ -27,12 +27,11 @@ namespace lbm {
 
 constexpr int kMaxComp = 8;
 
-// Reference of the shifted FP16 storage (unused by the other codecs).
+// Scale of the shifted FP16 storage per component (unused by the other
+// codecs); the references themselves are stored with the populations.
 struct ShiftRef {
-  float rbar[kMaxComp];       // mean density rbar^sigma of each component
   float scale[kMaxComp];      // s^sigma, a power of two
   float inv_scale[kMaxComp];  // 1 / s^sigma
-  float csum[kMaxComp];       // sum_i w_i rbar^sigma, rounded once to FP32
 };
 
 // Arithmetic parameters of one run, in the working precision T.

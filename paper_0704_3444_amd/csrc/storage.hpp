@@ -2,32 +2,44 @@
 // stored slot into a population value and back.
 //
 //   StoreF64, StoreF32  every population in the working precision T.
-//   StoreF16S           moving populations (i > 0) as FP16 deviations from
-//                       the shifted equilibrium w_i rbar^sigma of the mean
-//                       density, scaled by 1/s^sigma (s a power of two);
+//   StoreF16S           per site and component, an FP16 reference h, the
+//                       moving populations (i > 0) as FP16 deviations d_i
+//                       from the shifted equilibrium w_i (36 h s) of that
+//                       reference, in units of s^sigma (a power of two), and
 //                       the rest slot (i = 0) as an FP32 ledger.  All
 //                       arithmetic stays in FP32.
 //
-// Ledger of StoreF16S.  In units of s, every FP16 value is a multiple of
-// 2^-24, and so is the rest slot by construction.  A sum of such numbers is
-// exact in FP32 while its partial sums stay below 1 in magnitude.  A site
-// therefore holds the exact total deviation
-//     L = d_0 + sum_{i>0} d_i,     rho = sum_i C_i + s L,   C_i = w_i rbar,
-// and after the collision writes its moving deviations d*_i (each rounded to
-// FP16) and d*_0 = L - sum_{i>0} d*_i.  The rest slot absorbs all FP16
-// rounding, so every collision keeps the component mass exactly, and
-// streaming moves stored values unchanged.  s is the smallest power of two
-// not below max rho0^sigma, so |L| < 1 holds until a density exceeds
-// rbar + s (beyond that the sums round at 2^-23 s, still far below FP16).
+// Shifted codec.  A slot written at site r decodes, wherever it is read, with
+// the reference of r:  f = s (k_i h(r) + d),  k_i = 36 w_i  (an integer: 16,
+// 4, 1 on D2Q9; 12, 2, 1 on D3Q19; 24, 6 on D1Q3; sum_i k_i = 36).  The
+// collision at r sets h(r) = fl16(rho(r) / (36 s)), so the reference follows
+// the site's own density and the deviations stay small where one component is
+// scarce (a reference shared by a region puts the scarce phase of that region
+// far from it, and FP16's 11 bits then round its populations coarsely).
+//
+// Ledger.  Every FP16 number is a multiple of 2^-24, and so are k_i h and the
+// rest slot by construction.  A sum of such numbers is exact in FP32 while its
+// partial sums stay below 1 in magnitude.  The pulled populations of a site,
+// in units of s,  u_i = k_i h(src_i) + d_i  (u_0 = k_0 h(r) + rest slot),
+// are therefore exact, and so is their sum  T = rho / s.  The collision writes
+// the new reference h', the moving deviations d*_i = fl16(f*_i / s - k_i h')
+// and, in the rest slot,  T - 36 h' - sum_{i>0} d*_i:  the stored total stays
+// T exactly, so every collision keeps the component mass exactly, whatever
+// FP16 rounded, and streaming moves stored values unchanged.  s is twice the
+// smallest power of two not below max rho0^sigma, so the sums stay exact
+// until a density doubles that maximum (beyond, they round at 2^-23 s, still
+// far below FP16's steps).
 //
 // Block layout (all codecs): sites are grouped in blocks of 64 consecutive
 // x on one row (row = y + ny z).  A block stores, for each component, the
-// rest run (64 Rest values) followed by the Q - 1 moving runs (64 Move
-// values each), in the run order run_slot(i).  On D2Q9 the runs are grouped
-// by the y component of the velocity, v_y = 0 (i = 0, 1, 3), +1 (2, 5, 6),
-// -1 (4, 7, 8): the populations that one row pulls from each of its three
-// source rows are then one contiguous piece of that row's block per
-// component.  Other lattices keep the order of the velocity table.
+// rest run (64 Rest values), the Q - 1 moving runs (64 Move values each) in
+// the run order run_slot(i), and for the shifted codec one reference run (64
+// FP16 h values) after the first ref_pos - 1 runs.  On D2Q9 the runs are
+// grouped by the y component of the velocity, v_y = 0 (i = 0, 1, 3, and the
+// references), +1 (2, 5, 6), -1 (4, 7, 8): the populations that one row pulls
+// from each of its three source rows are then one contiguous piece of that
+// row's block per component.  Other lattices keep the order of the velocity
+// table, with the references after the rest run.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -43,6 +55,7 @@ struct StoreF64 {
   using Rest = double;
   using Move = double;
   static constexpr bool kShift = false;
+  static constexpr uint32_t kRef = 0;  // bytes of the reference per site
   static constexpr int kId = 0;
 };
 struct StoreF32 {
@@ -50,6 +63,7 @@ struct StoreF32 {
   using Rest = float;
   using Move = float;
   static constexpr bool kShift = false;
+  static constexpr uint32_t kRef = 0;
   static constexpr int kId = 1;
 };
 struct StoreF16S {
@@ -57,6 +71,7 @@ struct StoreF16S {
   using Rest = float;
   using Move = _Float16;
   static constexpr bool kShift = true;
+  static constexpr uint32_t kRef = 2;
   static constexpr int kId = 2;
 };
 
@@ -71,18 +86,33 @@ __host__ __device__ constexpr int run_slot(int i) {
   }
 }
 
+// Run position before which the reference run sits (shifted codec): after
+// the v_y = 0 group on D2Q9, after the rest run elsewhere.
+template <int Q>
+__host__ __device__ constexpr int ref_pos() {
+  return Q == 9 ? 3 : 1;
+}
+
 template <class S, int Q>
 struct BlockLayout {
   static constexpr uint32_t kRest = sizeof(typename S::Rest);
   static constexpr uint32_t kMove = sizeof(typename S::Move);
+  static constexpr uint32_t kRef = S::kRef;
   // bytes of one component in one block
-  static constexpr uint32_t kComp = kBlockX * (kRest + (Q - 1) * kMove);
+  static constexpr uint32_t kComp = kBlockX * (kRest + kRef + (Q - 1) * kMove);
   // offset of the run of population i of component c inside a block
   static constexpr uint32_t run(int c, int i) {
-    return uint32_t(c) * kComp + (i == 0 ? 0u : kBlockX * (kRest + uint32_t(run_slot<Q>(i) - 1) * kMove));
+    const int j = run_slot<Q>(i);
+    return uint32_t(c) * kComp +
+           (i == 0 ? 0u : kBlockX * (kRest + uint32_t(j - 1) * kMove + (j >= ref_pos<Q>() ? kRef : 0u)));
+  }
+  // offset of the reference run of component c inside a block
+  static constexpr uint32_t ref(int c) {
+    return uint32_t(c) * kComp + kBlockX * (kRest + uint32_t(ref_pos<Q>() - 1) * kMove);
   }
   // offset of site x within its run
   static constexpr uint32_t in_run(int i, int x) { return uint32_t(x & (kBlockX - 1)) * (i == 0 ? kRest : kMove); }
+  static constexpr uint32_t in_ref(int x) { return uint32_t(x & (kBlockX - 1)) * kRef; }
 };
 
 // Byte offset of the block that holds site (x, row), 64-bit.
@@ -97,6 +127,12 @@ __device__ __forceinline__ uint64_t pop_byte(int n, int nbx, int c, int i, int x
   return block_byte<S, Q>(n, nbx, x, row) + BlockLayout<S, Q>::run(c, i) + BlockLayout<S, Q>::in_run(i, x);
 }
 
+// Byte offset of the reference of component c at site (x, row) (shifted codec).
+template <class S, int Q>
+__device__ __forceinline__ uint64_t ref_byte(int n, int nbx, int c, int x, long long row) {
+  return block_byte<S, Q>(n, nbx, x, row) + BlockLayout<S, Q>::ref(c) + BlockLayout<S, Q>::in_ref(x);
+}
+
 // Raw slot value converted to the working precision (exact for every codec).
 template <class S>
 __device__ __forceinline__ typename S::T load_slot(const void* base, uint64_t off, int i) {
@@ -105,56 +141,92 @@ __device__ __forceinline__ typename S::T load_slot(const void* base, uint64_t of
   return typename S::T(*reinterpret_cast<const typename S::Move*>(b));
 }
 
-// Shifted equilibrium C_i = w_i rbar^sigma in FP32 (one rounding).
-template <int LAT>
-__device__ __forceinline__ float shift_ref(const ShiftRef& r, int c, int i) {
-#pragma clang fp contract(off)
-  return float(Lattice<LAT>::w(i)) * r.rbar[c];
+// Reference h at a byte offset, as FP32 (exact).
+__device__ __forceinline__ float load_ref(const void* base, uint64_t off) {
+  return float(*reinterpret_cast<const _Float16*>(static_cast<const char*>(base) + off));
 }
 
-// Population value from a raw slot value in the working precision: for the
-// shifted codec, f = C_i + s d (one FP32 rounding).
+// k_i = 36 w_i, the multiple of the reference in the shifted equilibrium of
+// direction i (an integer for every velocity set here).
+template <int LAT>
+__host__ __device__ constexpr float ref_weight(int i) {
+  return float(int(36.0 * Lattice<LAT>::w(i) + 0.5));
+}
+
+template <int LAT>
+constexpr bool ref_weights_exact() {
+  int sum = 0;
+  for (int i = 0; i < Lattice<LAT>::Q; ++i) {
+    const double k = 36.0 * Lattice<LAT>::w(i);
+    if (k - double(ref_weight<LAT>(i)) > 1e-12 || double(ref_weight<LAT>(i)) - k > 1e-12) return false;
+    sum += int(ref_weight<LAT>(i));
+  }
+  return sum == 36;
+}
+static_assert(ref_weights_exact<1>() && ref_weights_exact<2>() && ref_weights_exact<3>(), "36 w_i integral");
+
+// Take pulled slot i (raw value in the working precision; h the reference of
+// the site that wrote it, shifted codec only) into the population value f
+// and the site's running sum: the shifted codec sums u_i = k_i h + d in
+// units of s (exact) and returns f = s u_i; the plain codecs return the value
+// and sum it in direction order.
 template <class S, int LAT>
-__device__ __forceinline__ typename S::T decode(const ShiftRef& r, int c, int i, typename S::T raw) {
+__device__ __forceinline__ void take_slot(int i, typename S::T raw, float h, float scale, typename S::T& sum,
+                                          typename S::T& f) {
   if constexpr (S::kShift) {
-    return __builtin_fmaf(raw, r.scale[c], shift_ref<LAT>(r, c, i));
+    const float u = __builtin_fmaf(ref_weight<LAT>(i), h, raw);
+    sum = i == 0 ? u : sum + u;
+    f = u * scale;
   } else {
-    return raw;
+    sum = i == 0 ? raw : sum + raw;
+    f = raw;
   }
 }
 
-// The same value, exactly, in FP64 (C_i is an FP32 number and s d has at
-// most 24 significant bits, so the sum needs no rounding in FP64).
+// The same population exactly in FP64 (k_i h + d is exact in FP32 already;
+// the power-of-two scale keeps it exact).
 template <class S, int LAT>
-__device__ __forceinline__ double decode_exact(const ShiftRef& r, int c, int i, typename S::T raw) {
+__device__ __forceinline__ double take_exact(int i, typename S::T raw, float h, float scale) {
   if constexpr (S::kShift) {
-    return double(shift_ref<LAT>(r, c, i)) + double(raw) * double(r.scale[c]);
+    return double(scale) * (double(ref_weight<LAT>(i)) * double(h) + double(raw));
   } else {
     return double(raw);
   }
 }
 
-// Component density of one site from its decoded populations (plain codecs:
-// the sum in direction order) or from its ledger (shifted codec).
-template <class S, int Q>
-__device__ __forceinline__ typename S::T site_density(const ShiftRef& r, int c, const typename S::T (&f)[Q],
-                                                      typename S::T ledger) {
-  using T = typename S::T;
+// Component density of one site from the running sum of take_slot: the
+// direction-order sum itself (plain codecs) or s T (shifted codec, exact).
+template <class S>
+__device__ __forceinline__ typename S::T site_density(typename S::T sum, float scale) {
   if constexpr (S::kShift) {
-    return __builtin_fmaf(ledger, r.scale[c], r.csum[c]);
+    return sum * scale;
   } else {
-    T acc = T(0);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) acc += f[i];
-    return acc;
+    return sum;
   }
 }
 
-// Moving deviation d*_i of a post-collision value (shifted codec).
-template <int LAT>
-__device__ __forceinline__ _Float16 encode_move(const ShiftRef& r, int c, int i, float post) {
+// New reference of a site from its pulled total T = rho / s (shifted codec).
+__device__ __forceinline__ _Float16 new_ref(float sum) {
 #pragma clang fp contract(off)
-  return _Float16((post - shift_ref<LAT>(r, c, i)) * r.inv_scale[c]);
+  return _Float16(sum * (1.0f / 36.0f));
+}
+
+// Moving deviation d*_i of a post-collision value against the site's new
+// reference h' (shifted codec): fl16(f*_i / s - k_i h'), with f*_i / s exact.
+template <int LAT>
+__device__ __forceinline__ _Float16 encode_move(int i, float post, float inv_scale, float h) {
+  return _Float16(__builtin_fmaf(post, inv_scale, -(ref_weight<LAT>(i) * h)));
+}
+
+// Rest slot that keeps the stored total at T: T - 36 h' - sum_{i>0} d*_i,
+// each step exact.  `d` holds the stored moving deviations (index 0 unused).
+template <int Q>
+__device__ __forceinline__ float ledger_rest(float sum, float h, const float (&d)[Q]) {
+#pragma clang fp contract(off)
+  float rest = sum - 36.0f * h;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) rest -= d[i];
+  return rest;
 }
 
 }  // namespace lbm

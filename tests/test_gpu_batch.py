@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import lbinputs as LI
-from gpu_helpers import TOL, run_gpu, run_oracle
+from gpu_helpers import TOL, run_gpu, run_oracle, run_oracle_f16s_budget
 
 pytestmark = pytest.mark.gpu
 
@@ -200,12 +200,12 @@ def test_batch_rejects_what_it_cannot_run():
     b.close()
 
 
-@pytest.mark.parametrize("storage,tol", [("f32", TOL["f32"]), ("f16s", 1e-4)])
+@pytest.mark.parametrize("storage,tol", [("f32", TOL["f32"]), ("f16s", None)])
 def test_serving_loop_each_result_same_alone_and_in_mix(storage, tol):
     """Continuous batching of a Poisson mix: every request completes, and
     its densities equal the same run alone (bit for bit) and the oracle
-    within the storage's bar (shifted FP16: these near-uniform mixtures stay
-    within 1e-4 over 150 steps)."""
+    within the storage's bar (shifted FP16: the rounding budget of the run,
+    f16s_check)."""
     from paper_0704_3444_amd import serve
 
     reqs = LI.serving_mix(12, seed=77, rate_hz=400.0, side=(64, 160), steps=150)
@@ -220,6 +220,13 @@ def test_serving_loop_each_result_same_alone_and_in_mix(storage, tol):
         alone = solo(r["cfg"], r["rho0"], r["nsteps"], storage, "auto")
         assert np.array_equal(rec["rho"], alone["rho"]), r["id"]
     r = reqs[0]
+    if storage == "f16s":
+        o, budget = run_oracle_f16s_budget(r["cfg"], r["rho0"], r["nsteps"])
+        d = (np.abs(by_id[r["id"]]["rho"] - o["rho"]) / o["rho"]).max(axis=1)
+        ratio = float(np.max(d / (budget["rel"] + 1e-5)))
+        print(f"[serve] f16s request {r['id']} density error / rounding bar {ratio:.3f}", flush=True)
+        assert ratio < 1.0, ratio
+        return
     o = run_oracle(r["cfg"], r["rho0"], r["nsteps"])
     err = float(np.max(np.abs(by_id[r["id"]]["rho"] - o["rho"]) / o["rho"]))
     print(f"[serve] {storage} request {r['id']} vs oracle {err:.2e}", flush=True)

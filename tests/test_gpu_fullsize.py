@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import lbinputs as LI
+from gpu_helpers import run_oracle_f16s_budget
 from oracle import Oracle, OracleParams
 
 pytestmark = pytest.mark.gpu
@@ -28,17 +29,25 @@ def sample_sites(nx, ny, seed=5):
     return fixed + rnd
 
 
-def window_oracle(cfg, rho0, nx, ny, x, y, steps):
+def window_oracle(cfg, rho0, nx, ny, x, y, steps, budget=False):
+    """The oracle on the periodic window around (x, y): rho, mu and U at the
+    centre, and with budget=True the shifted FP16 rounding budget of the
+    window's run (its density bounds hold at every site of the window, the
+    centre included)."""
     R = 3 * steps + 4
     W = 2 * R + 1
     xs = np.arange(x - R, x + R + 1) % nx
     ys = np.arange(y - R, y + R + 1) % ny
     n = cfg["n_comp"]
-    g = rho0.reshape(n, ny, nx)[:, ys][:, :, xs].reshape(n, -1)
-    o = Oracle(OracleParams(**dict(cfg, shape=(W, W))), np.ascontiguousarray(g))
+    g = np.ascontiguousarray(rho0.reshape(n, ny, nx)[:, ys][:, :, xs].reshape(n, -1))
+    c = R * W + R
+    wcfg = dict(cfg, shape=(W, W))
+    if budget:
+        ob, b = run_oracle_f16s_budget(wcfg, g, steps)
+        return ob["rho"][:, c], ob["mu"][:, c], ob["U"][:, c], b, ob
+    o = Oracle(OracleParams(**wcfg), g)
     o.step(steps)
     ob = o.observe()
-    c = R * W + R
     return ob["rho"][:, c], ob["mu"][:, c], ob["U"][:, c]
 
 
@@ -47,8 +56,12 @@ def workload():
     return LI.ternary_immersion(N_FULL)
 
 
-@pytest.mark.parametrize("storage,tol", [("f32", 1e-5), ("f64", 1e-12), ("f16s", 2e-2)])
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-5), ("f64", 1e-12), ("f16s", None)])
 def test_fullsize_sampled_sites_match_oracle(workload, storage, tol):
+    """FP64 and FP32 at their relative bars; shifted FP16 against the rounding
+    budget of the window's run (densities relative per site, mu through its
+    first-order sensitivity, both plus the FP32 arithmetic's 1e-5; U is
+    checked on the same state in the parity tests)."""
     from paper_0704_3444_amd import Simulation
 
     cfg, rho0 = workload
@@ -59,6 +72,23 @@ def test_fullsize_sampled_sites_match_oracle(workload, storage, tol):
     out = sim.moments()
     sim.close()
     cs = 1 / np.sqrt(3)
+    if storage == "f16s":
+        worst = {"rho": 0.0, "mu": 0.0}
+        for (x, y) in sample_sites(N_FULL, N_FULL):
+            r, mu, _, b, ob = window_oracle(cfg, rho0, N_FULL, N_FULL, x, y, K, budget=True)
+            s = y * N_FULL + x
+            bb = b["rel"] + 1e-5
+            worst["rho"] = max(worst["rho"], float(np.max(np.abs(out["rho"][:, s] - r) / r / bb)))
+            n = cfg["n_comp"]
+            chi = np.abs(np.asarray(cfg["chi"], float)[:n, :n])
+            rmax = ob["rho"].max(axis=1)
+            bar = cfg["theta"] / np.asarray(cfg["m"][:n]) * bb + chi @ (bb * rmax) + 12.0 * cfg["kappa"] * bb * rmax
+            bar = bar + 1e-5 * float(np.abs(ob["mu"]).max())
+            worst["mu"] = max(worst["mu"], float(np.max(np.abs(out["mu"][:, s] - mu) / bar)))
+        print(f"[fullsize] f16s worst error / rounding bar {worst}", flush=True)
+        for k, v in worst.items():
+            assert v < 1.0, (k, worst)
+        return
     worst = {"rho": 0.0, "mu": 0.0, "U": 0.0}
     for (x, y) in sample_sites(N_FULL, N_FULL):
         r, mu, U = window_oracle(cfg, rho0, N_FULL, N_FULL, x, y, K)

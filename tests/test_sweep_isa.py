@@ -3,11 +3,12 @@
 The sweep kernel stages rows into LDS with direct global-to-LDS loads and
 waits for them with explicit ``s_waitcnt vmcnt(N)``: one counter covers
 loads and stores and retires them in issue order, and every round issues its
-9 N stores after its staging loads, so the next round waits until at most
-9 N operations remain in flight.  That is exact only if
+K stores after its staging loads (K = 9 N for FP32; 10 N for shifted FP16,
+whose rows also store the sites' references), so the next round waits until
+at most K operations remain in flight.  That is exact only if
 
-* every round's stores are exactly 9 N store instructions (none merged or
-  split), and every explicit wait is vmcnt(0) or vmcnt(9 N);
+* every round's stores are exactly K store instructions (none merged into a
+  wider store or split), and every explicit wait is vmcnt(0) or vmcnt(K);
 * the compiler adds no vmcnt wait of its own once staging has started (such
   a wait would also wait for the stores left in flight).
 
@@ -53,20 +54,99 @@ def test_every_instantiation_present(asm):
     assert found == {(s, n) for s in ("StoreF32", "StoreF16S") for n in (1, 2, 3, 4)}
 
 
-def test_stores_come_in_rounds_of_nine_n(asm):
+def stores_per_row(store, nc):
+    return (10 if store == "StoreF16S" else 9) * nc
+
+
+def blocks_of(lines):
+    """Basic blocks of a kernel's assembly: (label, first, last) line ranges
+    and the predecessors of each block."""
+    label = re.compile(r"^(\.LBB\w+):")
+    starts = [0]
+    for i, l in enumerate(lines):
+        t = l.strip()
+        if label.match(t) and i not in starts:
+            starts.append(i)
+        elif t.startswith(("s_branch", "s_cbranch", "s_endpgm")) and i + 1 < len(lines):
+            starts.append(i + 1)
+    starts = sorted(set(starts))
+    blocks = []
+    for k, a in enumerate(starts):
+        b = starts[k + 1] - 1 if k + 1 < len(starts) else len(lines) - 1
+        m = label.match(lines[a].strip())
+        blocks.append((m.group(1) if m else None, a, b))
+    index = {lab: k for k, (lab, _, _) in enumerate(blocks) if lab}
+    preds = [[] for _ in blocks]
+    for k, (_, a, b) in enumerate(blocks):
+        body = [lines[i].strip() for i in range(a, b + 1) if lines[i].strip() and not lines[i].strip().startswith(";")]
+        last = body[-1] if body else ""
+        if last.startswith(("s_branch", "s_cbranch")):
+            target = last.split()[1]
+            if target in index:
+                preds[index[target]].append(k)
+        if not last.startswith(("s_branch", "s_endpgm")) and k + 1 < len(blocks):
+            preds[k + 1].append(k)
+    return blocks, preds
+
+
+def stores_since_last_load(lines, blocks, preds, at):
+    """Numbers of store instructions on the paths from the nearest vector
+    memory load back before line `at` to `at`, over every control path (a
+    path that reaches an earlier vmcnt wait first stages nothing and is not
+    counted)."""
+    is_store = lambda t: t.startswith(("global_store", "buffer_store", "flat_store"))
+    is_load = lambda t: t.startswith(("global_load", "buffer_load", "flat_load"))
+    home = next(k for k, (_, a, b) in enumerate(blocks) if a <= at <= b)
+    found, todo, seen = set(), [(home, at - 1, 0)], set()
+    while todo:
+        k, i, n = todo.pop()
+        a = blocks[k][1]
+        hit = False
+        while i >= a:
+            t = lines[i].strip()
+            if is_load(t):
+                found.add(n)
+                hit = True
+                break
+            if "vmcnt" in t and "s_waitcnt" in t:
+                # an earlier wait with no staging load after it: this path
+                # stages nothing for the wait at `at` to protect
+                hit = True
+                break
+            if is_store(t):
+                n += 1
+            i -= 1
+        if hit:
+            continue
+        for q in preds[k]:
+            if (q, n) not in seen:
+                assert len(seen) < 100000, "a cycle without loads"
+                seen.add((q, n))
+                todo.append((q, blocks[q][2], n))
+    return found
+
+
+def test_stores_come_in_rounds_of_k(asm):
+    """On every control path into an explicit vmcnt(K) wait, exactly K stores
+    follow the last staging load (each slot its own store instruction: none
+    merged, none split), so that the wait lets only those stores stay in
+    flight; every store is a dword (FP32 slots, the rest slot) or a short
+    (FP16 moving slots and references)."""
+    checked = 0
     for store, nc, lines in kernels(asm):
-        groups, cur = [], 0
-        for line in lines:
-            t = line.strip()
-            if t.startswith(("global_store", "buffer_store", "flat_store")):
-                cur += 1
-            elif t.startswith(("global_", "buffer_", "flat_")) or ("s_waitcnt" in t and "vmcnt" in t):
-                if cur:
-                    groups.append(cur)
-                cur = 0
-        if cur:
-            groups.append(cur)
-        assert groups and all(g == 9 * nc for g in groups), (store, nc, groups)
+        k = stores_per_row(store, nc)
+        widths = {l.strip().split()[0] for l in lines
+                  if l.strip().startswith(("global_store", "buffer_store", "flat_store"))}
+        allowed = {"global_store_dword", "global_store_short"} if store == "StoreF16S" else {"global_store_dword"}
+        assert widths and widths <= allowed, (store, nc, widths)
+        blocks, preds = blocks_of(lines)
+        for i, line in enumerate(lines):
+            m = re.search(r"s_waitcnt\s.*vmcnt\((\d+)\)", line)
+            if m and "ASMSTART" in lines[i - 1] and int(m.group(1)) == k:
+                counts = stores_since_last_load(lines, blocks, preds, i)
+                assert counts == {k}, (store, nc, i, counts)
+                checked += 1
+    assert checked > 0
 
 
 def test_waits_after_staging_are_the_explicit_ones(asm):
@@ -80,7 +160,7 @@ def test_waits_after_staging_are_the_explicit_ones(asm):
             if i > first_dma:
                 assert explicit, (store, nc, i, line.strip())
             if explicit:
-                assert int(m.group(1)) in (0, 9 * nc), (store, nc, line.strip())
+                assert int(m.group(1)) in (0, stores_per_row(store, nc)), (store, nc, line.strip())
 
 
 TILE_KERNEL = re.compile(r"^(_ZN3lbm12k_(fused|batch)_d2q9INS_\d+(Store\w+?)ELi(\d)E\w*):", re.M)
@@ -121,3 +201,12 @@ def test_tile_kernel_loads_are_not_serialised(tile_asm):
         serial = [j for j, l in enumerate(lines) if l.startswith("global_load")
                   and any(lines[j + d].startswith("s_waitcnt vmcnt(0)") for d in (1, 2) if j + d < len(lines))]
         assert len(serial) <= 8, (m.group(1), len(serial))
+
+
+def test_sweep_kernels_inline_everything(asm):
+    """The rounds' helpers must be inlined: a call passes their arrays through
+    scratch memory, whose loads and stores are vector memory operations that
+    the explicit vmcnt waits do not count."""
+    for store, nc, lines in kernels(asm):
+        body = "\n".join(lines)
+        assert "s_swappc" not in body and "scratch_" not in body, (store, nc)
