@@ -158,16 +158,27 @@ def _source_sites(cfg, vi):
     return np.where(beyond, own, pulled).reshape(-1)
 
 
-def run_oracle_f16s_budget(cfg, rho0, steps):
+def run_oracle_f16s_budget(cfg, rho0, steps, focus=None, scale=None):
     """The oracle's run (as run_oracle) and the FP16 rounding budget along it:
     {"rel": [N] bound on |d rho^s| / rho^s per site and component, "mom": [D]
-    absolute bound on the total first moment per axis, "scale": s^sigma}."""
+    absolute bound on the total first moment per axis, "scale": s^sigma}.
+    focus = (x, y): the density bound of that site alone, whose state after
+    `steps` steps depends only on sites within 3 (steps - t) + 1 of it at
+    step t (a periodic window's wrapped rim stays outside).  scale: s^sigma
+    of the run being bounded when rho0 is only a window of its input (s
+    follows the whole input's maximum)."""
     from oracle.oracle import lattice_tables
 
     N = cfg["n_comp"]
     q, D, v, w = lattice_tables(cfg["lattice"])
     srcs = [_source_sites(cfg, v[i]) for i in range(q)]
-    s = f16s_scale(rho0)
+    s = f16s_scale(rho0) if scale is None else np.asarray(scale, float)
+    cone = None
+    if focus is not None:
+        dims = list(cfg["shape"]) + [1] * (3 - len(cfg["shape"]))
+        z, y, x = np.meshgrid(*(np.arange(n) for n in dims[::-1]), indexing="ij")
+        dist = np.maximum(np.abs(x - focus[0]), np.abs(y - focus[1])).reshape(-1)
+        cone = lambda t: dist <= 3 * (steps - t) + 1
     o = Oracle(OracleParams(**cfg), rho0)
     f = o.get_f()
     rho_prev = rho0
@@ -187,7 +198,8 @@ def run_oracle_f16s_budget(cfg, rho0, steps):
             tot = float(err.sum())
             for a in range(D):
                 b_mom[a] += abs(int(v[i][a])) * tot
-        b_rel += (inj / np.abs(f.sum(axis=1))).max(axis=1)
+        rel = inj / np.abs(f.sum(axis=1))
+        b_rel += (rel if cone is None else rel[:, cone(t)]).max(axis=1)
     out = o.observe()
     out["f"] = o.get_f()
     return out, {"rel": b_rel, "mom": b_mom, "scale": s}

@@ -10,16 +10,25 @@ read off them are compared with the Flory-Huggins binodal of Eq. (lgf)
 (common tangent, or equal chemical potentials plus the lever rule through
 the run's mean composition) and printed as a table.  The scheme's own
 coexistence differs from that binodal by an amount that grows with the
-quench (a few 1e-3 next to the critical point, up to 0.08 at the deepest
-stable quench); the assertions are the properties that hold under this
-implementation's readings of the paper:
+quench.  A CPU study of the oracle over the readings the paper leaves open
+(force line of Eq. (definef) x theta x gradient stencil) found no reading
+that removes this (the smallest deviations at chi = 2.4 are 0.025 to 0.04);
+the reading used here (log line, theta = 1/3, nearest-neighbour stencil)
+is the one stable over the widest range of quenches.  The assertions are
+the bars that study measured for it:
 
 * a run that goes unstable is flagged, never silently kept;
 * healthy runs conserve every component's mass;
 * the symmetric monomer mixture separates into mirror-image phases, the
-  separation grows with chi, and next to the critical point the phases
-  approach the binodal;
-* every stable run stays within 0.1 of the binodal."""
+  separation grows with chi;
+* binary monomer: |deviation| <= 0.17 (chi - 2) + 0.002 (the study's
+  slopes: 0.145 at 1/tau = 0.7, 0.11 at 0.9), below 1e-3 at chi = 2.05 for
+  1/tau = 0.9 and below 2.5e-3 for 1/tau = 0.7, and the two relaxation
+  times differ by at most 0.05 (chi - 2) + 0.002;
+* binary polymer: the polymer-poor phase within 6 (chi - chi_c)^2 + 0.005
+  of the binodal, the polymer-rich one within 0.01, stable up to chi = 0.94;
+* ternary: within 0.1 s + 0.01 of the tie line, s the distance of the start
+  from the critical point."""
 import json
 import os
 
@@ -75,6 +84,7 @@ def test_binary_monomer_binodal_sweep():
     runs = LI.binodal_runs("binary_monomer")
     res = gpu_sweep(runs, 200000, 50000)
     oracle_parity(runs, res, [6, 37], 50000)
+    dev = {}
     for inv_tau in (0.7, 0.9):
         last = 0.5
         stable = []
@@ -95,11 +105,19 @@ def test_binary_monomer_binodal_sweep():
             assert abs(ph["rich"][0] - ph["poor"][1]) < 3 * ph["spread"] + 1e-5
             assert poor < last + 1e-9
             last = poor
-            assert abs(poor - lo) < 0.1 and abs(rich - hi) < 0.1, label
+            bar = 0.17 * (chi - 2.0) + 0.002
+            assert abs(poor - lo) < bar and abs(rich - hi) < bar, (label, bar)
             if chi < 2.06:
-                assert abs(poor - lo) < 5e-3, label
+                assert abs(poor - lo) < (1e-3 if inv_tau == 0.9 else 2.5e-3), label
+            dev[(inv_tau, round(chi, 3))] = poor - lo
         # every quench up to 1.3 chi_c is stable at both relaxation times
         assert min(stable) < 2.06 and max(stable) > 2.59 and len(stable) >= 12, stable
+    # Sec. IV: only a slight dependence on the relaxation time
+    for (it, chi), d in dev.items():
+        if it == 0.7 and (0.9, chi) in dev:
+            gap = abs(d - dev[(0.9, chi)])
+            print(f"[replication] E1 chi={chi:.2f}: 1/tau 0.7 vs 0.9 differ by {gap:.4f}", flush=True)
+            assert gap < 0.05 * (chi - 2.0) + 0.002, (chi, gap)
 
 
 def test_binary_polymer_binodal_sweep():
@@ -120,8 +138,10 @@ def test_binary_polymer_binodal_sweep():
         stable += 1
         print(f"[replication] E2 {label}: LB {ph['poor'][0]:.5f} / {ph['rich'][0]:.5f}  binodal {lo:.5f} / {hi:.5f}  "
               f"plateau spread {ph['spread']:.1e}", flush=True)
-        assert abs(ph["poor"][0] - lo) < 0.1 and abs(ph["rich"][0] - hi) < 0.1, label
-    assert stable >= 3
+        chi_c = T.binary_critical(10, 1)[1]
+        assert abs(ph["poor"][0] - lo) < 6.0 * (chi - chi_c) ** 2 + 0.005, label
+        assert abs(ph["rich"][0] - hi) < 0.01, label
+    assert stable >= 4
 
 
 @pytest.mark.parametrize("experiment", ["ternary_monomer", "ternary_polymer", "ternary_monomer_plait",
@@ -156,7 +176,8 @@ def test_ternary_binodal_sweep(experiment):
         print(f"[replication] {experiment} {label}: LB {np.round(ph['rich'], 4)} | {np.round(ph['poor'], 4)}  "
               f"theory {np.round(pa, 4)} | {np.round(pb, 4)}  max deviation {d:.4f}  "
               f"plateau spread {ph['spread']:.1e}", flush=True)
-        assert d < 0.1, (label, d)
+        dist = float(label.split("=")[1])
+        assert d < 0.1 * dist + 0.01, (label, d)
         if ph["spread"] < 1e-3 and float(label.split("=")[1]) <= 0.25:
             near.append(d)
     if experiment == "ternary_monomer":
@@ -202,6 +223,15 @@ def test_polymer_profiles():
               f"{GOLD['fig2_muA_bulk_difference']:.0e}, {GOLD['fig2_muA_interface_variation']:.0e}; "
               f"< {GOLD['fig2_muB_bulk_below']:.0e}, {GOLD['fig2_muB_interface_variation']:.0e})", flush=True)
         assert st["mu0_range"] > st["mu1_range"] and st["drho_range"] < 1e-2
+        if label == "theta=1/3":
+            # the paper's order of magnitude holds for mu^A (bulk and across
+            # the interface); the bulk density contrast and mu^B's bulk gap
+            # are the reading study's (1.4e-3 and 5.6e-4 at 500 000 steps,
+            # against the paper's < 1e-5 and < 1e-4; no reading studied
+            # reaches both while keeping Fig. 1's quenches stable)
+            for k, g in (("mu0_bulk", "fig2_muA_bulk_difference"), ("mu0_range", "fig2_muA_interface_variation")):
+                assert 0.1 * GOLD[g] < st[k] < 10 * GOLD[g], (k, st[k], GOLD[g])
+            assert st["drho_bulk"] < 2e-3 and st["mu1_bulk"] < 1e-3, st
     cfg3, rho3 = LI.profile_run("ternary_polymer_profile")
     r3 = phase.run_lines([(cfg3, rho3, "")], 200000)[0]
     if not r3["healthy"]:
