@@ -311,7 +311,10 @@ def run_batch_only(n_req, steps, warmup, storage):
     from paper_0704_3444_amd import lb
 
     reqs = LI.serving_mix(256)[:n_req]
-    batch = lb.Batch(storage=storage, max_comp=3, max_slots=n_req, arena_bytes=8 << 30, graph_steps=50)
+    st = torch.cuda.current_stream()
+    # the batch steps on the stream the events are recorded on
+    batch = lb.Batch(storage=storage, max_comp=3, max_slots=n_req, arena_bytes=8 << 30, graph_steps=50,
+                     stream=st.cuda_stream)
     alg = 0
     try:
         for r in reqs:
@@ -320,7 +323,6 @@ def run_batch_only(n_req, steps, warmup, storage):
         batch.step(warmup)
         torch.cuda.synchronize()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        st = torch.cuda.current_stream()
         a.record(st)
         batch.step(steps)
         b.record(st)
