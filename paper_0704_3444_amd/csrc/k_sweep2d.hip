@@ -65,83 +65,126 @@ __device__ __forceinline__ void wait_vm() {
 // for its global loads in flight.
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
-// Staged row: per component the runs of the pulled populations in the
-// block's run order (v_y groups 0 | +1 | -1, each from its source row; group
-// 0 holds the row's own references in the shifted codec); for the shifted
-// codec the reference runs of the rows above and below (component c, row
-// above: kHRowOff + 256 c, row below: + 128); then the halo pieces: for
-// each run (c, i), from the same source row, the last 16 bytes of the left
-// neighbour block's run (columns x0 - 16/e .. x0 - 1, e the slot size) and
-// the first 16 bytes of the right neighbour block's run (columns x0 + 64 ..
-// x0 + 63 + 16/e), piece (c, i, side) at kHaloOff + 16 ((9 c + i) 2 + side);
-// for the shifted codec the same two pieces of the reference runs of the
-// three source rows (hr = 0: the row, 1: above, 2: below) at kHaloOff +
-// 16 (18 NC + (3 c + hr) 2 + side).
+// Staged row: every run that a row pulls, in LDS as one padded segment
+// [16 bytes of the left neighbour block's run | the 64 slots of the row's
+// own block column | 16 bytes of the right neighbour block's run], so that
+// column col (-16/e .. 63 + 16/e, e the slot size) of the run sits at
+// segment + 16 + col e and the edge lanes need no selects.  Segments are
+// grouped by source row (v_y = 0: the row itself; +1: the row above; -1:
+// the row below), and within a group by component, in the block's run order:
+// v_y = 0 holds runs 0, 1, 3, v_y = +1 runs 2, 5, 6, v_y = -1 runs 4, 7, 8;
+// for the shifted codec each group also holds the reference run of its
+// source row (after the component's runs).  The staged row is filled by
+// kLoads direct loads of 16 bytes per lane over its consecutive 16-byte
+// chunks, every lane active: the lanes beyond the last chunk read a valid
+// address and write into the padding after it.  (With the last loads issued
+// only by the lanes that have a chunk, the compiler had merged a partial
+// load with the next one under divergent control flow and taken one lane's
+// LDS destination for both.)  Only a load that straddles two groups selects
+// its row part per lane.
 template <class S, int NC>
 struct Staged {
   using B = BlockLayout<S, 9>;
-  static constexpr uint32_t kGroup0 = kW * (B::kRest + 2 * B::kMove + B::kRef);  // v_y = 0: i = 0, 1, 3 (+ h)
-  static constexpr uint32_t kGroup1 = kW * 3 * B::kMove;                         // v_y = +-1: 2, 5, 6 / 4, 7, 8
-  static constexpr uint32_t kMain = NC * B::kComp;
-  static constexpr uint32_t kHRowOff = kMain;
-  static constexpr uint32_t kHRows = S::kShift ? NC * 2 * kW * B::kRef : 0;
-  static constexpr int kRunPieces = 18 * NC;
-  static constexpr int kPieces = kRunPieces + (S::kShift ? 6 * NC : 0);
-  static constexpr int kHaloLoads = (kPieces + 63) / 64;
-  static constexpr uint32_t kHaloOff = kHRowOff + kHRows;
-  static constexpr uint32_t kBytes = kHaloOff + 16 * kPieces;
-  static constexpr int kLoads = 3 * NC + (S::kShift ? 1 : 0) + kHaloLoads;  // direct loads per staged row
-  static constexpr int kStores = (S::kShift ? 10 : 9) * NC;                // stores per collided row
-  static_assert(kGroup0 % 16 == 0 && kGroup1 % 16 == 0 && kGroup0 <= 1024 && kGroup1 <= 1024, "group size");
-  static_assert(kMain % 16 == 0 && kHaloOff % 16 == 0, "pieces aligned");
-  static_assert(!S::kShift || 2 * NC * kW * B::kRef <= 64 * 16, "reference rows in one load");
+  using L = Lattice<2>;
+  static constexpr int kRunsPerGroup = S::kShift ? 4 : 3;  // three runs (+ the reference run)
+  // velocity of run k of group g (k == 3: the reference run)
+  static constexpr int vel(int g, int k) {
+    constexpr int v[3][3] = {{0, 1, 3}, {2, 5, 6}, {4, 7, 8}};
+    return v[g][k];
+  }
+  static constexpr uint32_t elem(int g, int k) { return k == 3 ? B::kRef : (vel(g, k) == 0 ? B::kRest : B::kMove); }
+  static constexpr uint32_t seg_bytes(int g, int k) { return 32u + uint32_t(kW) * elem(g, k); }
+  static constexpr uint32_t comp_bytes(int g) {
+    uint32_t n = 0;
+    for (int k = 0; k < kRunsPerGroup; ++k) n += seg_bytes(g, k);
+    return n;
+  }
+  static constexpr uint32_t group_bytes(int g) { return NC * comp_bytes(g); }
+  static constexpr uint32_t group_off(int g) { return g == 0 ? 0u : (g == 1 ? group_bytes(0) : group_bytes(0) + group_bytes(1)); }
+  // LDS byte offset of segment (g, c, k)
+  static constexpr uint32_t seg(int g, int c, int k) {
+    uint32_t o = group_off(g) + uint32_t(c) * comp_bytes(g);
+    for (int q = 0; q < k; ++q) o += seg_bytes(g, q);
+    return o;
+  }
+  static constexpr int group_of(int i) { return L::cy(i) == 0 ? 0 : (L::cy(i) > 0 ? 1 : 2); }
+  static constexpr int slot_of(int i) {
+    const int g = group_of(i);
+    return vel(g, 0) == i ? 0 : (vel(g, 1) == i ? 1 : 2);
+  }
+  // LDS byte offset of column 0 of run i of component c, of the reference run
+  // of component c in the source row dy
+  static constexpr uint32_t run0(int c, int i) { return seg(group_of(i), c, slot_of(i)) + 16u; }
+  static constexpr uint32_t ref0(int c, int dy) { return seg(dy == 0 ? 0 : (dy > 0 ? 1 : 2), c, 3) + 16u; }
+  static constexpr int chunks(int g) { return int(group_bytes(g) / 16); }
+  static constexpr int kChunks = chunks(0) + chunks(1) + chunks(2);
+  static constexpr int kLoads = (kChunks + 63) / 64;  // direct loads per staged row
+  static constexpr uint32_t kBytes = 1024u * uint32_t(kLoads);  // chunks and padding
+  static constexpr int kStores = (S::kShift ? 10 : 9) * NC;  // stores per collided row
+  static_assert(group_bytes(0) % 16 == 0 && group_bytes(1) % 16 == 0, "segments aligned");
   static_assert(kStores < 64, "vmcnt range");
 };
 
-
-// Per-lane parts of the halo pieces that do not change along the sweep:
-// the column part of the piece's byte offset and which source row (v_y =
-// +1: the row above, 0: the row itself, -1: the row below) it comes from.
+// Per-lane column parts of the staging loads, which do not change along the
+// sweep: load j reads, in lane l, chunk 64 j + l of the staged row: the byte
+// offset, less the row part, of that 16-byte chunk in the left neighbour
+// block, the strip's own block or the right neighbour block (lanes past the
+// last chunk: the strip's own block).
 template <class S, int NC>
 struct Gather {
-  static constexpr int kN = Staged<S, NC>::kHaloLoads;
-  uint32_t col[kN];
-  int dy[kN];
+  uint32_t col[Staged<S, NC>::kLoads];
 };
 
 template <class S, int NC>
 __device__ __forceinline__ Gather<S, NC> make_gather(const Params<float>& p, int lane, int x0) {
-  using L = Lattice<2>;
   using B = BlockLayout<S, 9>;
   using G = Staged<S, NC>;
-  Gather<S, NC> g;
+  constexpr uint32_t comp = NC * B::kComp;
+  const uint32_t own = uint32_t(x0 >> 6) * comp;
+  const uint32_t left = uint32_t(wrap_add(x0, -1, p.nx) >> 6) * comp;
+  const uint32_t right = uint32_t(wrap_add(x0 + kW - 1, 1, p.nx) >> 6) * comp;
+  Gather<S, NC> gat;
 #pragma unroll
-  for (int j = 0; j < G::kHaloLoads; ++j) {
-    const int e0 = j * 64 + lane;
-    const int e = e0 < G::kPieces ? e0 : 0;
-    const int side = e & 1;
-    const int bx = side == 0 ? wrap_add(x0, -1, p.nx) : wrap_add(x0 + kW - 1, 1, p.nx);  // neighbour block
-    const uint32_t blk = uint32_t(bx >> 6) * uint32_t(NC * B::kComp);
-    if (e < G::kRunPieces) {  // piece e = (9 c + i) 2 + side
-      const int c = e / 18, i = (e / 2) % 9;
-      const uint32_t run_bytes = kW * (i == 0 ? B::kRest : B::kMove);
-      g.col[j] = blk + B::run(c, i) + (side == 0 ? run_bytes - 16u : 0u);
-      g.dy[j] = L::cy(i);
-    } else {  // reference piece e = 18 NC + (3 c + hr) 2 + side
-      const int q = (e - G::kRunPieces) / 2, c = q / 3, hr = q % 3;
-      g.col[j] = blk + B::ref(c) + (side == 0 ? kW * B::kRef - 16u : 0u);
-      g.dy[j] = hr == 0 ? 0 : (hr == 1 ? 1 : -1);
+  for (int j = 0; j < G::kLoads; ++j) {
+    const int ch = j * 64 + lane;
+    const int g = ch < G::chunks(0) ? 0 : (ch < G::chunks(0) + G::chunks(1) ? 1 : 2);
+    const int first = g == 0 ? 0 : (g == 1 ? G::chunks(0) : G::chunks(0) + G::chunks(1));
+    if (ch >= G::kChunks) {
+      gat.col[j] = own;
+      continue;
     }
+    const uint32_t byte = uint32_t(ch - first) * 16u;  // within the group
+    // segment of the chunk: component, run slot and position in it
+    const uint32_t cb = G::comp_bytes(g);
+    const int c = int(byte / cb);
+    uint32_t in = byte - uint32_t(c) * cb;
+    int k = 0;
+#pragma unroll
+    for (int q = 0; q < G::kRunsPerGroup - 1; ++q)
+      if (in >= G::seg_bytes(g, k)) {
+        in -= G::seg_bytes(g, k);
+        ++k;
+      }
+    const uint32_t run = k == 3 ? B::ref(c) : B::run(c, G::vel(g, k));
+    const uint32_t len = uint32_t(kW) * G::elem(g, k);  // bytes of the run in a block
+    uint32_t off;
+    if (in < 16u)
+      off = left + run + len - 16u;  // left neighbour's last 16 bytes
+    else if (in < 16u + len)
+      off = own + run + (in - 16u);
+    else
+      off = right + run;  // right neighbour's first 16 bytes
+    gat.col[j] = off;
   }
-  return g;
+  return gat;
 }
 
-// Stage the populations pulled into row r (wave-uniform) of the strip at x0
-// into the LDS slot `dst` (Staged layout) with exactly Staged::kLoads direct
-// loads (each load has at least one active lane).
+// Stage the populations pulled into row r (wave-uniform) of the strip into
+// the LDS slot `dst` (Staged layout) with exactly Staged::kLoads direct loads
+// of the whole wave.
 template <class S, int NC>
-__device__ __forceinline__ void stage_row(const char* fin, const Params<float>& p, const Gather<S, NC>& g,
-                                          int lane, int x0, int r, char* dst_in) {
+__device__ __forceinline__ void stage_row(const char* fin, const Params<float>& p, const Gather<S, NC>& gat,
+                                          int lane, int r, char* dst_in) {
   using B = BlockLayout<S, 9>;
   // The LDS destination is passed through an empty asm statement: the
   // compiler's own tracking of direct loads into LDS would otherwise add a
@@ -151,64 +194,17 @@ __device__ __forceinline__ void stage_row(const char* fin, const Params<float>& 
   asm volatile("" : "+s"(dst));
   using G = Staged<S, NC>;
   const uint32_t stride = uint32_t(p.nbx) * uint32_t(NC * B::kComp);
-  const uint32_t blk = uint32_t(x0 >> 6) * uint32_t(NC * B::kComp);
-  // row parts of the source rows of the v_y groups 0, +1 (row above), -1
-  const uint32_t row0 = uint32_t(r) * stride, rowu = uint32_t(wrap_add(r, -1, p.ny)) * stride,
-                 rowd = uint32_t(wrap_add(r, 1, p.ny)) * stride;
-  const uint32_t ry[3] = {row0, rowu, rowd};
-  constexpr int first[3] = {0, 2, 4};  // first velocity of each group
-  constexpr uint32_t bytes[3] = {G::kGroup0, G::kGroup1, G::kGroup1};
+  // row parts of the source rows of the groups v_y = 0, +1 (row above), -1
+  const uint32_t ry[3] = {uint32_t(r) * stride, uint32_t(wrap_add(r, -1, p.ny)) * stride,
+                          uint32_t(wrap_add(r, 1, p.ny)) * stride};
 #pragma unroll
-  for (int c = 0; c < NC; ++c) {
-#pragma unroll
-    for (int g3 = 0; g3 < 3; ++g3) {
-      const char* src = fin + (ry[g3] + blk + B::run(c, first[g3])) + uint32_t(lane) * 16u;
-      if (uint32_t(lane) * 16u < bytes[g3])
-        __builtin_amdgcn_global_load_lds(src, dst + B::run(c, first[g3]), 16, 0, 0);
-    }
+  for (int j = 0; j < G::kLoads; ++j) {
+    // the chunk's source row (known at compile time except for a load that
+    // straddles two groups)
+    const int ch = j * 64 + lane;
+    const uint32_t rp = ch < G::chunks(0) ? ry[0] : (ch < G::chunks(0) + G::chunks(1) ? ry[1] : ry[2]);
+    __builtin_amdgcn_global_load_lds(fin + (rp + gat.col[j]), dst + 1024u * uint32_t(j), 16, 0, 0);
   }
-  if constexpr (S::kShift) {
-    // reference runs of the rows above and below: lane (2 c + q) 8 + chunk
-    const int c = lane >> 4, q = (lane >> 3) & 1, chunk = lane & 7;
-    const uint32_t rq = q == 0 ? rowu : rowd;
-    if (lane < 16 * NC)
-      __builtin_amdgcn_global_load_lds(fin + (rq + blk + B::ref(c < NC ? c : 0) + uint32_t(chunk) * 16u),
-                                       dst + G::kHRowOff, 16, 0, 0);
-  }
-#pragma unroll
-  for (int j = 0; j < G::kHaloLoads; ++j) {
-    const uint32_t row = g.dy[j] > 0 ? rowu : (g.dy[j] < 0 ? rowd : row0);
-    if (j * 64 + lane < G::kPieces)
-      __builtin_amdgcn_global_load_lds(fin + (row + g.col[j]), dst + G::kHaloOff + 1024 * j, 16, 0, 0);
-  }
-}
-
-// LDS byte offset of slot i of component c in relative column col (-16/e ..
-// 63 + 16/e, e the slot size) of a staged row: the main runs for 0 .. 63,
-// the halo pieces outside.
-template <class S, int NC>
-__device__ __forceinline__ uint32_t staged_off(int c, int i, int col) {
-  using B = BlockLayout<S, 9>;
-  using G = Staged<S, NC>;
-  const uint32_t e = i == 0 ? B::kRest : B::kMove;
-  const int per = int(16 / e);  // columns per halo piece
-  if (col < 0) return G::kHaloOff + 16u * uint32_t((9 * c + i) * 2) + uint32_t(col + per) * e;
-  if (col >= kW) return G::kHaloOff + 16u * uint32_t((9 * c + i) * 2 + 1) + uint32_t(col - kW) * e;
-  return B::run(c, i) + uint32_t(col) * e;
-}
-
-// LDS byte offset of the reference of component c in relative column col
-// (-8 .. 71) of the source row dy (0, +1: above, -1: below) of a staged row
-// (shifted codec).
-template <class S, int NC>
-__device__ __forceinline__ uint32_t staged_ref_off(int c, int dy, int col) {
-  using B = BlockLayout<S, 9>;
-  using G = Staged<S, NC>;
-  const int hr = dy == 0 ? 0 : (dy > 0 ? 1 : 2);
-  if (col < 0) return G::kHaloOff + 16u * uint32_t(G::kRunPieces + (3 * c + hr) * 2) + uint32_t(col + 8) * 2u;
-  if (col >= kW) return G::kHaloOff + 16u * uint32_t(G::kRunPieces + (3 * c + hr) * 2 + 1) + uint32_t(col - kW) * 2u;
-  if (dy == 0) return B::ref(c) + uint32_t(col) * 2u;
-  return G::kHRowOff + uint32_t(2 * c + (dy > 0 ? 0 : 1)) * (kW * 2u) + uint32_t(col) * 2u;
 }
 
 __device__ __forceinline__ float lds_ref(const char* a) { return float(*reinterpret_cast<const _Float16*>(a)); }
@@ -247,10 +243,6 @@ __global__ void __launch_bounds__(256) k_sweep_d2q9(const void* fin_v, void* fou
   auto rslot = [&](int r) { return (r - ya + 8 * kRhoRing) & (kRhoRing - 1); };
   auto hslot = [&](int r) { return (r - ya + 8 * kHRing) & (kHRing - 1); };
 
-  // columns of the lane's pulled slots in a staged row, clamped into the
-  // strip; the edge lanes take the edge words instead
-  const int lm = lane > 0 ? lane - 1 : 0, lp = lane < kW - 1 ? lane + 1 : kW - 1;
-
   // Scale of the component of a halo lane (lane % NC), picked by selects
   // and kept in a register: an indexed read of the parameters would be a
   // vector memory load inside the rounds, whose wait would also wait for
@@ -272,21 +264,11 @@ __global__ void __launch_bounds__(256) k_sweep_d2q9(const void* fin_v, void* fou
       T led = T(0);
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
-        const int col = L::cx(i) > 0 ? lm : (L::cx(i) < 0 ? lp : lane);
-        const bool edge = L::cx(i) > 0 ? lane == 0 : lane == kW - 1;  // pulls from column -1 or 64
-        T raw = lds_raw<S>(st + B::run(c, i) + B::in_run(i, col), i);
-        if (L::cx(i) != 0) {
-          const T e = lds_raw<S>(st + staged_off<S, NC>(c, i, L::cx(i) > 0 ? -1 : kW), i);
-          raw = edge ? e : raw;
-        }
+        // column lane - v_x of the padded segment (-1 and 64 in the halo parts)
+        const int col = lane - L::cx(i);
+        const T raw = lds_raw<S>(st + G::run0(c, i) + col * int(i == 0 ? B::kRest : B::kMove), i);
         float h = 0.f;
-        if constexpr (S::kShift) {
-          h = lds_ref(st + staged_ref_off<S, NC>(c, L::cy(i), col));
-          if (L::cx(i) != 0) {
-            const float e = lds_ref(st + staged_ref_off<S, NC>(c, L::cy(i), L::cx(i) > 0 ? -1 : kW));
-            h = edge ? e : h;
-          }
-        }
+        if constexpr (S::kShift) h = lds_ref(st + G::ref0(c, L::cy(i)) + col * 2);
         take_slot<S, 2>(i, raw, h, p.sh.scale[c], led, f[c][i]);
       }
       ledger[c] = led;
@@ -309,9 +291,10 @@ __global__ void __launch_bounds__(256) k_sweep_d2q9(const void* fin_v, void* fou
       T v[9], led = T(0);
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
-        const T raw = lds_raw<S>(st + staged_off<S, NC>(c, i, hcol - L::cx(i)), i);
+        const int col = hcol - L::cx(i);  // -3 .. 66, inside the padded segment
+        const T raw = lds_raw<S>(st + G::run0(c, i) + col * int(i == 0 ? B::kRest : B::kMove), i);
         float h = 0.f;
-        if constexpr (S::kShift) h = lds_ref(st + staged_ref_off<S, NC>(c, L::cy(i), hcol - L::cx(i)));
+        if constexpr (S::kShift) h = lds_ref(st + G::ref0(c, L::cy(i)) + col * 2);
         take_slot<S, 2>(i, raw, h, halo_scale, led, v[i]);
       }
       s_rho[rslot(r)][c][hc < 2 ? hc : kW + hc] = site_density<S>(led, halo_scale);
@@ -444,20 +427,20 @@ __global__ void __launch_bounds__(256) k_sweep_d2q9(const void* fin_v, void* fou
   // rho of rows ya-2, ya-1 (waves 2, 3) and ya .. ya+3 (all waves); h of rows
   // ya-1 .. ya+2; populations of row ya + w in F0; row ya + 4 + w staged.
   if (w >= 2) {
-    stage_row<S, NC>(fin, p, gat, lane, x0, wrap_mod(ya - 4 + w, ny), stage);
+    stage_row<S, NC>(fin, p, gat, lane, wrap_mod(ya - 4 + w, ny), stage);
     wait_vm<0>();
     take(stage, F1, L1);
     put_rho(ya - 4 + w, F1, L1);
     put_rho_halo(ya - 4 + w, stage);
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // the slot is read before it is staged again
   }
-  stage_row<S, NC>(fin, p, gat, lane, x0, wrap_mod(ya + w, ny), stage);
+  stage_row<S, NC>(fin, p, gat, lane, wrap_mod(ya + w, ny), stage);
   wait_vm<0>();
   take(stage, F0, L0);
   put_rho(ya + w, F0, L0);
   put_rho_halo(ya + w, stage);
   asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-  stage_row<S, NC>(fin, p, gat, lane, x0, wrap_mod(ya + 4 + w, ny), stage);
+  stage_row<S, NC>(fin, p, gat, lane, wrap_mod(ya + 4 + w, ny), stage);
   lds_barrier();
   put_h4(ya - 1);
   lds_barrier();
@@ -488,7 +471,7 @@ __global__ void __launch_bounds__(256) k_sweep_d2q9(const void* fin_v, void* fou
       // ahead of the other waves' arithmetic (2.5% faster at 2048^2; the same
       // for FP32 is 4% slower)
       if constexpr (S::kShift) __builtin_amdgcn_s_setprio(1);
-      stage_row<S, NC>(fin, p, gat, lane, x0, wrap_mod(ra + 4, ny), stage);
+      stage_row<S, NC>(fin, p, gat, lane, wrap_mod(ra + 4, ny), stage);
       if constexpr (S::kShift) __builtin_amdgcn_s_setprio(0);
     }
     lds_barrier();

@@ -210,3 +210,24 @@ def test_sweep_kernels_inline_everything(asm):
     for store, nc, lines in kernels(asm):
         body = "\n".join(lines)
         assert "s_swappc" not in body and "scratch_" not in body, (store, nc)
+
+
+def test_staging_destinations_are_uniform(asm):
+    """A direct load's LDS destination is M0, one value for the whole wave.
+    The compiler once merged a load issued by some lanes with the next load
+    under divergent control flow and fed M0 from one lane of a per-lane
+    choice of the two destinations (v_readfirstlane), so that the other
+    lanes' data landed in the wrong place.  The staging loads are issued by
+    the whole wave now; M0 must never come from a v_readfirstlane."""
+    for store, nc, lines in kernels(asm):
+        from_lane = set()
+        for line in lines:
+            t = line.strip().replace(",", " ").split()
+            if not t:
+                continue
+            if t[0] == "v_readfirstlane_b32":
+                from_lane.add(t[1])
+            elif len(t) > 1 and t[1] == "m0":
+                assert not (set(t[2:]) & from_lane), (store, nc, line.strip())
+            elif len(t) > 1 and t[1] in from_lane and not t[0].startswith("v_readfirstlane"):
+                from_lane.discard(t[1])  # overwritten
