@@ -212,6 +212,52 @@ def test_sweep_kernels_inline_everything(asm):
         assert "s_swappc" not in body and "scratch_" not in body, (store, nc)
 
 
+@pytest.fixture(scope="module")
+def asm3d(tmp_path_factory):
+    if not shutil.which(B.HIPCC) and not os.path.exists(B.HIPCC):
+        pytest.skip("hipcc not available")
+    out = tmp_path_factory.mktemp("isa") / "sweep3d.s"
+    flags = [f for f in B.FLAGS if f not in ("-fPIC", "-Wall")]
+    cmd = [B.HIPCC, *flags, "-S", "--cuda-device-only", os.path.join(B.CSRC, "k_sweep3d.hip"), "-o", str(out)]
+    subprocess.run(cmd, check=True, capture_output=True)
+    return out.read_text()
+
+
+KERNEL3D = re.compile(r"^(_ZN3lbm6sweep313k_sweep_d3q19INS_\d+(Store\w+?)ELi(\d)E\w*):", re.M)
+
+
+def kernels3d(text):
+    for m in KERNEL3D.finditer(text):
+        end = text.index("s_endpgm", m.end())
+        yield m.group(2), int(m.group(3)), text[m.end():end].split("\n")
+
+
+def m0_from_lane(lines):
+    """Instructions that set M0 from a register written by v_readfirstlane."""
+    from_lane, bad = set(), []
+    for line in lines:
+        t = line.strip().replace(",", " ").split()
+        if not t:
+            continue
+        if t[0] == "v_readfirstlane_b32":
+            from_lane.add(t[1])
+        elif len(t) > 1 and t[1] == "m0":
+            if set(t[2:]) & from_lane:
+                bad.append(line.strip())
+        elif len(t) > 1 and t[1] in from_lane:
+            from_lane.discard(t[1])  # overwritten
+    return bad
+
+
+def test_d3q19_staging_destinations_are_uniform(asm3d):
+    """The same check on the D3Q19 plane sweep's direct loads."""
+    found = 0
+    for store, nc, lines in kernels3d(asm3d):
+        found += 1
+        assert not m0_from_lane(lines), (store, nc, m0_from_lane(lines))
+    assert found == 3
+
+
 def test_staging_destinations_are_uniform(asm):
     """A direct load's LDS destination is M0, one value for the whole wave.
     The compiler once merged a load issued by some lanes with the next load
@@ -220,14 +266,4 @@ def test_staging_destinations_are_uniform(asm):
     lanes' data landed in the wrong place.  The staging loads are issued by
     the whole wave now; M0 must never come from a v_readfirstlane."""
     for store, nc, lines in kernels(asm):
-        from_lane = set()
-        for line in lines:
-            t = line.strip().replace(",", " ").split()
-            if not t:
-                continue
-            if t[0] == "v_readfirstlane_b32":
-                from_lane.add(t[1])
-            elif len(t) > 1 and t[1] == "m0":
-                assert not (set(t[2:]) & from_lane), (store, nc, line.strip())
-            elif len(t) > 1 and t[1] in from_lane and not t[0].startswith("v_readfirstlane"):
-                from_lane.discard(t[1])  # overwritten
+        assert not m0_from_lane(lines), (store, nc, m0_from_lane(lines))
