@@ -311,8 +311,9 @@ def run_batch_only(n_req, steps, warmup, storage):
     from paper_0704_3444_amd import lb
 
     reqs = LI.serving_mix(256)[:n_req]
-    st = torch.cuda.current_stream()
-    # the batch steps on the stream the events are recorded on
+    # the batch steps on the stream the events are recorded on (a stream of
+    # its own: given the null stream, a batch creates a non-blocking stream)
+    st = torch.cuda.Stream()
     batch = lb.Batch(storage=storage, max_comp=3, max_slots=n_req, arena_bytes=8 << 30, graph_steps=50,
                      stream=st.cuda_stream)
     alg = 0

@@ -203,7 +203,7 @@ def test_f16s_accuracy_on_the_immersion_film():
     cfg, rho0 = LI.ternary_immersion(128, ny=77)
     o = run_oracle(cfg, rho0, 200)
     for path in paths_for(cfg, "f16s"):
-        g = run_gpu(cfg, rho0, 200, storage="f16s", path=path, fields=False)
+        g = run_gpu(cfg, rho0, 200, storage="f16s", path=path)
         e = float(np.max(np.abs(g["rho"] - o["rho"]) / o["rho"]))
         print(f"[f16s-film] {path}: max relative density error {e:.2e}", flush=True)
         assert e < 2e-3, (path, e)
