@@ -61,9 +61,13 @@ __device__ __forceinline__ typename S::T gload_slot(const void* base, uint32_t o
   return T(*(const __attribute__((address_space(1))) typename S::Move*)b);
 }
 
-// Reference of the shifted codec at a byte offset, as FP32 (exact).
-__device__ __forceinline__ float gload_ref(const void* base, uint32_t off) {
-  return float(*(const __attribute__((address_space(1))) _Float16*)((const GChar*)base + off));
+// FP16 value (moving slot or reference of the shifted codec) and FP32 value
+// at a byte offset.
+__device__ __forceinline__ _Float16 gload_half(const void* base, uint32_t off) {
+  return *(const __attribute__((address_space(1))) _Float16*)((const GChar*)base + off);
+}
+__device__ __forceinline__ float gload_f32(const void* base, uint32_t off) {
+  return *(const __attribute__((address_space(1))) float*)((const GChar*)base + off);
 }
 
 template <bool NTSTORE, typename V>
@@ -96,24 +100,34 @@ __device__ __forceinline__ void pull_offsets(const Params<typename S::T>& p, int
 }
 
 // Pulled populations of component c at a site from its offsets: decoded
-// values and their running sum (take_slot).
+// values and their running sum (take_slot, take_shifted).
 template <class S>
 __device__ __forceinline__ void pull_component(const void* __restrict__ fin, const Params<typename S::T>& p, int c,
                                                const uint32_t (&off)[9], const uint32_t (&roff)[9],
                                                typename S::T (&f)[9], typename S::T& sum) {
   using T = typename S::T;
   using B = BlockLayout<S, 9>;
-  T raw[9];
-  float h[9];
-#pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    raw[i] = gload_slot<S>(fin, off[i] + B::run(c, i), i);
-    h[i] = 0.f;
-    if constexpr (S::kShift) h[i] = gload_ref(fin, roff[i] + B::ref(c));
-  }
   sum = T(0);
+  if constexpr (S::kShift) {
+    float rest = 0.f;
+    _Float16 d[9], h[9];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) take_slot<S, 2>(i, raw[i], h[i], p.sh.scale[c], sum, f[i]);
+    for (int i = 0; i < 9; ++i) {
+      if (i == 0)
+        rest = gload_f32(fin, off[0] + B::run(c, 0));
+      else
+        d[i] = gload_half(fin, off[i] + B::run(c, i));
+      h[i] = gload_half(fin, roff[i] + B::ref(c));
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) take_shifted<2>(i, i == 0 ? _Float16(0) : d[i], rest, h[i], p.sh.scale[c], p.sh.one, sum, f[i]);
+  } else {
+    T raw[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) raw[i] = gload_slot<S>(fin, off[i] + B::run(c, i), i);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) take_slot<S, 2>(i, raw[i], sum, f[i]);
+  }
 }
 
 // rho^sigma at (x, y) from the pulled slots: the sum of the decoded
@@ -293,15 +307,14 @@ __device__ __forceinline__ void tile_step(const void* __restrict__ fin, void* __
         // the site's new reference, the FP16 deviations of the moving
         // populations, and the rest of the ledger
         const _Float16 h = new_ref(led[k][c]);
-        float d[Q];
+        _Float16 d[Q];
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
-          const _Float16 di = encode_move<2>(i, f[k][c][i], p.sh.inv_scale[c], float(h));
-          d[i] = float(di);
-          gstore<NTSTORE>(fout, own + B::run(c, i) + B::in_run(i, x), di);
+          d[i] = encode_move<2>(i, f[k][c][i], p.sh.inv_scale[c], float(h));
+          gstore<NTSTORE>(fout, own + B::run(c, i) + B::in_run(i, x), d[i]);
         }
         gstore<NTSTORE>(fout, own + B::ref(c) + B::in_ref(x), h);
-        gstore<NTSTORE>(fout, own + B::run(c, 0) + B::in_run(0, x), ledger_rest<Q>(led[k][c], float(h), d));
+        gstore<NTSTORE>(fout, own + B::run(c, 0) + B::in_run(0, x), ledger_rest<Q>(led[k][c], float(h), d, p.sh.minus_one));
       } else {
 #pragma unroll
         for (int i = 0; i < Q; ++i) gstore<NTSTORE>(fout, own + B::run(c, i) + B::in_run(i, x), f[k][c][i]);

@@ -100,7 +100,7 @@ __device__ __forceinline__ uint64_t own_byte(const SiteCoord& c, int k, int i, c
 }
 
 // Populations of component k pulled into site c, decoded to the working
-// precision, and their running sum (take_slot).
+// precision, and their running sum (take_slot, take_shifted).
 template <class S, int LAT>
 __device__ __forceinline__ void pull_pops(const void* fin, const SiteCoord& c, int k,
                                           const Params<typename S::T>& p,
@@ -111,10 +111,16 @@ __device__ __forceinline__ void pull_pops(const void* fin, const SiteCoord& c, i
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const SlotAt a = pull_slot<LAT>(c, i, p);
-    const T raw = load_slot<S>(fin, pop_byte<S, Q>(p.n, p.nbx, k, a.i, a.x, a.row), i);
-    float h = 0.f;
-    if constexpr (S::kShift) h = load_ref(fin, ref_byte<S, Q>(p.n, p.nbx, k, a.x, a.row));
-    take_slot<S, LAT>(i, raw, h, p.sh.scale[k], sum, f[i]);
+    const uint64_t at = pop_byte<S, Q>(p.n, p.nbx, k, a.i, a.x, a.row);
+    if constexpr (S::kShift) {
+      const _Float16 h = load_half(fin, ref_byte<S, Q>(p.n, p.nbx, k, a.x, a.row));
+      if (i == 0)
+        take_shifted<LAT>(0, _Float16(0), load_f32(fin, at), h, p.sh.scale[k], p.sh.one, sum, f[i]);
+      else
+        take_shifted<LAT>(i, load_half(fin, at), 0.f, h, p.sh.scale[k], p.sh.one, sum, f[i]);
+    } else {
+      take_slot<S, LAT>(i, load_slot<S>(fin, at, i), sum, f[i]);
+    }
   }
 }
 
@@ -128,7 +134,7 @@ __device__ __forceinline__ void pull_pops_exact(const void* fin, const SiteCoord
     const SlotAt a = pull_slot<LAT>(c, i, p);
     const auto raw = load_slot<S>(fin, pop_byte<S, Q>(p.n, p.nbx, k, a.i, a.x, a.row), i);
     float h = 0.f;
-    if constexpr (S::kShift) h = load_ref(fin, ref_byte<S, Q>(p.n, p.nbx, k, a.x, a.row));
+    if constexpr (S::kShift) h = float(load_half(fin, ref_byte<S, Q>(p.n, p.nbx, k, a.x, a.row)));
     f[i] = take_exact<S, LAT>(i, raw, h, p.sh.scale[k]);
   }
 }
@@ -145,15 +151,14 @@ __device__ __forceinline__ void store_pops(void* fout, const SiteCoord& c, int k
   char* out = static_cast<char*>(fout);
   if constexpr (S::kShift) {
     const _Float16 h = new_ref(sum);
-    float d[Q];
+    _Float16 d[Q];
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-      const _Float16 di = encode_move<LAT>(i, post[i], p.sh.inv_scale[k], float(h));
-      d[i] = float(di);
-      *reinterpret_cast<_Float16*>(out + own_byte<S, LAT>(c, k, i, p)) = di;
+      d[i] = encode_move<LAT>(i, post[i], p.sh.inv_scale[k], float(h));
+      *reinterpret_cast<_Float16*>(out + own_byte<S, LAT>(c, k, i, p)) = d[i];
     }
     *reinterpret_cast<_Float16*>(out + ref_byte<S, Q>(p.n, p.nbx, k, c.x, (long long)c.y + (long long)p.ny * c.z)) = h;
-    *reinterpret_cast<float*>(out + own_byte<S, LAT>(c, k, 0, p)) = ledger_rest<Q>(sum, float(h), d);
+    *reinterpret_cast<float*>(out + own_byte<S, LAT>(c, k, 0, p)) = ledger_rest<Q>(sum, float(h), d, p.sh.minus_one);
   } else {
 #pragma unroll
     for (int i = 0; i < Q; ++i) *reinterpret_cast<T*>(out + own_byte<S, LAT>(c, k, i, p)) = post[i];

@@ -207,7 +207,8 @@ __device__ __forceinline__ void stage_row(const char* fin, const Params<float>& 
   }
 }
 
-__device__ __forceinline__ float lds_ref(const char* a) { return float(*reinterpret_cast<const _Float16*>(a)); }
+__device__ __forceinline__ _Float16 lds_half(const char* a) { return *reinterpret_cast<const _Float16*>(a); }
+__device__ __forceinline__ float lds_f32(const char* a) { return *reinterpret_cast<const float*>(a); }
 
 template <class S>
 __device__ __forceinline__ float lds_raw(const char* a, int i) {
@@ -257,7 +258,7 @@ __global__ void __launch_bounds__(256) k_sweep_d2q9(const void* fin_v, void* fou
   }
 
   // Take a staged row into registers: decoded populations, in direction
-  // order, and the running sum of each component (take_slot).
+  // order, and the running sum of each component (take_slot, take_shifted).
   auto take = [&](const char* st, T (&f)[NC][9], T (&ledger)[NC]) __attribute__((always_inline)) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -266,10 +267,14 @@ __global__ void __launch_bounds__(256) k_sweep_d2q9(const void* fin_v, void* fou
       for (int i = 0; i < 9; ++i) {
         // column lane - v_x of the padded segment (-1 and 64 in the halo parts)
         const int col = lane - L::cx(i);
-        const T raw = lds_raw<S>(st + G::run0(c, i) + col * int(i == 0 ? B::kRest : B::kMove), i);
-        float h = 0.f;
-        if constexpr (S::kShift) h = lds_ref(st + G::ref0(c, L::cy(i)) + col * 2);
-        take_slot<S, 2>(i, raw, h, p.sh.scale[c], led, f[c][i]);
+        const char* at = st + G::run0(c, i) + col * int(i == 0 ? B::kRest : B::kMove);
+        if constexpr (S::kShift) {
+          const _Float16 h = lds_half(st + G::ref0(c, L::cy(i)) + col * 2);
+          take_shifted<2>(i, i == 0 ? _Float16(0) : lds_half(at), i == 0 ? lds_f32(at) : 0.f, h, p.sh.scale[c],
+                          p.sh.one, led, f[c][i]);
+        } else {
+          take_slot<S, 2>(i, lds_raw<S>(at, i), led, f[c][i]);
+        }
       }
       ledger[c] = led;
     }
@@ -292,10 +297,14 @@ __global__ void __launch_bounds__(256) k_sweep_d2q9(const void* fin_v, void* fou
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
         const int col = hcol - L::cx(i);  // -3 .. 66, inside the padded segment
-        const T raw = lds_raw<S>(st + G::run0(c, i) + col * int(i == 0 ? B::kRest : B::kMove), i);
-        float h = 0.f;
-        if constexpr (S::kShift) h = lds_ref(st + G::ref0(c, L::cy(i)) + col * 2);
-        take_slot<S, 2>(i, raw, h, halo_scale, led, v[i]);
+        const char* at = st + G::run0(c, i) + col * int(i == 0 ? B::kRest : B::kMove);
+        if constexpr (S::kShift) {
+          const _Float16 h = lds_half(st + G::ref0(c, L::cy(i)) + col * 2);
+          take_shifted<2>(i, i == 0 ? _Float16(0) : lds_half(at), i == 0 ? lds_f32(at) : 0.f, h, halo_scale,
+                          p.sh.one, led, v[i]);
+        } else {
+          take_slot<S, 2>(i, lds_raw<S>(at, i), led, v[i]);
+        }
       }
       s_rho[rslot(r)][c][hc < 2 ? hc : kW + hc] = site_density<S>(led, halo_scale);
     }
@@ -377,12 +386,12 @@ __global__ void __launch_bounds__(256) k_sweep_d2q9(const void* fin_v, void* fou
         // the site's new reference, the FP16 deviations of the moving
         // populations, and the rest of the ledger
         const float h = float(new_ref(Lc[c]));
-        float d[9];
+        _Float16 d[9];
 #pragma unroll
-        for (int i = 1; i < 9; ++i) d[i] = float(encode_move<2>(i, f[i], p.sh.inv_scale[c], h));
-        Lc[c] = ledger_rest<9>(Lc[c], h, d);
+        for (int i = 1; i < 9; ++i) d[i] = encode_move<2>(i, f[i], p.sh.inv_scale[c], h);
+        Lc[c] = ledger_rest<9>(Lc[c], h, d, p.sh.minus_one);
 #pragma unroll
-        for (int i = 1; i < 9; ++i) Fc[c][i] = d[i];
+        for (int i = 1; i < 9; ++i) Fc[c][i] = float(d[i]);
         Hc[c] = h;
       } else {
 #pragma unroll

@@ -200,6 +200,8 @@ lbm::ShiftRef shift_ref_of(const lb_params* p, const double* rho0, size_t S) {
   lbm::ShiftRef r;
   std::memset(&r, 0, sizeof(r));
   if (p->storage != LB_F16S) return r;
+  r.one = 1.0f;
+  r.minus_one = -1.0f;
   for (int k = 0; k < p->n_comp; ++k) {
     double mx = 0.0;
     for (size_t i = 0; i < S; ++i) mx = std::max(mx, rho0[k * S + i]);

@@ -32,6 +32,7 @@ constexpr int kMaxComp = 8;
 struct ShiftRef {
   float scale[kMaxComp];      // s^sigma, a power of two
   float inv_scale[kMaxComp];  // 1 / s^sigma
+  float one, minus_one;       // 1 and -1, as run-time factors of the codec's FMAs (storage.hpp)
 };
 
 // Arithmetic parameters of one run, in the working precision T.

@@ -141,9 +141,13 @@ __device__ __forceinline__ typename S::T load_slot(const void* base, uint64_t of
   return typename S::T(*reinterpret_cast<const typename S::Move*>(b));
 }
 
-// Reference h at a byte offset, as FP32 (exact).
-__device__ __forceinline__ float load_ref(const void* base, uint64_t off) {
-  return float(*reinterpret_cast<const _Float16*>(static_cast<const char*>(base) + off));
+// FP16 value (a moving slot or a reference of the shifted codec) and FP32
+// rest slot at a byte offset.
+__device__ __forceinline__ _Float16 load_half(const void* base, uint64_t off) {
+  return *reinterpret_cast<const _Float16*>(static_cast<const char*>(base) + off);
+}
+__device__ __forceinline__ float load_f32(const void* base, uint64_t off) {
+  return *reinterpret_cast<const float*>(static_cast<const char*>(base) + off);
 }
 
 // k_i = 36 w_i, the multiple of the reference in the shifted equilibrium of
@@ -165,22 +169,38 @@ constexpr bool ref_weights_exact() {
 }
 static_assert(ref_weights_exact<1>() && ref_weights_exact<2>() && ref_weights_exact<3>(), "36 w_i integral");
 
-// Take pulled slot i (raw value in the working precision; h the reference of
-// the site that wrote it, shifted codec only) into the population value f
-// and the site's running sum: the shifted codec sums u_i = k_i h + d in
-// units of s (exact) and returns f = s u_i; the plain codecs return the value
-// and sum it in direction order.
+// a h + d with h and d FP16, rounded once (for the codec's values the result
+// is exact).  Written as an FMA of the converted operands, which the compiler
+// turns into one v_fma_mix_f32 (converting the FP16 operands itself) unless
+// it can simplify the FMA: a factor of 1 or -1 would become an add, with two
+// separate conversions.  Such factors therefore come from the run's
+// parameters (ShiftRef::one, ShiftRef::minus_one), which the compiler cannot
+// fold.
+__device__ __forceinline__ float mix_fma(float a, _Float16 h, _Float16 d) {
+  return __builtin_fmaf(a, float(h), float(d));
+}
+
+// Take pulled slot i (raw value in the working precision) into the
+// population value f and the site's running sum, in direction order (plain
+// codecs).
 template <class S, int LAT>
-__device__ __forceinline__ void take_slot(int i, typename S::T raw, float h, float scale, typename S::T& sum,
-                                          typename S::T& f) {
-  if constexpr (S::kShift) {
-    const float u = __builtin_fmaf(ref_weight<LAT>(i), h, raw);
-    sum = i == 0 ? u : sum + u;
-    f = u * scale;
-  } else {
-    sum = i == 0 ? raw : sum + raw;
-    f = raw;
-  }
+__device__ __forceinline__ void take_slot(int i, typename S::T raw, typename S::T& sum, typename S::T& f) {
+  static_assert(!S::kShift, "plain codecs");
+  sum = i == 0 ? raw : sum + raw;
+  f = raw;
+}
+
+// The same for the shifted codec: slot i holds the FP16 deviation d (i > 0)
+// or the FP32 rest value (i == 0), written by the site whose reference is h.
+// Sums u_i = k_i h + d in units of s (exact) and returns f = s u_i.  `one`
+// is ShiftRef::one (1.0, the factor of the directions with k_i = 1).
+template <int LAT>
+__device__ __forceinline__ void take_shifted(int i, _Float16 d, float rest, _Float16 h, float scale, float one,
+                                             float& sum, float& f) {
+  const float k = ref_weight<LAT>(i) == 1.0f ? one : ref_weight<LAT>(i);
+  const float u = i == 0 ? __builtin_fmaf(k, float(h), rest) : mix_fma(k, h, d);
+  sum = i == 0 ? u : sum + u;
+  f = u * scale;
 }
 
 // The same population exactly in FP64 (k_i h + d is exact in FP32 already;
@@ -219,13 +239,15 @@ __device__ __forceinline__ _Float16 encode_move(int i, float post, float inv_sca
 }
 
 // Rest slot that keeps the stored total at T: T - 36 h' - sum_{i>0} d*_i,
-// each step exact.  `d` holds the stored moving deviations (index 0 unused).
+// each step exact.  `d` holds the stored moving deviations (index 0 unused);
+// each subtraction is an FMA of the FP16 value by `minus_one`
+// (ShiftRef::minus_one, -1.0), one v_fma_mix_f32.
 template <int Q>
-__device__ __forceinline__ float ledger_rest(float sum, float h, const float (&d)[Q]) {
+__device__ __forceinline__ float ledger_rest(float sum, float h, const _Float16 (&d)[Q], float minus_one) {
 #pragma clang fp contract(off)
   float rest = sum - 36.0f * h;
 #pragma unroll
-  for (int i = 1; i < Q; ++i) rest -= d[i];
+  for (int i = 1; i < Q; ++i) rest = __builtin_fmaf(float(d[i]), minus_one, rest);
   return rest;
 }
 
