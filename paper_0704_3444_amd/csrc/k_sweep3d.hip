@@ -65,16 +65,82 @@ __device__ __forceinline__ int slot(int z, int za) {
 
 // Pieces of the halo columns, per density row of a wave (2 rows): for every
 // direction i the 16 bytes at the end of run i of the block left of the
-// pencil and at the start of run i of the block right of it (the columns
-// x0 - 4 .. x0 - 1 and x0 + 64 .. x0 + 67 of a 4-byte run), and, for the 5
-// directions with v_x = -1 and the 5 with v_x = +1, the first and the last 16
-// bytes of run i of the pencil's own block (columns x0 and x0 + 63, pulled
-// into x0 - 1 and x0 + 64).  Piece index within a row: left 0 .. 18, right
-// 19 .. 37, own start 38 .. 42, own end 43 .. 47.
-constexpr int kPiecesPerRow = 48;
-constexpr int kPieces = 2 * kPiecesPerRow;
-constexpr int kXMinus[5] = {2, 8, 10, 12, 14};  // D3Q19 directions with v_x = -1
-constexpr int kXPlus[5] = {1, 7, 9, 11, 13};    // and with v_x = +1
+// pencil ("left", columns x0 - 4 .. x0 - 1 of a 4-byte run) and at the start
+// of run i of the block right of it ("right", x0 + 64 .. x0 + 67), and, for
+// the 5 directions with v_x = -1 and the 5 with v_x = +1, the first and the
+// last 16 bytes of run i of the pencil's own block ("own start", column x0,
+// pulled into x0 - 1; "own end", x0 + 63, pulled into x0 + 64).  The pieces
+// of a row sit in kSlotsPerRow 16-byte slots, arranged so that every halo
+// column finds the slot value it pulls from run i at one fixed offset from
+// its own base: left piece of run i at slot left_slot(i), followed by the own
+// start of i where v_x(i) = -1; right piece at left_slot(i) + kRightShift,
+// preceded by the own end of i where v_x(i) = +1.  Column x0 + s (s = -2, -1)
+// then reads run i at byte 16 left_slot(i) - 4 v_x(i) + 4 (s + 4), column
+// x0 + 64 + s (s = 0, 1) at 16 left_slot(i) - 4 v_x(i) + 16 kRightShift + 4 s:
+// one LDS read with an immediate offset per direction.  Slots 0 .. 14 hold
+// the x-pairs k = 0 .. 4 (left of x_plus(k), left of x_plus(k) + 1, own start
+// of x_plus(k) + 1), 15 .. 23 the left pieces of the 9 directions with
+// v_x = 0, 24 .. 38 (own end of x_plus(k), right of x_plus(k), right of
+// x_plus(k) + 1), 39 is unused, 40 .. 48 the right pieces of v_x = 0.
+constexpr int kSlotsPerRow = 49;
+constexpr int kRightShift = 25;
+constexpr int kPieces = 2 * kSlotsPerRow;
+
+// the k-th direction with v_x = +1 (its opposite, v_x = -1, is the next one)
+__host__ __device__ constexpr int x_plus(int k) { return k == 0 ? 1 : 2 * k + 5; }
+// the n-th direction with v_x = 0
+__host__ __device__ constexpr int x_zero(int n) { return n == 0 ? 0 : (n < 5 ? n + 2 : n + 10); }
+
+__host__ __device__ constexpr int left_slot(int i) {
+  for (int k = 0; k < 5; ++k) {
+    if (i == x_plus(k)) return 3 * k;
+    if (i == x_plus(k) + 1) return 3 * k + 1;
+  }
+  for (int n = 0; n < 9; ++n)
+    if (i == x_zero(n)) return 15 + n;
+  return -1;
+}
+
+constexpr bool piece_slots_consistent() {
+  // every direction has a slot; v_x = -1 leaves the next slot to its own
+  // start, v_x = +1 the slot before its right piece to its own end
+  for (int i = 0; i < 19; ++i) {
+    const int s = left_slot(i);
+    if (s < 0 || s + kRightShift >= kSlotsPerRow) return false;
+    for (int j = 0; j < 19; ++j) {
+      if (j != i && left_slot(j) == s) return false;
+      if (Lattice<3>::cx(i) == -1 && left_slot(j) == s + 1) return false;
+      if (Lattice<3>::cx(i) == 1 && left_slot(j) == s - 1) return false;
+    }
+  }
+  return kRightShift >= 15 + 9;  // the right pieces after all left slots
+}
+static_assert(piece_slots_consistent(), "halo-column piece slots");
+
+enum PieceKind { kLeftEnd, kOwnStart, kOwnEnd, kRightStart };
+
+// Direction and kind of the piece in slot idx of a row (slot 39, unused,
+// loads the left piece of the rest run again).
+__device__ __forceinline__ void piece_of(int idx, int& i, int& kind) {
+  if (idx < 15) {
+    const int k = idx / 3, m = idx - 3 * (idx / 3);
+    i = x_plus(k) + (m == 0 ? 0 : 1);
+    kind = m == 2 ? kOwnStart : kLeftEnd;
+  } else if (idx < 24) {
+    i = x_zero(idx - 15);
+    kind = kLeftEnd;
+  } else if (idx < 39) {
+    const int k = (idx - 24) / 3, m = (idx - 24) - 3 * ((idx - 24) / 3);
+    i = x_plus(k) + (m == 2 ? 1 : 0);
+    kind = m == 0 ? kOwnEnd : kRightStart;
+  } else if (idx == 39) {
+    i = 0;
+    kind = kLeftEnd;
+  } else {
+    i = x_zero(idx - 40);
+    kind = kRightStart;
+  }
+}
 
 // Per-wave staging of one plane, filled by direct global-to-LDS loads one
 // plane ahead: the halo-row unit (19 pulled values per lane) and the
@@ -139,30 +205,6 @@ __device__ __forceinline__ float load_slot32(__amdgpu_buffer_rsrc_t rs, uint32_t
 template <int V>
 using I = std::integral_constant<int, V>;
 
-// Slot value of run i at column x0 + src (src in -3 .. 66, but not 1 .. 62)
-// from the halo-column pieces of one density row (Stage::piece).
-__device__ __forceinline__ float piece_value(const char* row_pieces, int i, int src) {
-  constexpr int esz = 4;
-  constexpr int per = 16 / esz;  // slots per piece
-  int q, e;
-  if (src < 0) {
-    q = i, e = src + per;
-  } else if (src >= kW) {
-    q = 19 + i, e = src - kW;
-  } else if (src == 0) {  // pulled into x0 - 1 by a direction with v_x = -1
-    int k = 0;
-#pragma unroll
-    for (int m = 0; m < 5; ++m) k = kXMinus[m] == i ? m : k;
-    q = 38 + k, e = 0;
-  } else {  // src == 63: pulled into x0 + 64 by a direction with v_x = +1
-    int k = 0;
-#pragma unroll
-    for (int m = 0; m < 5; ++m) k = kXPlus[m] == i ? m : k;
-    q = 43 + k, e = per - 1;
-  }
-  return *reinterpret_cast<const float*>(row_pieces + q * 16 + e * esz);
-}
-
 // 16 bytes per lane from byte offset voff of the buffer into LDS at dst +
 // 16 lane (a direct load: no registers hold the data in flight).  Kept out
 // of the kernel body: there the 16-byte form of the builtin made the host
@@ -212,9 +254,11 @@ __global__ void __launch_bounds__(64 * kTY * NC) k_sweep_d3q19(const void* fin_v
   const int y_own = y0 + r;
   const int hrow = r < 2 ? r : kTY + r;  // density row of the halo unit: 0, 1, kTY + 2, kTY + 3
   const int y_halo = wrap_mod(y0 - 2 + hrow, p.ny);
-  // halo columns: lanes 0 .. 3 take columns x0 - 2, x0 - 1, x0 + 64, x0 + 65
-  // of the density rows 2 r and 2 r + 1
-  const int xcol_lds = lane < 2 ? lane : kW + lane;  // 0, 1, 66, 67 for lanes 0 .. 3
+  // halo columns: lanes 0 .. 7 take columns x0 - 2, x0 - 1, x0 + 64, x0 + 65
+  // (lane % 4) of the density row 2 r + lane / 4
+  const int hcol = lane & 3, hpass = (lane >> 2) & 1;
+  const int xcol_lds = hcol < 2 ? hcol : kW + hcol;                        // 0, 1, 66, 67
+  const int hbase = hpass * kSlotsPerRow * 16 + (hcol < 2 ? 4 * (hcol + 2) : 16 * kRightShift + 4 * (hcol - 2));
   const LanePart lp_own = lane_part<S, NC>(p, x);
   const uint32_t stride = uint32_t(p.nbx) * uint32_t(NC * B::kComp);  // bytes per row of blocks
   // the piece each lane loads in the two 16-byte loads of the halo columns:
@@ -226,20 +270,14 @@ __global__ void __launch_bounds__(64 * kTY * NC) k_sweep_d3q19(const void* fin_v
   for (int j = 0; j < 2; ++j) {
     const int q = j * kW + lane;
     const int qq = q < kPieces ? q : 0;
-    const int idx = qq % kPiecesPerRow;
-    int i, bx;
-    bool at_end;
-    if (idx < 19) {
-      i = idx, bx = wrap_mod(x0 - 1, p.nx) >> 6, at_end = true;
-    } else if (idx < 38) {
-      i = idx - 19, bx = wrap_mod(x0 + kW, p.nx) >> 6, at_end = false;
-    } else if (idx < 43) {
-      i = kXMinus[idx - 38], bx = x0 >> 6, at_end = false;
-    } else {
-      i = kXPlus[idx - 43], bx = x0 >> 6, at_end = true;
-    }
+    const int idx = qq % kSlotsPerRow;
+    int i, kind;
+    piece_of(idx, i, kind);
+    const int bx = kind == kLeftEnd ? wrap_mod(x0 - 1, p.nx) >> 6
+                 : (kind == kRightStart ? wrap_mod(x0 + kW, p.nx) >> 6 : x0 >> 6);
+    const bool at_end = kind == kLeftEnd || kind == kOwnEnd;
     const uint32_t esz = i == 0 ? B::kRest : B::kMove;
-    prow[j] = qq / kPiecesPerRow;
+    prow[j] = qq / kSlotsPerRow;
     pdy[j] = L::cy(i);
     pdz[j] = L::cz(i);
     pcol[j] = uint32_t(bx) * uint32_t(NC * B::kComp) + B::run(c, i) + (at_end ? kW * esz - 16u : 0u);
@@ -338,20 +376,15 @@ __global__ void __launch_bounds__(64 * kTY * NC) k_sweep_d3q19(const void* fin_v
       }
       sm.rho[rs][c][hrow][lane + 2] = led;
     }
-    if (lane < 4) {
-      const char* pieces = reinterpret_cast<const char*>(&sm.st[w].piece[0][0]);
-      const int xs = lane < 2 ? lane - 2 : kW + lane - 2;  // column - x0: -2, -1, 64, 65
+    if (lane < 8) {
+      const char* base = reinterpret_cast<const char*>(&sm.st[w].piece[0][0]) + hbase;
+      float led = 0.f;
 #pragma unroll
-      for (int pass = 0; pass < 2; ++pass) {
-        float f[19], led = 0.f;
-#pragma unroll
-        for (int i = 0; i < 19; ++i) {
-          const float v = piece_value(pieces + pass * kPiecesPerRow * 16, i, xs - L::cx(i));
-          led = i == 0 ? v : led + v;
-          f[i] = v;
-        }
-        sm.rho[rs][c][2 * r + pass][xcol_lds] = led;
+      for (int i = 0; i < 19; ++i) {
+        const float v = *reinterpret_cast<const float*>(base + 16 * left_slot(i) - 4 * L::cx(i));
+        led = i == 0 ? v : led + v;
       }
+      sm.rho[rs][c][2 * r + hpass][xcol_lds] = led;
     }
   };
 
@@ -453,16 +486,17 @@ __global__ void __launch_bounds__(64 * kTY * NC) k_sweep_d3q19(const void* fin_v
   potentials(za - 1);
   potentials(za);
 
-  // ---- iterations: potentials of plane zc + 1; plane zc + 3 is loaded into
-  // X before the stores of the collision of plane zc (D0), and consumed into
-  // D2 after them, so that the waits for X leave exactly those stores in
-  // flight (X is never in flight at the top of the loop)
+  // ---- iterations: plane zc + 3 is loaded into X first, so that its loads
+  // are in flight during the potentials of plane zc + 1 and the collision of
+  // plane zc (D0), and consumed into D2 after that collision's stores, so
+  // that the waits for X leave exactly those stores in flight (X is never in
+  // flight at the top of the loop)
   for (int k = 0; k < nplanes; ++k) {
     const int zc = za + k;
+    issue(zc + 3, X);
     lds_barrier();
     potentials(zc + 1);
     lds_barrier();
-    issue(zc + 3, X);
     collide_store(zc, D0, L0);
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
