@@ -48,7 +48,6 @@ KERNEL_SOURCES = {
 }
 KERNEL_NAMES = {("D2Q9", "sweep"): "k_sweep_d2q9", ("D2Q9", "tile"): "k_fused_d2q9",
                 ("D3Q19", "sweep"): "k_sweep_d3q19"}
-# bytes of one stored population: (rest slot, moving slot)
 # bytes per site and component: (rest slot, moving slot, reference)
 STORE_BYTES = {"f64": (8, 8, 0), "f32": (4, 4, 0), "f16s": (4, 2, 2)}
 

@@ -8,19 +8,22 @@
 // z + 1 and the densities of planes z - 1 .. z + 1; h of plane z + 1 needs
 // the Laplacian of the densities, so densities run two planes ahead of the
 // collision.  One iteration, for the collision of plane zc:
-//   1. every wave pulls the 19 populations of its unit in plane zc + 2 into
-//      registers (decoded), writes the unit's density and first moments to
-//      LDS rings, and keeps the populations: each wave holds three planes of
-//      its unit (zc, zc + 1, zc + 2), so each population is loaded once;
-//      it also sums the densities of one unit of the two halo rows above and
-//      below the pencil and of 8 sites of the halo columns (two on either
-//      side), which the neighbouring pencils load as their own (mostly L2
-//      hits);
+//   1. every wave issues the loads of its unit in plane zc + 3 (and those of
+//      the halo pieces of plane zc + 4, a plane earlier than the rest: they
+//      are scattered over many cache lines and land last), and writes the
+//      first moments of its unit in plane zc to LDS;
 //   2. (barrier) chemical potentials and h of plane zc + 1 on the rows and
 //      columns the force stencil reaches, into an LDS ring;
 //   3. (barrier) force, equilibrium, forcing term and collision of plane zc
 //      from the registers; non-temporal stores in place (the next step's pull
-//      streams them).
+//      streams them);
+//   4. the 19 populations of plane zc + 3 land in registers; the wave writes
+//      their density to an LDS ring and keeps them: each wave holds three
+//      planes of its unit (zc + 1 .. zc + 3 after the step), so each
+//      population is loaded once.  It also sums the densities of one unit of
+//      the two halo rows above and below the pencil and of 8 sites of the
+//      halo columns (two on either side), which the neighbouring pencils load
+//      as their own (mostly L2 hits).
 // Each site's arithmetic is the split path's (the same physics.hpp functions
 // with the same operands in the same order), so the two agree bit for bit.
 // Workgroups are banded per XCD so that neighbouring pencils share an L2.
@@ -41,7 +44,7 @@ constexpr int kW = 64;          // pencil width = block width = wave size
 constexpr int kTY = 4;          // rows per pencil
 constexpr int kRP = 5;          // density planes in LDS (zc - 2 .. zc + 2 live)
 constexpr int kHP = 3;          // h planes in LDS (zc - 1 .. zc + 1 live)
-constexpr int kJP = 4;          // first-moment planes in LDS (zc - 1 .. zc + 2 live)
+constexpr int kJP = 2;          // first-moment planes in LDS (zc and zc + 1 live)
 constexpr int kRR = kTY + 4;    // density rows: y0 - 2 .. y0 + kTY + 1
 constexpr int kRC = kW + 4;     // density columns: x0 - 2 .. x0 + 65
 constexpr int kHR = kTY + 2;    // h rows: y0 - 1 .. y0 + kTY
@@ -142,12 +145,12 @@ __device__ __forceinline__ void piece_of(int idx, int& i, int& kind) {
   }
 }
 
-// Per-wave staging of one plane, filled by direct global-to-LDS loads one
-// plane ahead: the halo-row unit (19 pulled values per lane) and the
-// halo-column pieces.
+// Per-wave staging, filled by direct global-to-LDS loads: the halo-row unit
+// of one plane (19 pulled values per lane) and the halo-column pieces of two
+// planes (by parity of the plane).
 struct Stage {
   uint32_t unit[19][kW];
-  uint32_t piece[kPieces][4];
+  uint32_t piece[2][kPieces][4];
 };
 
 template <class S, int NC>
@@ -201,9 +204,6 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const void* base, ui
 __device__ __forceinline__ float load_slot32(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, 0));
 }
-
-template <int V>
-using I = std::integral_constant<int, V>;
 
 // 16 bytes per lane from byte offset voff of the buffer into LDS at dst +
 // 16 lane (a direct load: no registers hold the data in flight).  Kept out
@@ -306,11 +306,26 @@ __global__ void __launch_bounds__(64 * kTY * NC) k_sweep_d3q19(const void* fin_v
   // that every set keeps one place in registers.
   float X[19], D0[19], D1[19], D2[19], L0 = 0.f, L1 = 0.f, L2 = 0.f;
 
-  // Issue the loads of virtual plane z: the halo-row unit and the
-  // halo-column pieces into this wave's staging, then the own unit into
-  // register set Pn.  Exactly 19 vector memory loads follow the staging
-  // loads (the own unit's), so a wait for at most 19 operations in flight
-  // covers the staging whatever follows.
+  // The halo-column pieces of virtual plane z into this wave's staging (by
+  // parity of z).
+  auto issue_pieces = [&](int z) __attribute__((always_inline)) {
+    const int zw = wrap_mod(z, p.nz);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      if (j * kW + lane < kPieces) {
+        const int yr = wrap_mod(y0 - 2 + 2 * r + prow[j], p.ny);
+        load_lds16(fin, stg + (19 * kW * 4 + (z & 1) * kPieces * 16 + j * kW * 16),
+                   rowb(yr, zw, pdy[j], pdz[j]) + pcol[j]);
+      }
+    }
+  };
+
+  // Issue the loads of virtual plane z: the halo-row unit into this wave's
+  // staging, the own unit into register set Pn, then the pieces of plane
+  // z + 1 (those of plane z were issued with plane z - 1).  Exactly 21 vector
+  // memory operations follow the halo-row unit's loads before consume(z)
+  // waits for them (the own unit's and the two of the next pieces), and the
+  // pieces of plane z precede them: one wait covers both.
   auto issue = [&](int z, float (&Pn)[19]) __attribute__((always_inline)) {
     const int zw = wrap_mod(z, p.nz);
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // this wave's reads of the staging are done
@@ -318,27 +333,37 @@ __global__ void __launch_bounds__(64 * kTY * NC) k_sweep_d3q19(const void* fin_v
     for (int i = 0; i < 19; ++i)
       __builtin_amdgcn_raw_ptr_buffer_load_lds(fin, stg + i * (kW * 4), 4, col_off(lp_own, i),
                                                rowb(y_halo, zw, L::cy(i), L::cz(i)) + B::run(c, i), 0, 0);
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      if (j * kW + lane < kPieces) {
-        const int yr = wrap_mod(y0 - 2 + 2 * r + prow[j], p.ny);
-        load_lds16(fin, stg + (19 * kW * 4 + j * kW * 16), rowb(yr, zw, pdy[j], pdz[j]) + pcol[j]);
-      }
-    }
-    asm volatile("" ::: "memory");  // the own unit's loads after the staging loads
+    asm volatile("" ::: "memory");  // the own unit's loads after the halo-row unit's
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
       const uint32_t so = rowb(y_own, zw, L::cy(i), L::cz(i)) + B::run(c, i);
       const uint32_t vo = i == 0 ? lp_own.rest : lp_own.move[L::cx(i) + 1];
       Pn[i] = load_slot32(fin, vo, so);
     }
+    asm volatile("" ::: "memory");  // the next pieces after the own unit's loads
+    issue_pieces(z + 1);
   };
 
-  // Step 1 for virtual plane z, loads issued by issue(z, Xr): densities of
-  // the own unit (decoded from Xr into Dd, with its ledger Ld, and when keep
-  // its first moments), of the halo-row unit and of the halo-column sites.
-  auto consume = [&](int z, const float (&Xr)[19], float (&Dd)[19], float& Ld, bool keep)
-                     __attribute__((always_inline)) {
+  // First moments of this wave's unit in virtual plane z from its populations
+  // f, into the LDS ring.
+  auto moments = [&](int z, const float (&f)[19]) __attribute__((always_inline)) {
+    float ax = 0.f, ay = 0.f, az = 0.f;
+#pragma unroll
+    for (int i = 1; i < 19; ++i) {
+      if (L::cx(i)) ax += T(L::cx(i)) * f[i];
+      if (L::cy(i)) ay += T(L::cy(i)) * f[i];
+      if (L::cz(i)) az += T(L::cz(i)) * f[i];
+    }
+    const int js = slot<kJP>(z, za);
+    sm.j[js][0][c][r][lane] = ax;
+    sm.j[js][1][c][r][lane] = ay;
+    sm.j[js][2][c][r][lane] = az;
+  };
+
+  // Step 4 for virtual plane z, loads issued by issue(z, Xr): densities of
+  // the own unit (decoded from Xr into Dd, with its ledger Ld), of the
+  // halo-row unit and of the halo-column sites.
+  auto consume = [&](int z, const float (&Xr)[19], float (&Dd)[19], float& Ld) __attribute__((always_inline)) {
     const int rs = slot<kRP>(z, za);
     {
       float led = 0.f;
@@ -350,34 +375,20 @@ __global__ void __launch_bounds__(64 * kTY * NC) k_sweep_d3q19(const void* fin_v
       }
       sm.rho[rs][c][r + 2][lane + 2] = led;
       Ld = led;
-      if (keep) {
-        float ax = 0.f, ay = 0.f, az = 0.f;
-#pragma unroll
-        for (int i = 1; i < 19; ++i) {
-          if (L::cx(i)) ax += T(L::cx(i)) * Dd[i];
-          if (L::cy(i)) ay += T(L::cy(i)) * Dd[i];
-          if (L::cz(i)) az += T(L::cz(i)) * Dd[i];
-        }
-        const int js = slot<kJP>(z, za);
-        sm.j[js][0][c][r][lane] = ax;
-        sm.j[js][1][c][r][lane] = ay;
-        sm.j[js][2][c][r][lane] = az;
-      }
     }
-    wait_vm<19>();  // the staging loads have landed
+    wait_vm<21>();  // the halo-row unit and the pieces of plane z have landed
     const uint32_t* su = reinterpret_cast<const uint32_t*>(&sm.st[w].unit[0][0]);
     {
-      float f[19], led = 0.f;
+      float led = 0.f;
 #pragma unroll
       for (int i = 0; i < 19; ++i) {
         const float v = __builtin_bit_cast(float, su[i * kW + lane]);
         led = i == 0 ? v : led + v;
-        f[i] = v;
       }
       sm.rho[rs][c][hrow][lane + 2] = led;
     }
     if (lane < 8) {
-      const char* base = reinterpret_cast<const char*>(&sm.st[w].piece[0][0]) + hbase;
+      const char* base = reinterpret_cast<const char*>(&sm.st[w].piece[z & 1][0][0]) + hbase;
       float led = 0.f;
 #pragma unroll
       for (int i = 0; i < 19; ++i) {
@@ -472,16 +483,17 @@ __global__ void __launch_bounds__(64 * kTY * NC) k_sweep_d3q19(const void* fin_v
 
   // ---- prologue: densities of planes za - 2 .. za + 2 (the last three kept
   // in D0, D1 and D2), potentials of planes za - 1 and za
+  issue_pieces(za - 2);
   issue(za - 2, X);
-  consume(za - 2, X, D2, L2, false);
+  consume(za - 2, X, D2, L2);
   issue(za - 1, X);
-  consume(za - 1, X, D2, L2, false);
+  consume(za - 1, X, D2, L2);
   issue(za, X);
-  consume(za, X, D0, L0, true);
+  consume(za, X, D0, L0);
   issue(za + 1, X);
-  consume(za + 1, X, D1, L1, true);
+  consume(za + 1, X, D1, L1);
   issue(za + 2, X);
-  consume(za + 2, X, D2, L2, true);
+  consume(za + 2, X, D2, L2);
   lds_barrier();
   potentials(za - 1);
   potentials(za);
@@ -494,6 +506,7 @@ __global__ void __launch_bounds__(64 * kTY * NC) k_sweep_d3q19(const void* fin_v
   for (int k = 0; k < nplanes; ++k) {
     const int zc = za + k;
     issue(zc + 3, X);
+    moments(zc, D0);
     lds_barrier();
     potentials(zc + 1);
     lds_barrier();
@@ -505,7 +518,7 @@ __global__ void __launch_bounds__(64 * kTY * NC) k_sweep_d3q19(const void* fin_v
     }
     L0 = L1;
     L1 = L2;
-    consume(zc + 3, X, D2, L2, true);
+    consume(zc + 3, X, D2, L2);
   }
 }
 
