@@ -321,12 +321,13 @@ __global__ void __launch_bounds__(64 * kTY * NC) k_sweep_d3q19(const void* fin_v
   };
 
   // Issue the loads of virtual plane z: the halo-row unit into this wave's
-  // staging, the own unit into register set Pn, then the pieces of plane
-  // z + 1 (those of plane z were issued with plane z - 1).  Exactly 21 vector
-  // memory operations follow the halo-row unit's loads before consume(z)
-  // waits for them (the own unit's and the two of the next pieces), and the
-  // pieces of plane z precede them: one wait covers both.
-  auto issue = [&](int z, float (&Pn)[19]) __attribute__((always_inline)) {
+  // staging, the own unit into register set Pn, then (in the prologue) the
+  // pieces of plane z + 1; in the iterations those follow later (see there).
+  // Exactly 21 vector memory operations follow the halo-row unit's loads
+  // before consume(z) waits for them (the own unit's and the two of the next
+  // pieces, in the iterations also 19 stores of which 19 are allowed in
+  // flight), and the pieces of plane z precede them: one wait covers both.
+  auto issue = [&](int z, float (&Pn)[19], bool next_pieces) __attribute__((always_inline)) {
     const int zw = wrap_mod(z, p.nz);
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // this wave's reads of the staging are done
 #pragma unroll
@@ -340,8 +341,10 @@ __global__ void __launch_bounds__(64 * kTY * NC) k_sweep_d3q19(const void* fin_v
       const uint32_t vo = i == 0 ? lp_own.rest : lp_own.move[L::cx(i) + 1];
       Pn[i] = load_slot32(fin, vo, so);
     }
-    asm volatile("" ::: "memory");  // the next pieces after the own unit's loads
-    issue_pieces(z + 1);
+    if (next_pieces) {
+      asm volatile("" ::: "memory");  // the next pieces after the own unit's loads
+      issue_pieces(z + 1);
+    }
   };
 
   // First moments of this wave's unit in virtual plane z from its populations
@@ -484,15 +487,15 @@ __global__ void __launch_bounds__(64 * kTY * NC) k_sweep_d3q19(const void* fin_v
   // ---- prologue: densities of planes za - 2 .. za + 2 (the last three kept
   // in D0, D1 and D2), potentials of planes za - 1 and za
   issue_pieces(za - 2);
-  issue(za - 2, X);
+  issue(za - 2, X, true);
   consume(za - 2, X, D2, L2);
-  issue(za - 1, X);
+  issue(za - 1, X, true);
   consume(za - 1, X, D2, L2);
-  issue(za, X);
+  issue(za, X, true);
   consume(za, X, D0, L0);
-  issue(za + 1, X);
+  issue(za + 1, X, true);
   consume(za + 1, X, D1, L1);
-  issue(za + 2, X);
+  issue(za + 2, X, true);
   consume(za + 2, X, D2, L2);
   lds_barrier();
   potentials(za - 1);
@@ -502,14 +505,19 @@ __global__ void __launch_bounds__(64 * kTY * NC) k_sweep_d3q19(const void* fin_v
   // are in flight during the potentials of plane zc + 1 and the collision of
   // plane zc (D0), and consumed into D2 after that collision's stores, so
   // that the waits for X leave exactly those stores in flight (X is never in
-  // flight at the top of the loop)
+  // flight at the top of the loop).  The pieces of plane zc + 4 are issued
+  // between the potentials and the collision: half an iteration before the
+  // neighbouring pencils load the blocks they come from (at the top of the
+  // next iteration), so those lines are mostly still in L2 then, and an
+  // iteration and a half before they are read.
   for (int k = 0; k < nplanes; ++k) {
     const int zc = za + k;
-    issue(zc + 3, X);
+    issue(zc + 3, X, false);
     moments(zc, D0);
     lds_barrier();
     potentials(zc + 1);
     lds_barrier();
+    issue_pieces(zc + 4);
     collide_store(zc, D0, L0);
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
