@@ -420,10 +420,6 @@ __global__ void __launch_bounds__(64 * kTY * NC) k_sweep_d3q19(const void* fin_v
               return sm.rho[sz][k][pr + L::cy(i)][pc + L::cx(i)];
             },
             rr[k]);
-        // one component's 18 LDS reads at a time: issued together for all
-        // components they would hold 18 N registers next to the planes of
-        // populations
-        asm volatile("" ::: "memory");
       }
       site_potential<T, NC>(p, rr, lap, mu, hh);
 #pragma unroll
@@ -476,12 +472,16 @@ __global__ void __launch_bounds__(64 * kTY * NC) k_sweep_d3q19(const void* fin_v
     const T jx = sm.j[js][0][c][r][lane], jy = sm.j[js][1][c][r][lane], jz = sm.j[js][2][c][r][lane];
     collide<3, T>(f, rs, ux, uy, uz, Ax, Ay, Az, jx * inv_rs, jy * inv_rs, jz * inv_rs, p.inv_tau);
     // non-temporal buffer stores (policy bit nt): the row and run part of
-    // each slot's offset in an SGPR, the lane's column part in a VGPR
+    // each slot's offset in an SGPR, the lane's column part in a VGPR.  The
+    // wave issues them at raised priority, ahead of the other waves'
+    // arithmetic, so that the stores of a plane leave the CU together.
     const uint32_t row = rowb(y_own, zw, 0, 0);
+    __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int i = 0; i < 19; ++i)
       __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, f[i]), fout, lp_own.rest,
                                             row + B::run(c, i), 2);
+    __builtin_amdgcn_s_setprio(0);
   };
 
   // ---- prologue: densities of planes za - 2 .. za + 2 (the last three kept
