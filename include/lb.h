@@ -88,7 +88,8 @@ typedef enum lb_force_form { LB_FORCE_LOG = 0, LB_FORCE_EXPANDED = 1 } lb_force_
  *   LB_PATH_AUTO:  the fastest path that supports the run (sweep, then tile,
  *                  then split).
  *   LB_PATH_TILE:  fused one-kernel D2Q9 step over 2-D tiles with a two-site
- *                  density halo (any nx, every storage, periodic box).
+ *                  density halo (any nx, every storage, periodic box or
+ *                  walls).
  *   LB_PATH_SPLIT: three kernels per step (density, potential, collide and
  *                  stream); every lattice, periodic box or walls.
  *   LB_PATH_SWEEP: fused one-kernel step that sweeps the box: on D2Q9
@@ -126,7 +127,8 @@ typedef struct lb_params {
                             reversed (no slip; every component's mass kept), and
                             the density and potential stencils mirror the layer
                             next to the wall (zero normal gradient, a wall that
-                            favours no component).  LB_PATH_SPLIT only.        */
+                            favours no component).  LB_PATH_SPLIT, and
+                            LB_PATH_TILE on D2Q9 (the same values bit for bit). */
   int32_t reserved;      /* 0                                                     */
 } lb_params;
 

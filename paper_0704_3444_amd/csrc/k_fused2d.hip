@@ -79,23 +79,57 @@ __device__ __forceinline__ void gstore(void* base, uint32_t off, V v) {
     *d = v;
 }
 
+// Coordinate of the site whose values stand at coordinate v of an axis of n
+// layers: periodic, or, on an axis closed by walls, the mirror image of the
+// layer next to the wall for the first two layers beyond it (zero normal
+// gradient of the stencils' fields, as on the split path); positions further
+// out (only in ragged tiles, where no site reads them) wrap, which keeps
+// every access inside the box.
+__device__ __forceinline__ int axis_site(int v, int n, bool wall) {
+  if (wall) v = v < 0 ? -1 - v : (v >= n ? 2 * n - 1 - v : v);
+  return wrap_mod(v, n);
+}
+
 // Byte offsets, without the component part, of the nine slots pulled into
 // site (x, y) (slot i of the site r - v_i) and, for the shifted codec, of
-// the references of those sites.
-template <class S>
+// the references of those sites.  Where r - v_i lies beyond a wall the slot
+// is -v_i of r itself (half-way bounce-back); its offset then also carries
+// the distance from run i to run -v_i (the same for every component), so
+// that adding run(c, i) lands on run(c, -v_i).
+template <class S, bool W>
 __device__ __forceinline__ void pull_offsets(const Params<typename S::T>& p, int x, int y, uint32_t (&off)[9],
                                              uint32_t (&roff)[9]) {
   using L = Lattice<2>;
   using B = BlockLayout<S, 9>;
   const int xm = wrap_add(x, -1, p.nx), xp = wrap_add(x, 1, p.nx);
   const int ym = wrap_add(y, -1, p.ny), yp = wrap_add(y, 1, p.ny);
+  if constexpr (!W) {  // periodic box
 #pragma unroll
-  for (int i = 0; i < L::Q; ++i) {
-    const int sx = L::cx(i) > 0 ? xm : (L::cx(i) < 0 ? xp : x);
-    const int sy = L::cy(i) > 0 ? ym : (L::cy(i) < 0 ? yp : y);
-    const uint32_t blk = block_off<S>(p, sx, sy);
-    off[i] = blk + B::in_run(i, sx);
-    roff[i] = blk + B::in_ref(sx);
+    for (int i = 0; i < L::Q; ++i) {
+      const int sx = L::cx(i) > 0 ? xm : (L::cx(i) < 0 ? xp : x);
+      const int sy = L::cy(i) > 0 ? ym : (L::cy(i) < 0 ? yp : y);
+      const uint32_t blk = block_off<S>(p, sx, sy);
+      off[i] = blk + B::in_run(i, sx);
+      roff[i] = blk + B::in_ref(sx);
+    }
+  } else {
+    const bool wx = p.walls & 1, wy = p.walls & 2;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+      int sx = L::cx(i) > 0 ? xm : (L::cx(i) < 0 ? xp : x);
+      int sy = L::cy(i) > 0 ? ym : (L::cy(i) < 0 ? yp : y);
+      uint32_t hop = 0;
+      if (i > 0) {
+        const int ux = x - L::cx(i), uy = y - L::cy(i);
+        const bool beyond = (wx && (ux < 0 || ux >= p.nx)) || (wy && (uy < 0 || uy >= p.ny));
+        sx = beyond ? x : sx;
+        sy = beyond ? y : sy;
+        hop = beyond ? B::run(0, L::opp(i)) - B::run(0, i) : 0u;
+      }
+      const uint32_t blk = block_off<S>(p, sx, sy);
+      off[i] = blk + B::in_run(i, sx) + hop;
+      roff[i] = blk + B::in_ref(sx);
+    }
   }
 }
 
@@ -133,12 +167,12 @@ __device__ __forceinline__ void pull_component(const void* __restrict__ fin, con
 // rho^sigma at (x, y) from the pulled slots: the sum of the decoded
 // populations in lattice order, or s times the exact pulled total for the
 // shifted codec (the same values as the split path's density kernel).
-template <class S, int NC>
+template <class S, int NC, bool W>
 __device__ __forceinline__ void pulled_density(const void* __restrict__ fin, const Params<typename S::T>& p, int x,
                                                int y, typename S::T (&rho)[NC]) {
   using T = typename S::T;
   uint32_t off[9], roff[9];
-  pull_offsets<S>(p, x, y, off, roff);
+  pull_offsets<S, W>(p, x, y, off, roff);
 #pragma unroll
   for (int k = 0; k < NC; ++k) {
     T v[9], sum = T(0);
@@ -159,8 +193,10 @@ struct TileLds {
 };
 
 // The whole step for the tile with corner (x0, y0).  Every thread of the
-// workgroup calls it (it contains workgroup barriers).
-template <class S, int NC, int TX, int TY, int NT, bool NTSTORE>
+// workgroup calls it (it contains workgroup barriers).  W: the box has walls
+// (p.walls != 0; a separate instantiation keeps the periodic step free of
+// the wall logic).
+template <class S, int NC, int TX, int TY, int NT, bool NTSTORE, bool W>
 __device__ __forceinline__ void tile_step(const void* __restrict__ fin, void* __restrict__ fout,
                                           const Params<typename S::T>& p, int x0, int y0,
                                           TileLds<typename S::T, NC, TX, TY>& lds) {
@@ -189,7 +225,7 @@ __device__ __forceinline__ void tile_step(const void* __restrict__ fin, void* __
     valid[k] = x < nx && y < ny;
     if (valid[k]) {
       uint32_t off[Q], roff[Q];
-      pull_offsets<S>(p, x, y, off, roff);
+      pull_offsets<S, W>(p, x, y, off, roff);
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         // one uniform branch per component, so that its loads are issued
@@ -230,7 +266,9 @@ __device__ __forceinline__ void tile_step(const void* __restrict__ fin, void* __
         px = TX + 2 + j % 2;
       }
       T r[NC];
-      pulled_density<S, NC>(fin, p, wrap_mod(x0 - 2 + px, nx), wrap_mod(y0 - 2 + py, ny), r);
+      pulled_density<S, NC, W>(fin, p, axis_site(x0 - 2 + px, nx, W && (p.walls & 1)),
+                               axis_site(y0 - 2 + py, ny, W && (p.walls & 2)),
+                            r);
 #pragma unroll
       for (int c = 0; c < NC; ++c) s_rho[c][py][px] = r[c];
     }
@@ -240,7 +278,9 @@ __device__ __forceinline__ void tile_step(const void* __restrict__ fin, void* __
       const bool inner = px >= 2 && px < TX + 2 && py >= 2 && py < TY + 2 && x0 + px - 2 < nx && y0 + py - 2 < ny;
       if (inner) continue;  // filled in phase A
       T r[NC];
-      pulled_density<S, NC>(fin, p, wrap_mod(x0 - 2 + px, nx), wrap_mod(y0 - 2 + py, ny), r);
+      pulled_density<S, NC, W>(fin, p, axis_site(x0 - 2 + px, nx, W && (p.walls & 1)),
+                               axis_site(y0 - 2 + py, ny, W && (p.walls & 2)),
+                            r);
 #pragma unroll
       for (int c = 0; c < NC; ++c) s_rho[c][py][px] = r[c];
     }
@@ -248,9 +288,19 @@ __device__ __forceinline__ void tile_step(const void* __restrict__ fin, void* __
   __syncthreads();
 
   // ---- C: potential h on the tile plus one ring ---------------------------
+  // (a position one layer beyond a wall takes h of the layer next to it,
+  // computed there from the same neighbours as on the split path)
   for (int idx = threadIdx.x; idx < GX * GY; idx += NT) {
     const int qx = idx % GX, qy = idx / GX;
-    const int cx = qx + 1, cy = qy + 1;  // position in the rho region
+    int cx = qx + 1, cy = qy + 1;  // position in the rho region
+    if (W && (p.walls & 1)) {
+      const int X = x0 - 1 + qx;
+      cx = X == -1 ? cx + 1 : (X == nx ? cx - 1 : cx);
+    }
+    if (W && (p.walls & 2)) {
+      const int Y = y0 - 1 + qy;
+      cy = Y == -1 ? cy + 1 : (Y == ny ? cy - 1 : cy);
+    }
     T r[NC], lap[NC], mu[NC], h[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -323,7 +373,7 @@ __device__ __forceinline__ void tile_step(const void* __restrict__ fin, void* __
   }
 }
 
-template <class S, int NC, int TX, int TY, int NT, bool NTSTORE>
+template <class S, int NC, int TX, int TY, int NT, bool NTSTORE, bool W>
 __global__ void __launch_bounds__(NT) k_fused_d2q9(const void* __restrict__ fin, void* __restrict__ fout,
                                                    Params<typename S::T> p, int nbx, int ntiles, int tiles_per_xcd,
                                                    int xcd_remap) {
@@ -333,7 +383,7 @@ __global__ void __launch_bounds__(NT) k_fused_d2q9(const void* __restrict__ fin,
   const int b = blockIdx.x;
   const int t = xcd_remap ? (b % kXcds) * tiles_per_xcd + b / kXcds : b;
   if (t >= ntiles) return;
-  tile_step<S, NC, TX, TY, NT, NTSTORE>(fin, fout, p, (t % nbx) * TX, (t / nbx) * TY, lds);
+  tile_step<S, NC, TX, TY, NT, NTSTORE, W>(fin, fout, p, (t % nbx) * TX, (t / nbx) * TY, lds);
 }
 
 // ---------------------------------------------------------- batched ----
@@ -366,7 +416,7 @@ __global__ void __launch_bounds__(NT) k_batch_d2q9(const BatchSlot<typename S::T
     if (t >= sl.t_end) continue;  // uniform: the whole workgroup skips
     const int tile = w - sl.first_item;
     const int x0 = (tile % sl.tiles_x) * TX, y0 = (tile / sl.tiles_x) * TY;
-    tile_step<S, NC, TX, TY, NT, true>(sl.f[t & 1], sl.f[(t + 1) & 1], sl.p, x0, y0, lds);
+    tile_step<S, NC, TX, TY, NT, true, false>(sl.f[t & 1], sl.f[(t + 1) & 1], sl.p, x0, y0, lds);  // periodic runs
     __syncthreads();  // the next tile reuses the LDS
   }
 }
@@ -447,7 +497,11 @@ static void launch_tile(const Params<typename S::T>& p, const void* fin, void* f
   const int ntiles = nbx * nby;
   const int per_xcd = (ntiles + kXcds - 1) / kXcds;
   const int grid = remap ? per_xcd * kXcds : ntiles;
-  k_fused_d2q9<S, NC, TX, TY, NT, NTSTORE><<<grid, NT, 0, stream>>>(fin, fout, p, nbx, ntiles, per_xcd, remap);
+  if (p.walls)
+    k_fused_d2q9<S, NC, TX, TY, NT, NTSTORE, true><<<grid, NT, 0, stream>>>(fin, fout, p, nbx, ntiles, per_xcd, remap);
+  else
+    k_fused_d2q9<S, NC, TX, TY, NT, NTSTORE, false><<<grid, NT, 0, stream>>>(fin, fout, p, nbx, ntiles, per_xcd,
+                                                                            remap);
 }
 
 template <class S, int NC, int TX, int TY>

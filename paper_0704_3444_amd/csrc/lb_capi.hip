@@ -366,10 +366,13 @@ int init_impl(const lb_params* p, const double* rho0, void* workspace, size_t wo
   fill_params(p, &c.pd);
   c.pf.sh = c.pd.sh = shift_ref_of(p, rho0, S);
 
-  // the fused kernels address one population copy with 32-bit byte offsets
-  // (walls: the split path only)
-  const bool small = fbytes < (size_t(1) << 32) && p->walls == 0;
-  lbm::FusedStepFn tile = small ? lbm::fused_step_for(p->lattice, p->storage, p->n_comp) : nullptr;
+  // the fused kernels address one population copy with 32-bit byte offsets;
+  // walls: the D2Q9 tile kernel and the split path
+  const bool fits = fbytes < (size_t(1) << 32);
+  const bool small = fits && p->walls == 0;
+  lbm::FusedStepFn tile = fits && (p->walls == 0 || p->lattice == LB_D2Q9)
+                              ? lbm::fused_step_for(p->lattice, p->storage, p->n_comp)
+                              : nullptr;
   lbm::FusedStepFn sweep =
       small && p->lattice == LB_D2Q9 && p->nx % 64 == 0 ? lbm::sweep_step_for(p->storage, p->n_comp) : nullptr;
   if (small && p->lattice == LB_D3Q19 && p->nx % 64 == 0 && p->ny % 4 == 0)

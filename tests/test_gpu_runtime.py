@@ -231,7 +231,7 @@ def test_every_slot_written_each_step(case):
     elif case == "walls":
         cfg, rho0 = LI.ternary_immersion(37, ny=23)
         cfg = dict(cfg, walls=0b011)
-        combos = [("split", st) for st in storages("split")]
+        combos = [(p, st) for p in ("split", "tile") for st in storages(p)]
     else:
         cfg, rho0, _ = LI.binodal_runs("ternary_monomer")[9]
         combos = [("lines", "f64"), ("lines", "f32")]

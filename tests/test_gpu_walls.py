@@ -1,6 +1,7 @@
-"""Walls (not in the paper; lb_params.walls) on the split path against the
-oracle's walls, every lattice and storage, and the paths and groups that
-refuse them.  The oracle's walls are pinned by tests/test_oracle_walls.py."""
+"""Walls (not in the paper; lb_params.walls) on the split path and the D2Q9
+tile kernel against the oracle's walls, every lattice and storage, the two
+paths against each other bit for bit, and the paths and groups that refuse
+them.  The oracle's walls are pinned by tests/test_oracle_walls.py."""
 import numpy as np
 import pytest
 
@@ -25,21 +26,25 @@ def walled(lattice, shape, walls, n, seed):
     return cfg, LI.noisy_uniform(cfg, [1.0 / n] * n, 0.1 / n, seed)
 
 
+# (case, path): the split path everywhere, the tile kernel on D2Q9
+PATH_CASES = [(k, "split") for k in range(len(CASES))] + [(k, "tile") for k, c in enumerate(CASES) if c[0] == "D2Q9"]
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32"])
-@pytest.mark.parametrize("case", range(len(CASES)))
-def test_walls_match_oracle(case, storage):
+@pytest.mark.parametrize("case,path", PATH_CASES, ids=[f"{CASES[k][0]}-{k}-{pth}" for k, pth in PATH_CASES])
+def test_walls_match_oracle(case, path, storage):
     lattice, shape, walls, n = CASES[case]
     cfg, rho0 = walled(lattice, shape, walls, n, 40 + case)
-    g = run_gpu(cfg, rho0, 200, storage=storage, path="auto")
-    assert g["path"] == "split"
+    g = run_gpu(cfg, rho0, 200, storage=storage, path=path)
+    assert g["path"] == path
     o = run_oracle(cfg, rho0, 200)
     e = errors(g, o, cfg["theta"], lattice=lattice)
-    print(f"[walls] {lattice} {shape} walls={walls:03b} {storage}: {e}", flush=True)
+    print(f"[walls] {lattice} {shape} walls={walls:03b} {storage} {path}: {e}", flush=True)
     for k in ("rho", "f", "U_cs", "mu", "mom"):
         assert e[k] < TOL[storage], (k, e)
     assert e["mass"] < (1e-13 if storage == "f64" else 1e-6), e
     es = errors(g, oracle_observe_of(cfg, rho0, g["f"]), cfg["theta"], lattice=lattice)
-    print(f"[walls] {lattice} {shape} walls={walls:03b} {storage} same-state observables: {es}", flush=True)
+    print(f"[walls] {lattice} {shape} walls={walls:03b} {storage} {path} same-state observables: {es}", flush=True)
     for k in ("rho", "U", "mu", "P", "mom", "mass"):
         assert es[k] < SAME_STATE_TOL, (k, es)
 
@@ -60,6 +65,29 @@ def test_walls_shifted_fp16_match_oracle(case):
         assert v < 1.0, (k, r)
 
 
+# D2Q9 boxes for the tile kernel with walls: several tiles with ragged
+# edges, a box smaller than one tile, tile-multiple sides, each wall set
+TILE_WALL_BOXES = [((150, 40), 0b11, 3), ((37, 23), 0b11, 2), ((64, 32), 0b10, 3), ((130, 70), 0b01, 2),
+                   ((128, 48), 0b11, 1), ((2, 19), 0b01, 2)]
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16s"])
+@pytest.mark.parametrize("shape,walls,n", TILE_WALL_BOXES,
+                         ids=[f"{s[0]}x{s[1]}-w{w:02b}-N{n}" for s, w, n in TILE_WALL_BOXES])
+def test_walls_tile_equals_split(shape, walls, n, storage):
+    """The tile kernel with walls against the split path, bit for bit: the
+    bounce-back pulls, the mirrored density ring and the potential one layer
+    beyond a wall (taken from the layer next to it) give the split path's
+    values in the same order; auto picks the tile kernel."""
+    cfg, rho0 = walled("D2Q9", shape, walls, n, 70 + n + walls)
+    a = run_gpu(cfg, rho0, 37, storage=storage, path="split")
+    b = run_gpu(cfg, rho0, 37, storage=storage, path="auto")
+    assert b["path"] == "tile"
+    print(f"[walls-tile] {shape} walls={walls:02b} N={n} {storage}: max |df| {np.abs(a['f'] - b['f']).max():.3e}",
+          flush=True)
+    assert np.array_equal(a["f"], b["f"])
+
+
 def test_walls_keep_mass_in_shifted_fp16():
     cfg, rho0 = walled("D2Q9", (48, 32), 0b011, 3, 50)
     g = run_gpu(cfg, rho0, 500, storage="f16s", path="auto", fields=True)
@@ -72,9 +100,13 @@ def test_walls_refused_where_not_built():
     from paper_0704_3444_amd.lb import LB_EINVAL, LB_ENOTSUP
 
     cfg, rho0 = walled("D2Q9", (64, 32), 0b010, 2, 60)
+    with pytest.raises(LBError) as ei:
+        Simulation(cfg, rho0, storage="f32", path="sweep")
+    assert ei.value.code == LB_ENOTSUP
+    c3, r3 = walled("D3Q19", (64, 8, 6), 0b100, 2, 61)
     for path in ("tile", "sweep"):
         with pytest.raises(LBError) as ei:
-            Simulation(cfg, rho0, storage="f32", path=path)
+            Simulation(c3, r3, storage="f32", path=path)
         assert ei.value.code == LB_ENOTSUP
     with pytest.raises(LBError) as ei:
         Simulation(dict(cfg, walls=0b100), rho0)  # D2Q9 has no z axis
@@ -102,6 +134,7 @@ def test_immersion_film_on_a_wall():
     cfg, rho0 = LI.ternary_immersion(128, ny=32)
     cfg = dict(cfg, walls=0b001)
     g = run_gpu(cfg, rho0, 100, storage="f32", path="auto")
+    assert g["path"] == "tile"
     o = run_oracle(cfg, rho0, 100)
     e = errors(g, o, cfg["theta"])
     print(f"[walls] immersion film on a wall, 100 steps, f32: {e}", flush=True)
