@@ -325,7 +325,7 @@ __global__ void __launch_bounds__(256) k_sweep_d2q9(const void* fin_v, void* fou
           },
           rr[c]);
     }
-    site_potential<T, NC>(p, rr, lap, mu, hh);
+    site_potential<T, NC, true>(p, rr, lap, mu, hh);  // instantiated for N itself
     const int sh = hslot(r);
 #pragma unroll
     for (int c = 0; c < NC; ++c) s_h[sh][c][q] = hh[c];

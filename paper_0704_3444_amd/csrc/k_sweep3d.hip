@@ -421,7 +421,7 @@ __global__ void __launch_bounds__(64 * kTY * NC) k_sweep_d3q19(const void* fin_v
             },
             rr[k]);
       }
-      site_potential<T, NC>(p, rr, lap, mu, hh);
+      site_potential<T, NC, true>(p, rr, lap, mu, hh);  // instantiated for N itself
 #pragma unroll
       for (int k = 0; k < NC; ++k) sm.h[hs][k][hr][hc] = hh[k];
     }

@@ -129,7 +129,7 @@ __global__ void __launch_bounds__(64) k_lines(const Run<typename S::T>* __restri
         r[k] = rho[k][j];
         lap[k] = lattice_laplacian<1, T>([&](int i) { return i == 1 ? rr[k][j] : rl[k][j]; }, r[k]);
       }
-      site_potential<T, NC>(p, r, lap, mu, hs);
+      site_potential<T, NC, true>(p, r, lap, mu, hs);  // a group has one N, NC
 #pragma unroll
       for (int k = 0; k < NC; ++k) h[k][j] = hs[k];
     }

@@ -77,10 +77,12 @@ __device__ __forceinline__ double fma_(double a, double b, double c) { return __
 //          - kappa lap^s
 //   h^s  = mu^s - ln(rho^s)/3   (log form)   or   mu^s   (expanded form)
 // NC is the compile-time component count (n <= NC; entries >= n are ignored).
-template <typename T, int NC>
+// EXACT: the caller is instantiated for n itself (n == NC), which removes
+// the run-time guards and their branches; the arithmetic is the same.
+template <typename T, int NC, bool EXACT = false>
 __device__ __forceinline__ void site_potential(const Params<T>& p, const T (&rho)[NC],
                                                const T (&lap)[NC], T (&mu)[NC], T (&h)[NC]) {
-  const int n = p.n;
+  const int n = EXACT ? NC : p.n;
   T rt = T(0);
 #pragma unroll
   for (int s = 0; s < NC; ++s)
