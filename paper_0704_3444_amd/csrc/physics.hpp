@@ -180,26 +180,25 @@ __device__ __forceinline__ void collide(T (&f)[Lattice<LAT>::Q], T rho, T ux, T 
   const T keep = T(1) - inv_tau;
   const T uu = L::D == 3 ? fma_(uz, uz, fma_(uy, uy, ux * ux)) : (L::D == 2 ? fma_(uy, uy, ux * ux) : ux * ux);
   const T Aus = L::D == 3 ? fma_(Az, usz, fma_(Ay, usy, Ax * usx)) : (L::D == 2 ? fma_(Ay, usy, Ax * usx) : Ax * usx);
-  const T base = fma_(T(-1.5), uu, T(1));
+  // the rate folded into the equilibrium's coefficients once per site:
+  //   G_even = (rho w / tau) [1 - 3/2 u.u + 9/2 (v.u)^2] - 3 w A.us + 9 w (v.A)(v.us)
+  //   G_odd  = (rho w / tau) 3 v.u + 3 w v.A
+  const T t_base = inv_tau * fma_(T(-1.5), uu, T(1));
+  const T t_sq = inv_tau * T(4.5), t_lin = inv_tau * T(3);
   T defect = T(0);
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
     if (L::opp(i) < i) continue;
     const int j = L::opp(i);
     // per weight value (the compiler forms these once per distinct w)
-    const T w = T(L::w(i));
-    const T wr = w * rho;
-    const T e_even0 = wr * base, e_even2 = wr * T(4.5), e_odd1 = wr * T(3);
-    const T F_even0 = T(-3.0 * L::w(i)) * Aus;
+    const T wr = T(L::w(i)) * rho;
+    const T a_sq = wr * t_sq, a_lin = wr * t_lin;
+    const T a_0 = fma_(wr, t_base, T(-3.0 * L::w(i)) * Aus);
     const T vu = vdot<LAT, T>(i, ux, uy, uz);
     const T vA = vdot<LAT, T>(i, Ax, Ay, Az);
     const T vus = vdot<LAT, T>(i, usx, usy, usz);
-    const T e_even = fma_(e_even2, vu * vu, e_even0);
-    const T e_odd = e_odd1 * vu;
-    const T F_even = fma_(T(9.0 * L::w(i)) * vA, vus, F_even0);
-    const T F_odd = T(3.0 * L::w(i)) * vA;
-    const T G_even = fma_(inv_tau, e_even, F_even);
-    const T G_odd = fma_(inv_tau, e_odd, F_odd);
+    const T G_even = fma_(a_sq, vu * vu, fma_(T(9.0 * L::w(i)) * vA, vus, a_0));
+    const T G_odd = fma_(a_lin, vu, T(3.0 * L::w(i)) * vA);
     const T post_i = fma_(keep, f[i], G_even + G_odd);
     const T post_j = fma_(keep, f[j], G_even - G_odd);
     defect += f[i] - post_i;
@@ -212,15 +211,17 @@ __device__ __forceinline__ void collide(T (&f)[Lattice<LAT>::Q], T rho, T ux, T 
 
 // Stencils, written once so that every kernel forms them in the same order.
 // `g(i)` returns the field at r + v_i.
-//   lap g   = 6 sum_{i>0} w_i (g(r + v_i) - g(r))
+//   lap g   = 6 sum_{i>0} w_i (g(r + v_i) - g(r)) = 6 sum_{i>0} w_i g(r + v_i) - 6 W g(r),
+//             W = sum_{i>0} w_i = 1 - w_0 (formed the second way: one FMA per neighbour)
 //   grad g  = 3 sum_{i>0} w_i v_i g(r + v_i)
 template <int LAT, typename T, typename G>
 __device__ __forceinline__ T lattice_laplacian(const G& g, T g0) {
   using L = Lattice<LAT>;
+  constexpr double kW = 1.0 - L::w(0);
   T acc = T(0);
 #pragma unroll
-  for (int i = 1; i < L::Q; ++i) acc = fma_(T(L::w(i)), g(i) - g0, acc);
-  return T(6) * acc;
+  for (int i = 1; i < L::Q; ++i) acc = fma_(T(L::w(i)), g(i), acc);
+  return fma_(T(6), acc, T(-6.0 * kW) * g0);
 }
 
 // sum_{i>0} w_i v_i g(r + v_i): one third of the gradient stencil.
