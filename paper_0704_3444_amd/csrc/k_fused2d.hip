@@ -21,7 +21,9 @@
 // The kernel is templated on the storage codec (storage.hpp): FP64, FP32,
 // or shifted FP16 (decoded on load against the references of the source
 // sites, the density from the exact pulled total, encoded on store against
-// the site's new reference).  No MFMA: the step is a bandwidth-bound stencil, not a
+// the site's new reference).  Boxes closed by walls take a separate
+// instantiation: bounce-back in the pull, mirrored layers beyond a wall in
+// the density and potential rings (the split path's values, bit for bit).  No MFMA: the step is a bandwidth-bound stencil, not a
 // contraction.
 #include <hip/hip_runtime.h>
 
