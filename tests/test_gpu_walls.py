@@ -68,7 +68,7 @@ def test_walls_shifted_fp16_match_oracle(case):
 # D2Q9 boxes for the tile kernel with walls: several tiles with ragged
 # edges, a box smaller than one tile, tile-multiple sides, each wall set
 TILE_WALL_BOXES = [((150, 40), 0b11, 3), ((37, 23), 0b11, 2), ((64, 32), 0b10, 3), ((130, 70), 0b01, 2),
-                   ((128, 48), 0b11, 1), ((2, 19), 0b01, 2)]
+                   ((128, 48), 0b11, 1), ((2, 19), 0b01, 2), ((70, 30), 0b11, 5)]
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16s"])
