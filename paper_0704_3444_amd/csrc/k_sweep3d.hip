@@ -8,14 +8,14 @@
 // z + 1 and the densities of planes z - 1 .. z + 1; h of plane z + 1 needs
 // the Laplacian of the densities, so densities run two planes ahead of the
 // collision.  One iteration, for the collision of plane zc:
-//   1. every wave issues the loads of its unit in plane zc + 3 (and those of
-//      the halo pieces of plane zc + 4, a plane earlier than the rest: they
-//      are scattered over many cache lines and land last), and writes the
-//      first moments of its unit in plane zc to LDS;
+//   1. every wave issues the loads of its unit in plane zc + 3 and writes
+//      the first moments of its unit in plane zc to LDS;
 //   2. (barrier) chemical potentials and h of plane zc + 1 on the rows and
 //      columns the force stencil reaches, into an LDS ring;
-//   3. (barrier) force, equilibrium, forcing term and collision of plane zc
-//      from the registers; non-temporal stores in place (the next step's pull
+//   3. (barrier) the loads of the halo-column pieces of plane zc + 4, a plane
+//      ahead of the rest (they are scattered over many cache lines and land
+//      last); force, equilibrium, forcing term and collision of plane zc from
+//      the registers; non-temporal stores in place (the next step's pull
 //      streams them);
 //   4. the 19 populations of plane zc + 3 land in registers; the wave writes
 //      their density to an LDS ring and keeps them: each wave holds three
@@ -323,10 +323,12 @@ __global__ void __launch_bounds__(64 * kTY * NC) k_sweep_d3q19(const void* fin_v
   // Issue the loads of virtual plane z: the halo-row unit into this wave's
   // staging, the own unit into register set Pn, then (in the prologue) the
   // pieces of plane z + 1; in the iterations those follow later (see there).
-  // Exactly 21 vector memory operations follow the halo-row unit's loads
-  // before consume(z) waits for them (the own unit's and the two of the next
-  // pieces, in the iterations also 19 stores of which 19 are allowed in
-  // flight), and the pieces of plane z precede them: one wait covers both.
+  // consume(z) waits until at most 21 vector memory operations are in
+  // flight: in the prologue the own unit's 19 loads and the two of the next
+  // pieces follow the halo-row unit's loads, in the iterations the two of
+  // the next pieces and the collision's 19 stores follow the own unit's.
+  // Either way the halo-row unit has landed, and so have the pieces of
+  // plane z, issued before both.
   auto issue = [&](int z, float (&Pn)[19], bool next_pieces) __attribute__((always_inline)) {
     const int zw = wrap_mod(z, p.nz);
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // this wave's reads of the staging are done
