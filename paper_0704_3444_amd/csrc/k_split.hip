@@ -280,7 +280,8 @@ __global__ void __launch_bounds__(kBlock) k_potential(const T* __restrict__ rho,
       lap[k] = lattice_laplacian<LAT, T>([&](int i) { return rk[nb[i]]; }, r[k]);
     }
   }
-  site_potential<T, NC>(p, r, lap, mu, h);
+  // NC < kMaxComp: instantiated for N itself (the run-time guards on N go)
+  site_potential<T, NC, (NC < kMaxComp)>(p, r, lap, mu, h);
   for (int k = 0; k < p.n; ++k) {
     if (mu_out) mu_out[(long long)k * p.S + s] = mu[k];
     h_out[(long long)k * p.S + s] = h[k];
