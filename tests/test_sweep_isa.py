@@ -212,6 +212,23 @@ def test_sweep_kernels_inline_everything(asm):
         assert "s_swappc" not in body and "scratch_" not in body, (store, nc)
 
 
+def test_shifted_fp16_decode_uses_mixed_precision_fmas(asm):
+    """The shifted codec's decode (k_i h + d) and ledger (rest - d) are
+    written so that they compile to v_fma_mix_f32, which converts its FP16
+    operands itself; a factor the compiler could fold (1 or -1 as a
+    constant) would turn them back into a conversion per operand plus an
+    add.  Checked over each kernel: a handful of conversions at most."""
+    for store, nc, lines in kernels(asm):
+        if store != "StoreF16S":
+            continue
+        loop = [l.strip() for l in lines if l.strip() and not l.strip().startswith((";", "."))]
+        mix = sum(1 for l in loop if l.startswith("v_fma_mix_f32"))
+        cvt = sum(1 for l in loop if l.startswith("v_cvt_f32_f16"))
+        # per row and component: 8 decoded moving slots, 8 ledger terms
+        assert mix >= 16 * nc, (nc, mix, cvt)
+        assert cvt <= 6 * nc, (nc, mix, cvt)  # 4 N today; 59 in the loop alone before
+
+
 @pytest.fixture(scope="module")
 def asm3d(tmp_path_factory):
     if not shutil.which(B.HIPCC) and not os.path.exists(B.HIPCC):
