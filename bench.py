@@ -351,7 +351,7 @@ def main():
     ap.add_argument("--only-phase", action="store_true", help="time only the phase sweeps (for profiling them)")
     ap.add_argument("--only-batch", type=int, default=0,
                     help="time only one batch of this many serving requests (for profiling the batched kernel)")
-    ap.add_argument("--walls", type=int, default=0, help="close axes by walls (bit a: axis a; the D2Q9 tile kernel or the split path)")
+    ap.add_argument("--walls", type=int, default=0, help="close axes by walls (bit a: axis a; walls on y only: the D2Q9 strip sweep, else the tile kernel or the split path)")
     ap.add_argument("--serving-requests", type=int, default=256)
     args = ap.parse_args()
 

@@ -123,6 +123,9 @@ struct Staged {
   static constexpr int kStores = (S::kShift ? 10 : 9) * NC;  // stores per collided row
   static_assert(group_bytes(0) % 16 == 0 && group_bytes(1) % 16 == 0, "segments aligned");
   static_assert(kStores < 64, "vmcnt range");
+  // a bounced run of group 1 or 2 is read from the same slot of the other
+  static_assert(vel(1, 0) == L::opp(vel(2, 0)) && vel(1, 1) == L::opp(vel(2, 1)) && vel(1, 2) == L::opp(vel(2, 2)),
+                "opposite runs share their slot");
 };
 
 // Per-lane column parts of the staging loads, which do not change along the
@@ -133,6 +136,10 @@ struct Staged {
 template <class S, int NC>
 struct Gather {
   uint32_t col[Staged<S, NC>::kLoads];
+  // boxes with walls on y: the distance from the chunk's run to the opposite
+  // run of the other vertical group (moving runs of the groups v_y = +1 and
+  // -1; 0 elsewhere), which a row next to a wall reads instead (bounce-back)
+  uint32_t adj[Staged<S, NC>::kLoads];
 };
 
 template <class S, int NC>
@@ -149,6 +156,7 @@ __device__ __forceinline__ Gather<S, NC> make_gather(const Params<float>& p, int
     const int ch = j * 64 + lane;
     const int g = ch < G::chunks(0) ? 0 : (ch < G::chunks(0) + G::chunks(1) ? 1 : 2);
     const int first = g == 0 ? 0 : (g == 1 ? G::chunks(0) : G::chunks(0) + G::chunks(1));
+    gat.adj[j] = 0;
     if (ch >= G::kChunks) {
       gat.col[j] = own;
       continue;
@@ -175,16 +183,23 @@ __device__ __forceinline__ Gather<S, NC> make_gather(const Params<float>& p, int
     else
       off = right + run;  // right neighbour's first 16 bytes
     gat.col[j] = off;
+    if (g != 0 && k < 3) gat.adj[j] = B::run(c, G::vel(3 - g, k)) - B::run(c, G::vel(g, k));
   }
   return gat;
 }
 
 // Stage the populations pulled into row r (wave-uniform) of the strip into
 // the LDS slot `dst` (Staged layout) with exactly Staged::kLoads direct loads
-// of the whole wave.
+// of the whole wave.  bnc (walls on y): 1 for row 0, whose v_y = +1 group
+// would come from beyond the wall and bounces back instead (it is read from
+// the row itself, runs -v_i), 2 for row ny - 1 (the v_y = -1 group
+// likewise), 0 otherwise.
+// (The gather columns come as a plain pointer: taken as a reference to
+// Gather<S, NC>, the second instantiation of the kernel for the same S and
+// NC failed to compile.)
 template <class S, int NC>
-__device__ __forceinline__ void stage_row(const char* fin, const Params<float>& p, const Gather<S, NC>& gat,
-                                          int lane, int r, char* dst_in) {
+__device__ __forceinline__ void stage_row(const char* fin, const Params<float>& p, const uint32_t* gat_col,
+                                          const uint32_t* gat_adj, int bnc, int lane, int r, char* dst_in) {
   using B = BlockLayout<S, 9>;
   // The LDS destination is passed through an empty asm statement: the
   // compiler's own tracking of direct loads into LDS would otherwise add a
@@ -195,15 +210,18 @@ __device__ __forceinline__ void stage_row(const char* fin, const Params<float>& 
   using G = Staged<S, NC>;
   const uint32_t stride = uint32_t(p.nbx) * uint32_t(NC * B::kComp);
   // row parts of the source rows of the groups v_y = 0, +1 (row above), -1
-  const uint32_t ry[3] = {uint32_t(r) * stride, uint32_t(wrap_add(r, -1, p.ny)) * stride,
-                          uint32_t(wrap_add(r, 1, p.ny)) * stride};
+  const uint32_t ry0 = uint32_t(r) * stride;
+  const uint32_t ry[3] = {ry0, bnc == 1 ? ry0 : uint32_t(wrap_add(r, -1, p.ny)) * stride,
+                          bnc == 2 ? ry0 : uint32_t(wrap_add(r, 1, p.ny)) * stride};
 #pragma unroll
   for (int j = 0; j < G::kLoads; ++j) {
     // the chunk's source row (known at compile time except for a load that
     // straddles two groups)
     const int ch = j * 64 + lane;
-    const uint32_t rp = ch < G::chunks(0) ? ry[0] : (ch < G::chunks(0) + G::chunks(1) ? ry[1] : ry[2]);
-    __builtin_amdgcn_global_load_lds(fin + (rp + gat.col[j]), dst + 1024u * uint32_t(j), 16, 0, 0);
+    const int g = ch < G::chunks(0) ? 0 : (ch < G::chunks(0) + G::chunks(1) ? 1 : 2);
+    const uint32_t rp = g == 0 ? ry[0] : (g == 1 ? ry[1] : ry[2]);
+    const uint32_t hop = bnc != 0 && g == bnc ? gat_adj[j] : 0u;
+    __builtin_amdgcn_global_load_lds(fin + (rp + gat_col[j] + hop), dst + 1024u * uint32_t(j), 16, 0, 0);
   }
 }
 
@@ -216,7 +234,9 @@ __device__ __forceinline__ float lds_raw(const char* a, int i) {
   return float(*reinterpret_cast<const typename S::Move*>(a));
 }
 
-template <class S, int NC>
+// W: the box has walls on y (p.walls == 2), a separate instantiation, so the
+// periodic sweep carries none of their logic.
+template <class S, int NC, bool W>
 __global__ void __launch_bounds__(256) k_sweep_d2q9(const void* fin_v, void* fout,
                                                     Params<float> p, int strips, int seg_rows, int ntiles,
                                                     int tiles_per_xcd) {
@@ -243,6 +263,17 @@ __global__ void __launch_bounds__(256) k_sweep_d2q9(const void* fin_v, void* fou
   // ring slots of virtual row r (r >= ya - 8 always)
   auto rslot = [&](int r) { return (r - ya + 8 * kRhoRing) & (kRhoRing - 1); };
   auto hslot = [&](int r) { return (r - ya + 8 * kHRing) & (kHRing - 1); };
+  // walls on y: the row whose values the stencils use for virtual row v (the
+  // layer next to a wall stands for the layer beyond it), and the bounce of
+  // a staged virtual row v (stage_row's bnc)
+  auto mrow = [&](int v) __attribute__((always_inline)) {
+    if constexpr (W) return v < 0 ? -1 - v : (v >= ny ? 2 * ny - 1 - v : v);
+    return v;
+  };
+  auto bnc_of = [&](int v) __attribute__((always_inline)) {
+    if constexpr (W) return v == 0 ? 1 : (v == ny - 1 ? 2 : 0);
+    return 0;
+  };
 
   // Scale of the component of a halo lane (lane % NC), picked by selects
   // and kept in a register: an indexed read of the parameters would be a
@@ -259,14 +290,17 @@ __global__ void __launch_bounds__(256) k_sweep_d2q9(const void* fin_v, void* fou
 
   // Take a staged row into registers: decoded populations, in direction
   // order, and the running sum of each component (take_slot, take_shifted).
-  auto take = [&](const char* st, T (&f)[NC][9], T (&ledger)[NC]) __attribute__((always_inline)) {
+  // bnc: the staged row's bounce (stage_row); a bounced group's runs are the
+  // row's own runs -v_i, read at the lane's own column.
+  auto take = [&](const char* st, T (&f)[NC][9], T (&ledger)[NC], int bnc) __attribute__((always_inline)) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       T led = T(0);
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
         // column lane - v_x of the padded segment (-1 and 64 in the halo parts)
-        const int col = lane - L::cx(i);
+        const bool own = bnc != 0 && bnc == G::group_of(i);
+        const int col = own ? lane : lane - L::cx(i);
         const char* at = st + G::run0(c, i) + col * int(i == 0 ? B::kRest : B::kMove);
         if constexpr (S::kShift) {
           const _Float16 h = lds_half(st + G::ref0(c, L::cy(i)) + col * 2);
@@ -289,14 +323,15 @@ __global__ void __launch_bounds__(256) k_sweep_d2q9(const void* fin_v, void* fou
   // lane hc * NC + c sums its nine pulled values in direction order (the
   // lane's component varies over the lanes: its scale is the one picked
   // once per lane above)
-  auto put_rho_halo = [&](int r, const char* st) __attribute__((always_inline)) {
+  auto put_rho_halo = [&](int r, const char* st, int bnc) __attribute__((always_inline)) {
     if (lane < 4 * NC) {
       const int hc = lane / NC, c = lane % NC;
       const int hcol = hc < 2 ? hc - 2 : kW + hc - 2;
       T v[9], led = T(0);
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
-        const int col = hcol - L::cx(i);  // -3 .. 66, inside the padded segment
+        const bool own = bnc != 0 && bnc == G::group_of(i);
+        const int col = own ? hcol : hcol - L::cx(i);  // -3 .. 66, inside the padded segment
         const char* at = st + G::run0(c, i) + col * int(i == 0 ? B::kRest : B::kMove);
         if constexpr (S::kShift) {
           const _Float16 h = lds_half(st + G::ref0(c, L::cy(i)) + col * 2);
@@ -312,7 +347,7 @@ __global__ void __launch_bounds__(256) k_sweep_d2q9(const void* fin_v, void* fou
 
   // potential h of virtual row r at h position q (column x0 - 1 + q)
   auto put_h = [&](int r, int q) __attribute__((always_inline)) {
-    const int s0 = rslot(r - 1), s1 = rslot(r), s2 = rslot(r + 1);
+    const int s0 = rslot(mrow(r - 1)), s1 = rslot(r), s2 = rslot(mrow(r + 1));
     const int pc = q + 1;  // rho position of the column
     T rr[NC], lap[NC], mu[NC], hh[NC];
 #pragma unroll
@@ -362,8 +397,8 @@ __global__ void __launch_bounds__(256) k_sweep_d2q9(const void* fin_v, void* fou
     const T inv_rt = rcp_(rt);
     ux *= inv_rt;
     uy *= inv_rt;
-    const int h0 = hslot(rc - 1), h1 = hslot(rc), h2 = hslot(rc + 1);
-    const int r0 = rslot(rc - 1), r2 = rslot(rc + 1);
+    const int h0 = hslot(mrow(rc - 1)), h1 = hslot(rc), h2 = hslot(mrow(rc + 1));
+    const int r0 = rslot(mrow(rc - 1)), r2 = rslot(mrow(rc + 1));
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       T Ax, Ay, Az;
@@ -436,20 +471,20 @@ __global__ void __launch_bounds__(256) k_sweep_d2q9(const void* fin_v, void* fou
   // rho of rows ya-2, ya-1 (waves 2, 3) and ya .. ya+3 (all waves); h of rows
   // ya-1 .. ya+2; populations of row ya + w in F0; row ya + 4 + w staged.
   if (w >= 2) {
-    stage_row<S, NC>(fin, p, gat, lane, wrap_mod(ya - 4 + w, ny), stage);
+    stage_row<S, NC>(fin, p, gat.col, gat.adj, bnc_of(ya - 4 + w), lane, wrap_mod(ya - 4 + w, ny), stage);
     wait_vm<0>();
-    take(stage, F1, L1);
+    take(stage, F1, L1, bnc_of(ya - 4 + w));
     put_rho(ya - 4 + w, F1, L1);
-    put_rho_halo(ya - 4 + w, stage);
+    put_rho_halo(ya - 4 + w, stage, bnc_of(ya - 4 + w));
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // the slot is read before it is staged again
   }
-  stage_row<S, NC>(fin, p, gat, lane, wrap_mod(ya + w, ny), stage);
+  stage_row<S, NC>(fin, p, gat.col, gat.adj, bnc_of(ya + w), lane, wrap_mod(ya + w, ny), stage);
   wait_vm<0>();
-  take(stage, F0, L0);
+  take(stage, F0, L0, bnc_of(ya + w));
   put_rho(ya + w, F0, L0);
-  put_rho_halo(ya + w, stage);
+  put_rho_halo(ya + w, stage, bnc_of(ya + w));
   asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-  stage_row<S, NC>(fin, p, gat, lane, wrap_mod(ya + 4 + w, ny), stage);
+  stage_row<S, NC>(fin, p, gat.col, gat.adj, bnc_of(ya + 4 + w), lane, wrap_mod(ya + 4 + w, ny), stage);
   lds_barrier();
   put_h4(ya - 1);
   lds_barrier();
@@ -471,16 +506,16 @@ __global__ void __launch_bounds__(256) k_sweep_d2q9(const void* fin_v, void* fou
       wait_vm<G::kStores>();
     else
       wait_vm<0>();
-    take(stage, F1, L1);
+    take(stage, F1, L1, bnc_of(ra));
     put_rho(ra, F1, L1);
-    put_rho_halo(ra, stage);
+    put_rho_halo(ra, stage, bnc_of(ra));
     if (k + 1 < rounds) {
       asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // the slot is read before it is staged again
       // shifted FP16: the wave issues its staging loads at raised priority,
       // ahead of the other waves' arithmetic (2.5% faster at 2048^2; the same
       // for FP32 is 4% slower)
       if constexpr (S::kShift) __builtin_amdgcn_s_setprio(1);
-      stage_row<S, NC>(fin, p, gat, lane, wrap_mod(ra + 4, ny), stage);
+      stage_row<S, NC>(fin, p, gat.col, gat.adj, bnc_of(ra + 4), lane, wrap_mod(ra + 4, ny), stage);
       if constexpr (S::kShift) __builtin_amdgcn_s_setprio(0);
     }
     lds_barrier();
@@ -526,7 +561,7 @@ template <class S, int NC>
 static int sweep_slots() {
   static const int slots = [] {
     int per_cu = 0, dev = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sweep::k_sweep_d2q9<S, NC>, 256, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sweep::k_sweep_d2q9<S, NC, false>, 256, 0) != hipSuccess ||
         per_cu < 1)
       per_cu = 1;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -543,8 +578,13 @@ static void launch_rows(const Ctx& c, const void* fin, void* fout, int rows) {
   const int strips = p.nx / 64;
   const int ntiles = strips * ((p.ny + rows - 1) / rows);
   const int per_xcd = (ntiles + sweep::kXcds - 1) / sweep::kXcds;
-  sweep::k_sweep_d2q9<S, NC><<<per_xcd * sweep::kXcds, 256, 0, c.stream>>>(fin, fout, p, strips, rows, ntiles,
-                                                                           per_xcd);
+  // walls: on y only (the context takes the sweep for no other)
+  if (p.walls & 2)
+    sweep::k_sweep_d2q9<S, NC, true><<<per_xcd * sweep::kXcds, 256, 0, c.stream>>>(fin, fout, p, strips, rows, ntiles,
+                                                                                   per_xcd);
+  else
+    sweep::k_sweep_d2q9<S, NC, false><<<per_xcd * sweep::kXcds, 256, 0, c.stream>>>(fin, fout, p, strips, rows,
+                                                                                    ntiles, per_xcd);
 }
 
 template <class S, int NC>

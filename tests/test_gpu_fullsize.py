@@ -152,14 +152,17 @@ def test_fullsize_mass_conserved(workload, storage):
     assert drift < 1e-6
 
 
+@pytest.mark.parametrize("walls", [0, 0b10], ids=["periodic", "walls-y"])
 @pytest.mark.parametrize("storage", ["f32", "f16s"])
-def test_fullsize_tuned_sweep_equals_split_path(workload, storage):
+def test_fullsize_tuned_sweep_equals_split_path(workload, storage, walls):
     """On grids this large lb_init times several segment lengths on the new
     state and restores it; whichever length it keeps, every site must come
-    out bit for bit as on the one-thread-per-site split path."""
+    out bit for bit as on the one-thread-per-site split path (also with the
+    box closed by walls on y)."""
     from paper_0704_3444_amd import Simulation
 
     cfg, rho0 = workload
+    cfg = dict(cfg, walls=walls)
     out = {}
     for path in ("sweep", "split"):
         sim = Simulation(cfg, rho0, storage=storage, path=path)
@@ -167,7 +170,7 @@ def test_fullsize_tuned_sweep_equals_split_path(workload, storage):
         sim.step(2)
         out[path] = sim.moments(fields=True)
         sim.close()
-    print(f"[fullsize] {storage} tuned sweep vs split, 132 steps", flush=True)
+    print(f"[fullsize] {storage} walls={walls:02b} tuned sweep vs split, 132 steps", flush=True)
     assert out["sweep"]["step"] == out["split"]["step"] == 132
     assert np.array_equal(out["sweep"]["rho"], out["split"]["rho"])
     assert np.array_equal(out["sweep"]["U"], out["split"]["U"])

@@ -211,7 +211,7 @@ def poison_copy(s, cfg, storage, which):
     s.workspace[start:start + n].fill_(255)
 
 
-@pytest.mark.parametrize("case", ["d2q9", "ragged", "d3q19", "lines", "walls"])
+@pytest.mark.parametrize("case", ["d2q9", "ragged", "d3q19", "lines", "walls", "walls_y"])
 def test_every_slot_written_each_step(case):
     """The copy a step writes is filled with NaN before the step; after three
     steps the state equals that of an unpoisoned run bit for bit, so every
@@ -232,6 +232,10 @@ def test_every_slot_written_each_step(case):
         cfg, rho0 = LI.ternary_immersion(37, ny=23)
         cfg = dict(cfg, walls=0b011)
         combos = [(p, st) for p in ("split", "tile") for st in storages(p)]
+    elif case == "walls_y":
+        cfg, rho0 = LI.ternary_immersion(128, ny=37)
+        cfg = dict(cfg, walls=0b010)
+        combos = [(p, st) for p in PATHS for st in storages(p)]
     else:
         cfg, rho0, _ = LI.binodal_runs("ternary_monomer")[9]
         combos = [("lines", "f64"), ("lines", "f32")]

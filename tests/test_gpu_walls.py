@@ -1,7 +1,8 @@
 """Walls (not in the paper; lb_params.walls) on the split path and the D2Q9
-tile kernel against the oracle's walls, every lattice and storage, the two
-paths against each other bit for bit, and the paths and groups that refuse
-them.  The oracle's walls are pinned by tests/test_oracle_walls.py."""
+tile kernel against the oracle's walls, every lattice and storage, the D2Q9
+tile kernel and strip sweep (walls on y) against the split path bit for bit,
+and the paths and groups that refuse them.  The oracle's walls are pinned by
+tests/test_oracle_walls.py."""
 import numpy as np
 import pytest
 
@@ -78,13 +79,34 @@ def test_walls_tile_equals_split(shape, walls, n, storage):
     """The tile kernel with walls against the split path, bit for bit: the
     bounce-back pulls, the mirrored density ring and the potential one layer
     beyond a wall (taken from the layer next to it) give the split path's
-    values in the same order; auto picks the tile kernel."""
+    values in the same order."""
     cfg, rho0 = walled("D2Q9", shape, walls, n, 70 + n + walls)
     a = run_gpu(cfg, rho0, 37, storage=storage, path="split")
-    b = run_gpu(cfg, rho0, 37, storage=storage, path="auto")
-    assert b["path"] == "tile"
+    b = run_gpu(cfg, rho0, 37, storage=storage, path="tile")
     print(f"[walls-tile] {shape} walls={walls:02b} N={n} {storage}: max |df| {np.abs(a['f'] - b['f']).max():.3e}",
           flush=True)
+    assert np.array_equal(a["f"], b["f"])
+
+
+# D2Q9 boxes for the strip sweep with walls on y: one strip and several,
+# segments of four rows with a ragged last one, a box of two rows (both next
+# to a wall; a segment of fewer than four rows), segments of two rounds,
+# N = 1 .. 4
+SWEEP_WALL_BOXES = [((128, 40), 3), ((64, 37), 2), ((192, 23), 4), ((64, 2), 1), ((128, 5), 3), ((64, 3101), 3)]
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16s"])
+@pytest.mark.parametrize("shape,n", SWEEP_WALL_BOXES, ids=[f"{s[0]}x{s[1]}-N{n}" for s, n in SWEEP_WALL_BOXES])
+def test_walls_sweep_equals_split(shape, n, storage):
+    """The strip sweep with walls on y against the split path, bit for bit:
+    the rows next to a wall stage their bounced group from their own
+    opposite runs, and the density and potential stencils take the row next
+    to the wall for the row beyond it; auto picks the sweep."""
+    cfg, rho0 = walled("D2Q9", shape, 0b10, n, 90 + n)
+    a = run_gpu(cfg, rho0, 37, storage=storage, path="split")
+    b = run_gpu(cfg, rho0, 37, storage=storage, path="auto")
+    assert b["path"] == "sweep"
+    print(f"[walls-sweep] {shape} N={n} {storage}: max |df| {np.abs(a['f'] - b['f']).max():.3e}", flush=True)
     assert np.array_equal(a["f"], b["f"])
 
 
@@ -100,9 +122,10 @@ def test_walls_refused_where_not_built():
     from paper_0704_3444_amd.lb import LB_EINVAL, LB_ENOTSUP
 
     cfg, rho0 = walled("D2Q9", (64, 32), 0b010, 2, 60)
-    with pytest.raises(LBError) as ei:
-        Simulation(cfg, rho0, storage="f32", path="sweep")
-    assert ei.value.code == LB_ENOTSUP
+    for walls in (0b001, 0b011):  # the sweep takes walls on y only
+        with pytest.raises(LBError) as ei:
+            Simulation(dict(cfg, walls=walls), rho0, storage="f32", path="sweep")
+        assert ei.value.code == LB_ENOTSUP
     c3, r3 = walled("D3Q19", (64, 8, 6), 0b100, 2, 61)
     for path in ("tile", "sweep"):
         with pytest.raises(LBError) as ei:

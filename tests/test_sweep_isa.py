@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 
 from paper_0704_3444_amd import build as B  # noqa: E402
 
-KERNEL = re.compile(r"^(_ZN3lbm5sweep12k_sweep_d2q9INS_\d+(Store\w+?)ELi(\d)E\w*):", re.M)
+KERNEL = re.compile(r"^(_ZN3lbm5sweep12k_sweep_d2q9INS_\d+(Store\w+?)ELi(\d)ELb(\d)E\w*):", re.M)
 
 
 @pytest.fixture(scope="module")
@@ -43,15 +43,22 @@ def asm(tmp_path_factory):
     return out.read_text()
 
 
-def kernels(text):
+def kernels_w(text):
     for m in KERNEL.finditer(text):
         end = text.index("s_endpgm", m.end())
-        yield m.group(2), int(m.group(3)), text[m.end():end].split("\n")
+        yield m.group(2), int(m.group(3)), int(m.group(4)), text[m.end():end].split("\n")
+
+
+def kernels(text):
+    for s, n, _, lines in kernels_w(text):
+        yield s, n, lines
 
 
 def test_every_instantiation_present(asm):
-    found = {(s, n) for s, n, _ in kernels(asm)}
-    assert found == {(s, n) for s in ("StoreF32", "StoreF16S") for n in (1, 2, 3, 4)}
+    # periodic, and walls on y (separate instantiations); every structural
+    # test below covers both
+    found = sorted((s, n, w) for s, n, w, _ in kernels_w(asm))
+    assert found == sorted((s, n, w) for s in ("StoreF32", "StoreF16S") for n in (1, 2, 3, 4) for w in (0, 1))
 
 
 def stores_per_row(store, nc):
