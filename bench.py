@@ -65,6 +65,7 @@ def workload(name):
 
     table = {
         "ternary_d2q9_2048": lambda: LI.ternary_immersion(2048),
+        "ternary_substrate_d2q9_2048": lambda: LI.ternary_film_on_substrate(2048),
         "binary_d2q9_1024": lambda: LI.binary_spinodal(1024, seed=1001),
         "ternary_d3q19_256": lambda: LI.ternary_d3q19(256),
         "five_d2q9_512": lambda: LI.five_component(512),
@@ -444,7 +445,7 @@ def main():
         "dtype": "f64" if args.storage == "f64" else "f32", "data": "synthetic",
         "config": {"workload": args.workload, "lattice": cfg["lattice"], "shape": shape[: len(cfg["shape"])],
                    "n_comp": N, "storage": args.storage, "path": path, "force_form": cfg["force_form"],
-                   "walls": args.walls},
+                   "walls": int(cfg.get("walls", 0))},
         "hbm_frac": round(achieved / HBM_PEAK_GBS, 4),
         "wall_s": round(wall, 4), "mass_drift": mass_drift, "status": health["status"],
         "roofline": roofline, "cpu_baseline": cpu, "f16s": f16s, "serving": serving, "phase_sweeps": phase_sweeps,

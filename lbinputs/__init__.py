@@ -114,6 +114,32 @@ def ternary_immersion(n=2048, *, seed=1002, kappa=0.01, ny=None, width=2.0):
     return p, rho
 
 
+def ternary_film_on_substrate(n=2048, *, seed=1003, kappa=0.01, ny=None, width=2.0):
+    """The immersion film of ternary_immersion cast on a substrate: the
+    film's normal along y, the substrate a wall below row 0 and the bath
+    closed by a wall above row ny - 1 (walls = 0b10; x periodic).  Rows
+    y < ny/2: (0.30, 0.69, 0.01) with 0.01 (2U - 1) noise on P and S; rows
+    above: the bath (0.01, 0.01, 0.98).  Only the film's free face is smoothed
+    (1/2 (1 + tanh(d / width)), d the distance to y = ny/2): the film meets
+    the substrate as it is."""
+    ny = n if ny is None else ny
+    p = params("D2Q9", 3, (n, ny), kappa=kappa,
+               chi=_chi(3, {(0, 1): 2.0, (1, 2): 2.5, (0, 2): 3.0})) | {"walls": 0b10}
+    S = n * ny
+    yc = np.arange(ny) + 0.5
+    d = ny // 2 - yc
+    prof = 0.5 * (1.0 + np.tanh(d / width)) if width > 0 else (d > 0).astype(float)
+    film = prof[np.arange(S) // n]
+    left = (0.30, 0.69, 0.01)
+    right = (0.01, 0.01, 0.98)
+    rho = np.empty((3, S))
+    for c in range(3):
+        rho[c] = film * left[c] + (1 - film) * right[c]
+    for c in (0, 1):
+        rho[c] += film * 0.01 * (2.0 * uniform(seed, c, S) - 1.0)
+    return p, rho
+
+
 def film_profile(n: int, width: float) -> np.ndarray:
     """Film fraction along x for a periodic box of length n: 1 on [0, n/2),
     0 on [n/2, n); with width > 0 both faces are smoothed as
@@ -218,6 +244,7 @@ WORKLOADS = {
     "binary_d2q9_64_stable": lambda: binary_spinodal(64, chi=1.6),
     "binary_d2q9_1024": lambda: binary_spinodal(1024, seed=1001),
     "ternary_d2q9_2048": lambda: ternary_immersion(2048),
+    "ternary_substrate_d2q9_2048": lambda: ternary_film_on_substrate(2048),
     "ternary_d3q19_256": lambda: ternary_d3q19(256),
     "five_d2q9_512": lambda: five_component(512),
 }

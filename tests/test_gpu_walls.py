@@ -169,3 +169,33 @@ def test_immersion_film_on_a_wall():
     sim.close()
     assert m["status"] == 0
     assert float(np.max(np.abs(m["mass"] / rho0.sum(axis=1) - 1))) < 1e-6
+
+
+def test_film_on_substrate_sweep():
+    """The immersion film cast on a substrate (film normal along y, walls on
+    y) runs on the strip sweep: against the oracle after 100 steps (FP32
+    bar, and shifted FP16 within its rounding budget); healthy, with every
+    component's mass kept, after 3000 steps."""
+    from paper_0704_3444_amd import Simulation
+
+    cfg, rho0 = LI.ternary_film_on_substrate(128, ny=64)
+    g = run_gpu(cfg, rho0, 100, storage="f32", path="auto")
+    assert g["path"] == "sweep"
+    o, budget = run_oracle_f16s_budget(cfg, rho0, 100)
+    e = errors(g, o, cfg["theta"], lattice="D2Q9")
+    print(f"[walls] film on a substrate, 100 steps, f32 sweep: {e}", flush=True)
+    for k in ("rho", "f", "U_cs", "mu", "mom"):
+        assert e[k] < TOL["f32"], (k, e)
+    h = run_gpu(cfg, rho0, 100, storage="f16s", path="auto")
+    assert h["path"] == "sweep"
+    r = f16s_check(h, o, budget, cfg, rho0)
+    print(f"[walls] film on a substrate, 100 steps, f16s sweep error / rounding bar: {r}", flush=True)
+    for k, v in r.items():
+        assert v < 1.0, (k, r)
+    for storage in ("f32", "f16s"):
+        sim = Simulation(cfg, rho0, storage=storage)
+        sim.step(3000)
+        m = sim.moments(fields=False)
+        sim.close()
+        assert m["status"] == 0, storage
+        assert float(np.max(np.abs(m["mass"] / rho0.sum(axis=1) - 1))) < 1e-6, storage
