@@ -96,8 +96,8 @@ typedef enum lb_force_form { LB_FORCE_LOG = 0, LB_FORCE_EXPANDED = 1 } lb_force_
  *                  64-column strips row by row (LB_F32 or LB_F16S, N <= 4,
  *                  nx a multiple of 64), on D3Q19 pencils of 64 x 4 sites
  *                  plane by plane (LB_F32, N <= 3, nx a multiple of 64, ny
- *                  of 4); periodic boxes (on D2Q9 also walls on y),
- *                  population copies below 4 GiB.
+ *                  of 4); periodic boxes or walls on the swept axis (y
+ *                  on D2Q9, z on D3Q19), population copies below 4 GiB.
  * Asking for a path that does not support the run gives LB_ENOTSUP. */
 typedef enum lb_path { LB_PATH_AUTO = 0, LB_PATH_TILE = 1, LB_PATH_SPLIT = 2, LB_PATH_SWEEP = 3 } lb_path;
 
@@ -129,9 +129,9 @@ typedef struct lb_params {
                             the density and potential stencils mirror the layer
                             next to the wall (zero normal gradient, a wall that
                             favours no component).  LB_PATH_SPLIT; on D2Q9
-                            also LB_PATH_TILE, and LB_PATH_SWEEP for walls on
-                            y only (all three give the same values bit for
-                            bit). */
+                            also LB_PATH_TILE; LB_PATH_SWEEP for walls on y
+                            only (D2Q9) or z only (D3Q19).  Every path gives
+                            the same values bit for bit. */
   int32_t reserved;      /* 0                                                     */
 } lb_params;
 

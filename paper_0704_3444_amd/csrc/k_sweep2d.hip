@@ -557,11 +557,11 @@ static int sweep_rows(int nx, int ny, int slots) {
 }
 
 // Resident workgroups of the sweep kernel on the current device.
-template <class S, int NC>
-static int sweep_slots() {
+template <class S, int NC, bool W>
+static int sweep_slots_of() {
   static const int slots = [] {
     int per_cu = 0, dev = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sweep::k_sweep_d2q9<S, NC, false>, 256, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sweep::k_sweep_d2q9<S, NC, W>, 256, 0) != hipSuccess ||
         per_cu < 1)
       per_cu = 1;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -570,6 +570,13 @@ static int sweep_slots() {
     return per_cu * cus;
   }();
   return slots;
+}
+
+// Resident workgroups of the instantiation that run p launches (walls on y
+// or not).
+template <class S, int NC>
+static int sweep_slots(const Params<float>& p) {
+  return (p.walls & 2) ? sweep_slots_of<S, NC, true>() : sweep_slots_of<S, NC, false>();
 }
 
 template <class S, int NC>
@@ -590,7 +597,7 @@ static void launch_rows(const Ctx& c, const void* fin, void* fout, int rows) {
 template <class S, int NC>
 static void launch_sweep(const Ctx& c, const void* fin, void* fout) {
   const Params<float>& p = c.params<float>();
-  launch_rows<S, NC>(c, fin, fout, c.sweep_rows > 0 ? c.sweep_rows : sweep_rows(p.nx, p.ny, sweep_slots<S, NC>()));
+  launch_rows<S, NC>(c, fin, fout, c.sweep_rows > 0 ? c.sweep_rows : sweep_rows(p.nx, p.ny, sweep_slots<S, NC>(p)));
 }
 
 // Segment lengths worth timing for this run, the one-wave default first.
@@ -609,7 +616,7 @@ static int candidates(const Ctx& c, int* cand) {
       if (cand[i] == r) return;
     cand[nc++] = r;
   };
-  add(sweep_rows(p.nx, p.ny, sweep_slots<S, NC>()));
+  add(sweep_rows(p.nx, p.ny, sweep_slots<S, NC>(p)));
   for (int r : {16, 24, 32, 48, 64, 96, 128}) add(r);
   return nc;
 }

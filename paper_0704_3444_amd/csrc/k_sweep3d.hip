@@ -222,7 +222,9 @@ __device__ __forceinline__ void wait_vm() {
   asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
 }
 
-template <class S, int NC>
+// W: the box has walls on z (p.walls == 4), a separate instantiation, so the
+// periodic sweep carries none of their logic.
+template <class S, int NC, bool W>
 __global__ void __launch_bounds__(64 * kTY * NC) k_sweep_d3q19(const void* fin_v, void* fout_v, Params<float> p,
                                                                int strips, int ytiles, int seg, int ntiles,
                                                                int tiles_per_xcd) {
@@ -265,7 +267,7 @@ __global__ void __launch_bounds__(64 * kTY * NC) k_sweep_d3q19(const void* fin_v
   // density row 2 r + prow[j], source row offsets (pdy, pdz), and the part of
   // its byte offset that does not depend on the row
   int prow[2], pdy[2], pdz[2];
-  uint32_t pcol[2];
+  uint32_t pcol[2], padj[2];
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     const int q = j * kW + lane;
@@ -281,7 +283,26 @@ __global__ void __launch_bounds__(64 * kTY * NC) k_sweep_d3q19(const void* fin_v
     pdy[j] = L::cy(i);
     pdz[j] = L::cz(i);
     pcol[j] = uint32_t(bx) * uint32_t(NC * B::kComp) + B::run(c, i) + (at_end ? kW * esz - 16u : 0u);
+    padj[j] = B::run(c, L::opp(i)) - B::run(c, i);  // to the same piece of the opposite run
   }
+
+  // Walls on z: whether direction i, pulled into virtual plane z, would come
+  // from beyond a wall (v_z = +1 into plane 0, -1 into plane nz - 1); it
+  // then bounces back: the site's own population -v_i, read at the site
+  // itself.  mz: the plane whose densities and potentials the stencils use
+  // for virtual plane v (the plane next to a wall stands for the one beyond).
+  const int nz = p.nz;
+  auto bounced = [&](int z, int dz) __attribute__((always_inline)) {
+    if constexpr (W) return dz > 0 ? z == 0 : (dz < 0 ? z == nz - 1 : false);
+    return false;
+  };
+  auto mz = [&](int v) __attribute__((always_inline)) {
+    if constexpr (W) return v < 0 ? -1 - v : (v >= nz ? 2 * nz - 1 - v : v);
+    return v;
+  };
+  // The loads of the own and halo-row units of a plane next to a wall take a
+  // branch of their own, so that the other planes' loads carry no selects.
+  auto at_wall = [&](int z) __attribute__((always_inline)) { return z == 0 || z == nz - 1; };
 
   // The staging slot's LDS address is passed through an empty asm
   // statement: the compiler's own tracking of direct loads into LDS would
@@ -308,14 +329,18 @@ __global__ void __launch_bounds__(64 * kTY * NC) k_sweep_d3q19(const void* fin_v
 
   // The halo-column pieces of virtual plane z into this wave's staging (by
   // parity of z).
+  // (Its two loads select their offsets per lane instead: with the loads in
+  // both branches, the compiler merged them under the lane condition and
+  // passed their common LDS destination through a VGPR.)
   auto issue_pieces = [&](int z) __attribute__((always_inline)) {
     const int zw = wrap_mod(z, p.nz);
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       if (j * kW + lane < kPieces) {
         const int yr = wrap_mod(y0 - 2 + 2 * r + prow[j], p.ny);
-        load_lds16(fin, stg + (19 * kW * 4 + (z & 1) * kPieces * 16 + j * kW * 16),
-                   rowb(yr, zw, pdy[j], pdz[j]) + pcol[j]);
+        uint32_t off = rowb(yr, zw, pdy[j], pdz[j]) + pcol[j];
+        if constexpr (W) off = bounced(z, pdz[j]) ? rowb(yr, zw, 0, 0) + pcol[j] + padj[j] : off;
+        load_lds16(fin, stg + (19 * kW * 4 + (z & 1) * kPieces * 16 + j * kW * 16), off);
       }
     }
   };
@@ -332,16 +357,46 @@ __global__ void __launch_bounds__(64 * kTY * NC) k_sweep_d3q19(const void* fin_v
   auto issue = [&](int z, float (&Pn)[19], bool next_pieces) __attribute__((always_inline)) {
     const int zw = wrap_mod(z, p.nz);
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // this wave's reads of the staging are done
+    // walls: the loads of both units, for a plane next to a wall (WP) or not
+    auto body = [&](auto wall) __attribute__((always_inline)) {
+      constexpr bool WP = decltype(wall)::value;
 #pragma unroll
-    for (int i = 0; i < 19; ++i)
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(fin, stg + i * (kW * 4), 4, col_off(lp_own, i),
-                                               rowb(y_halo, zw, L::cy(i), L::cz(i)) + B::run(c, i), 0, 0);
-    asm volatile("" ::: "memory");  // the own unit's loads after the halo-row unit's
+      for (int i = 0; i < 19; ++i) {
+        const bool bo = WP && bounced(z, L::cz(i));
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            fin, stg + i * (kW * 4), 4, bo ? lp_own.move[1] : col_off(lp_own, i),
+            bo ? rowb(y_halo, zw, 0, 0) + B::run(c, L::opp(i)) : rowb(y_halo, zw, L::cy(i), L::cz(i)) + B::run(c, i),
+            0, 0);
+      }
+      asm volatile("" ::: "memory");  // the own unit's loads after the halo-row unit's
 #pragma unroll
-    for (int i = 0; i < 19; ++i) {
-      const uint32_t so = rowb(y_own, zw, L::cy(i), L::cz(i)) + B::run(c, i);
-      const uint32_t vo = i == 0 ? lp_own.rest : lp_own.move[L::cx(i) + 1];
-      Pn[i] = load_slot32(fin, vo, so);
+      for (int i = 0; i < 19; ++i) {
+        const bool bo = WP && bounced(z, L::cz(i));
+        const uint32_t so =
+            bo ? rowb(y_own, zw, 0, 0) + B::run(c, L::opp(i)) : rowb(y_own, zw, L::cy(i), L::cz(i)) + B::run(c, i);
+        const uint32_t vo = bo ? lp_own.move[1] : (i == 0 ? lp_own.rest : lp_own.move[L::cx(i) + 1]);
+        Pn[i] = load_slot32(fin, vo, so);
+      }
+    };
+    if constexpr (W) {
+      if (at_wall(z))
+        body(std::true_type{});
+      else
+        body(std::false_type{});
+    } else {
+      // periodic box: the same loads written out (through the generic body
+      // the compiler scheduled the periodic kernel differently)
+#pragma unroll
+      for (int i = 0; i < 19; ++i)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(fin, stg + i * (kW * 4), 4, col_off(lp_own, i),
+                                                 rowb(y_halo, zw, L::cy(i), L::cz(i)) + B::run(c, i), 0, 0);
+      asm volatile("" ::: "memory");  // the own unit's loads after the halo-row unit's
+#pragma unroll
+      for (int i = 0; i < 19; ++i) {
+        const uint32_t so = rowb(y_own, zw, L::cy(i), L::cz(i)) + B::run(c, i);
+        const uint32_t vo = i == 0 ? lp_own.rest : lp_own.move[L::cx(i) + 1];
+        Pn[i] = load_slot32(fin, vo, so);
+      }
     }
     if (next_pieces) {
       asm volatile("" ::: "memory");  // the next pieces after the own unit's loads
@@ -394,20 +449,41 @@ __global__ void __launch_bounds__(64 * kTY * NC) k_sweep_d3q19(const void* fin_v
     }
     if (lane < 8) {
       const char* base = reinterpret_cast<const char*>(&sm.st[w].piece[z & 1][0][0]) + hbase;
-      float led = 0.f;
+      // WP: plane next to a wall (its reads then take a branch of their own,
+      // with immediate offsets like the others)
+      auto body = [&](auto wall) __attribute__((always_inline)) {
+        float led = 0.f;
 #pragma unroll
-      for (int i = 0; i < 19; ++i) {
-        const float v = *reinterpret_cast<const float*>(base + 16 * left_slot(i) - 4 * L::cx(i));
-        led = i == 0 ? v : led + v;
+        for (int i = 0; i < 19; ++i) {
+          // a bounced run was loaded into the same pieces from the site's
+          // own row and plane: its value sits at the column itself
+          const int sh = decltype(wall)::value && bounced(z, L::cz(i)) ? 0 : -4 * L::cx(i);
+          const float v = *reinterpret_cast<const float*>(base + 16 * left_slot(i) + sh);
+          led = i == 0 ? v : led + v;
+        }
+        sm.rho[rs][c][2 * r + hpass][xcol_lds] = led;
+      };
+      if constexpr (W) {
+        if (at_wall(z))
+          body(std::true_type{});
+        else
+          body(std::false_type{});
+      } else {
+        float led = 0.f;  // the periodic box's reads written out (see issue)
+#pragma unroll
+        for (int i = 0; i < 19; ++i) {
+          const float v = *reinterpret_cast<const float*>(base + 16 * left_slot(i) - 4 * L::cx(i));
+          led = i == 0 ? v : led + v;
+        }
+        sm.rho[rs][c][2 * r + hpass][xcol_lds] = led;
       }
-      sm.rho[rs][c][2 * r + hpass][xcol_lds] = led;
     }
   };
 
   // Step 2 for virtual plane z: potentials h on the kHR x kHC sites around
   // the pencil, all components at once.
   auto potentials = [&](int z) __attribute__((always_inline)) {
-    const int s0 = slot<kRP>(z - 1, za), s1 = slot<kRP>(z, za), s2 = slot<kRP>(z + 1, za);
+    const int s0 = slot<kRP>(mz(z - 1), za), s1 = slot<kRP>(z, za), s2 = slot<kRP>(mz(z + 1), za);
     const int hs = slot<kHP>(z, za);
     for (int q = threadIdx.x; q < kHR * kHC; q += 64 * kTY * NC) {
       const int hr = q / kHC, hc = q - hr * kHC;
@@ -433,8 +509,8 @@ __global__ void __launch_bounds__(64 * kTY * NC) k_sweep_d3q19(const void* fin_v
   // wave's unit and its 19 stores.
   auto collide_store = [&](int z, float (&f)[19], float led) __attribute__((always_inline)) {
     const int zw = wrap_mod(z, p.nz);
-    const int s0 = slot<kRP>(z - 1, za), s1 = slot<kRP>(z, za), s2 = slot<kRP>(z + 1, za);
-    const int h0 = slot<kHP>(z - 1, za), h1 = slot<kHP>(z, za), h2 = slot<kHP>(z + 1, za);
+    const int s0 = slot<kRP>(mz(z - 1), za), s1 = slot<kRP>(z, za), s2 = slot<kRP>(mz(z + 1), za);
+    const int h0 = slot<kHP>(mz(z - 1), za), h1 = slot<kHP>(z, za), h2 = slot<kHP>(mz(z + 1), za);
     const int js = slot<kJP>(z, za);
     T rt = T(0), ux = T(0), uy = T(0), uz = T(0);
 #pragma unroll
@@ -535,11 +611,11 @@ __global__ void __launch_bounds__(64 * kTY * NC) k_sweep_d3q19(const void* fin_v
 }  // namespace sweep3
 
 // Resident workgroups of the D3Q19 sweep on the current device.
-template <class S, int NC>
+template <class S, int NC, bool W>
 static int sweep3_slots() {
   static const int slots = [] {
     int per_cu = 0, dev = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sweep3::k_sweep_d3q19<S, NC>, 64 * sweep3::kTY * NC,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sweep3::k_sweep_d3q19<S, NC, W>, 64 * sweep3::kTY * NC,
                                                      0) != hipSuccess ||
         per_cu < 1)
       per_cu = 1;
@@ -560,13 +636,18 @@ static void launch_sweep3(const Ctx& c, const void* fin, void* fout) {
   const int strips = p.nx / sweep3::kW;
   const int ytiles = p.ny / sweep3::kTY;
   const int pencils = strips * ytiles;
-  const int slots = sweep3_slots<S, NC>();
+  const int slots = (p.walls & 4) ? sweep3_slots<S, NC, true>() : sweep3_slots<S, NC, false>();
   const int segs = std::max(1, std::min(p.nz, (slots + pencils - 1) / pencils));
   const int seg = (p.nz + segs - 1) / segs;
   const int ntiles = pencils * ((p.nz + seg - 1) / seg);
   const int per_xcd = (ntiles + sweep3::kXcds - 1) / sweep3::kXcds;
-  sweep3::k_sweep_d3q19<S, NC><<<per_xcd * sweep3::kXcds, 64 * sweep3::kTY * NC, 0, c.stream>>>(
-      fin, fout, p, strips, ytiles, seg, ntiles, per_xcd);
+  // walls: on z only (the context takes the sweep for no other)
+  if (p.walls & 4)
+    sweep3::k_sweep_d3q19<S, NC, true><<<per_xcd * sweep3::kXcds, 64 * sweep3::kTY * NC, 0, c.stream>>>(
+        fin, fout, p, strips, ytiles, seg, ntiles, per_xcd);
+  else
+    sweep3::k_sweep_d3q19<S, NC, false><<<per_xcd * sweep3::kXcds, 64 * sweep3::kTY * NC, 0, c.stream>>>(
+        fin, fout, p, strips, ytiles, seg, ntiles, per_xcd);
 }
 
 template <class S>
@@ -580,7 +661,7 @@ static FusedStepFn sweep3_for_n(int n_comp) {
 }
 
 // D3Q19 plane sweep: FP32, N <= 3; the caller checks nx % 64 == 0, ny % 4 ==
-// 0, no walls and a copy below 4 GiB.  The shifted FP16 codec takes the split
+// 0, walls on z at most and a copy below 4 GiB.  The shifted FP16 codec takes the split
 // path: its decode needs the references of the 19 source sites of every
 // unit, halo rows and columns included, which the pencil's registers and
 // LDS (full at N = 3) do not hold.

@@ -367,8 +367,8 @@ int init_impl(const lb_params* p, const double* rho0, void* workspace, size_t wo
   c.pf.sh = c.pd.sh = shift_ref_of(p, rho0, S);
 
   // the fused kernels address one population copy with 32-bit byte offsets;
-  // walls: the split path, the D2Q9 tile kernel, and the D2Q9 sweep when
-  // they close y only
+  // walls: the split path, the D2Q9 tile kernel, and the sweeps when they
+  // close only the swept axis (y on D2Q9, z on D3Q19)
   const bool fits = fbytes < (size_t(1) << 32);
   lbm::FusedStepFn tile = fits && (p->walls == 0 || p->lattice == LB_D2Q9)
                               ? lbm::fused_step_for(p->lattice, p->storage, p->n_comp)
@@ -376,7 +376,7 @@ int init_impl(const lb_params* p, const double* rho0, void* workspace, size_t wo
   lbm::FusedStepFn sweep = fits && (p->walls & ~2) == 0 && p->lattice == LB_D2Q9 && p->nx % 64 == 0
                                ? lbm::sweep_step_for(p->storage, p->n_comp)
                                : nullptr;
-  if (fits && p->walls == 0 && p->lattice == LB_D3Q19 && p->nx % 64 == 0 && p->ny % 4 == 0)
+  if (fits && (p->walls & ~4) == 0 && p->lattice == LB_D3Q19 && p->nx % 64 == 0 && p->ny % 4 == 0)
     sweep = lbm::sweep3d_step_for(p->storage, p->n_comp);
   switch (p->path) {
     case LB_PATH_AUTO:
@@ -393,7 +393,7 @@ int init_impl(const lb_params* p, const double* rho0, void* workspace, size_t wo
       c.path = LB_PATH_SWEEP;
       if (!sweep) {
         lb_free(h);
-        return fail(LB_ENOTSUP, "the sweep kernels need D2Q9 (FP32 or shifted FP16, N <= 4) or D3Q19 (FP32, N <= 3, ny a multiple of 4), nx a multiple of 64; walls on y only, on D2Q9");
+        return fail(LB_ENOTSUP, "the sweep kernels need D2Q9 (FP32 or shifted FP16, N <= 4) or D3Q19 (FP32, N <= 3, ny a multiple of 4), nx a multiple of 64; walls only on the swept axis, y on D2Q9 and z on D3Q19");
       }
       break;
     default:

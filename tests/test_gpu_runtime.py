@@ -211,7 +211,7 @@ def poison_copy(s, cfg, storage, which):
     s.workspace[start:start + n].fill_(255)
 
 
-@pytest.mark.parametrize("case", ["d2q9", "ragged", "d3q19", "lines", "walls", "walls_y"])
+@pytest.mark.parametrize("case", ["d2q9", "ragged", "d3q19", "lines", "walls", "walls_y", "walls_z"])
 def test_every_slot_written_each_step(case):
     """The copy a step writes is filled with NaN before the step; after three
     steps the state equals that of an unpoisoned run bit for bit, so every
@@ -232,6 +232,11 @@ def test_every_slot_written_each_step(case):
         cfg, rho0 = LI.ternary_immersion(37, ny=23)
         cfg = dict(cfg, walls=0b011)
         combos = [(p, st) for p in ("split", "tile") for st in storages(p)]
+    elif case == "walls_z":
+        cfg, _ = LI.ternary_d3q19(8)
+        cfg = dict(cfg, shape=(64, 8, 6), walls=0b100)
+        rho0 = LI.noisy_uniform(cfg, [1 / 3] * 3, 0.01, 1021)
+        combos = [("split", st) for st in storages("split")] + [("sweep", "f32")]
     elif case == "walls_y":
         cfg, rho0 = LI.ternary_immersion(128, ny=37)
         cfg = dict(cfg, walls=0b010)

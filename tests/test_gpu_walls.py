@@ -1,6 +1,7 @@
 """Walls (not in the paper; lb_params.walls) on the split path and the D2Q9
 tile kernel against the oracle's walls, every lattice and storage, the D2Q9
-tile kernel and strip sweep (walls on y) against the split path bit for bit,
+tile kernel and strip sweep (walls on y) and the D3Q19 plane sweep (walls on
+z) against the split path bit for bit,
 and the paths and groups that refuse them.  The oracle's walls are pinned by
 tests/test_oracle_walls.py."""
 import numpy as np
@@ -110,6 +111,29 @@ def test_walls_sweep_equals_split(shape, n, storage):
     assert np.array_equal(a["f"], b["f"])
 
 
+# D3Q19 boxes for the plane sweep with walls on z: two planes (both next to
+# a wall), one pencil and several, segments of one plane and of four,
+# N = 1 .. 3
+D3Q19_SWEEP_WALL_BOXES = [((64, 4, 2), 3), ((64, 8, 5), 2), ((128, 8, 9), 3), ((64, 12, 7), 1), ((64, 16, 33), 3),
+                          ((256, 48, 24), 3)]
+
+
+@pytest.mark.parametrize("shape,n", D3Q19_SWEEP_WALL_BOXES,
+                         ids=[f"{s[0]}x{s[1]}x{s[2]}-N{n}" for s, n in D3Q19_SWEEP_WALL_BOXES])
+def test_walls_d3q19_sweep_equals_split(shape, n):
+    """The D3Q19 plane sweep with walls on z against the split path, bit for
+    bit: at a plane next to a wall the bounced directions are loaded from the
+    site's own row and plane, run -v_i (own unit, halo-row unit and
+    halo-column pieces alike), and the density and potential stencils take
+    that plane for the one beyond the wall; auto picks the sweep."""
+    cfg, rho0 = walled("D3Q19", shape, 0b100, n, 110 + n)
+    a = run_gpu(cfg, rho0, 13, storage="f32", path="split")
+    b = run_gpu(cfg, rho0, 13, storage="f32", path="auto")
+    assert b["path"] == "sweep"
+    print(f"[walls-sweep3d] {shape} N={n}: max |df| {np.abs(a['f'] - b['f']).max():.3e}", flush=True)
+    assert np.array_equal(a["f"], b["f"])
+
+
 def test_walls_keep_mass_in_shifted_fp16():
     cfg, rho0 = walled("D2Q9", (48, 32), 0b011, 3, 50)
     g = run_gpu(cfg, rho0, 500, storage="f16s", path="auto", fields=True)
@@ -127,9 +151,12 @@ def test_walls_refused_where_not_built():
             Simulation(dict(cfg, walls=walls), rho0, storage="f32", path="sweep")
         assert ei.value.code == LB_ENOTSUP
     c3, r3 = walled("D3Q19", (64, 8, 6), 0b100, 2, 61)
-    for path in ("tile", "sweep"):
+    with pytest.raises(LBError) as ei:
+        Simulation(c3, r3, storage="f32", path="tile")
+    assert ei.value.code == LB_ENOTSUP
+    for walls in (0b001, 0b010, 0b101):  # the D3Q19 sweep takes walls on z only
         with pytest.raises(LBError) as ei:
-            Simulation(c3, r3, storage="f32", path=path)
+            Simulation(dict(c3, walls=walls), r3, storage="f32", path="sweep")
         assert ei.value.code == LB_ENOTSUP
     with pytest.raises(LBError) as ei:
         Simulation(dict(cfg, walls=0b100), rho0)  # D2Q9 has no z axis

@@ -247,13 +247,13 @@ def asm3d(tmp_path_factory):
     return out.read_text()
 
 
-KERNEL3D = re.compile(r"^(_ZN3lbm6sweep313k_sweep_d3q19INS_\d+(Store\w+?)ELi(\d)E\w*):", re.M)
+KERNEL3D = re.compile(r"^(_ZN3lbm6sweep313k_sweep_d3q19INS_\d+(Store\w+?)ELi(\d)ELb(\d)E\w*):", re.M)
 
 
 def kernels3d(text):
     for m in KERNEL3D.finditer(text):
         end = text.index("s_endpgm", m.end())
-        yield m.group(2), int(m.group(3)), text[m.end():end].split("\n")
+        yield m.group(2), int(m.group(3)), int(m.group(4)), text[m.end():end].split("\n")
 
 
 def m0_from_lane(lines):
@@ -275,11 +275,12 @@ def m0_from_lane(lines):
 
 def test_d3q19_staging_destinations_are_uniform(asm3d):
     """The same check on the D3Q19 plane sweep's direct loads."""
-    found = 0
-    for store, nc, lines in kernels3d(asm3d):
-        found += 1
-        assert not m0_from_lane(lines), (store, nc, m0_from_lane(lines))
-    assert found == 3
+    found = []
+    for store, nc, walls, lines in kernels3d(asm3d):
+        found.append((nc, walls))
+        assert not m0_from_lane(lines), (store, nc, walls, m0_from_lane(lines))
+    # N = 1 .. 3, periodic and walls on z
+    assert sorted(found) == [(n, w) for n in (1, 2, 3) for w in (0, 1)]
 
 
 def test_staging_destinations_are_uniform(asm):
