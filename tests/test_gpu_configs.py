@@ -8,7 +8,8 @@ at any size (conservation, agreement of precisions, permutation symmetry).
   growth and the concentrations of the domain cores;
 * the binary coexistence concentrations at equilibrium, on a flat
   interface (a slab), GPU vs the oracle over the same 20000 steps;
-* ternary D3Q19 256^3: sampled sites vs the oracle, mass conservation;
+* ternary D3Q19 256^3: sampled sites vs the oracle, mass conservation, and
+  the same box between walls on z (sweep vs split);
 * five components, D2Q9 512^2: permutation symmetry and sampled sites vs
   the oracle.
 
@@ -204,6 +205,35 @@ def test_ternary_d3q19_256_sampled_sites_and_mass():
     sim.close()
     drift = float(np.max(np.abs(m / rho0.sum(axis=1) - 1)))
     print(f"[configs] D3Q19 256^3 mass drift after 50 steps {drift:.2e}", flush=True)
+    assert drift < 1e-6
+
+
+def test_ternary_d3q19_256_walls_on_z():
+    """The same box closed by walls on z: the plane sweep (auto) bit for bit
+    equal to the split path after 6 steps, at the real launch configuration
+    (z-segments starting and ending at the walls), and mass kept over 50
+    steps."""
+    from paper_0704_3444_amd import Simulation
+
+    cfg, rho0 = LI.ternary_d3q19(256)
+    cfg = dict(cfg, walls=0b100)
+    sim = Simulation(cfg, rho0, storage="f32", path="auto")
+    assert sim.path == "sweep"
+    sim.step(6)
+    ref = Simulation(cfg, rho0, storage="f32", path="split")
+    ref.step(6)
+    a = sim.moments(fields=True)
+    b = ref.moments(fields=True)
+    ref.close()
+    print("[configs] D3Q19 256^3 walls on z: sweep vs split after 6 steps", flush=True)
+    assert np.array_equal(a["rho"], b["rho"]) and np.array_equal(a["U"], b["U"])
+    del a, b
+    sim.step(44)
+    m = sim.moments(fields=False)
+    sim.close()
+    assert m["status"] == 0
+    drift = float(np.max(np.abs(m["mass"] / rho0.sum(axis=1) - 1)))
+    print(f"[configs] D3Q19 256^3 walls on z: mass drift after 50 steps {drift:.2e}", flush=True)
     assert drift < 1e-6
 
 
