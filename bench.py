@@ -354,6 +354,8 @@ def main():
                     help="time only one batch of this many serving requests (for profiling the batched kernel)")
     ap.add_argument("--walls", type=int, default=0, help="close axes by walls (bit a: axis a; walls on y only: the D2Q9 strip sweep, else the tile kernel or the split path)")
     ap.add_argument("--serving-requests", type=int, default=256)
+    ap.add_argument("--no-substrate", action="store_true",
+                    help="skip the film-on-a-substrate run (walls on y) timed beside the default workload")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -393,6 +395,20 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+
+    # the same film cast on a substrate (walls on y), timed first so that
+    # the main workload's launches are the last ones of the run
+    substrate = None
+    if not args.no_substrate and args.workload == "ternary_d2q9_2048" and args.storage == "f32" and not args.walls:
+        scfg, srho = workload("ternary_substrate_d2q9_2048")
+        h = time_steps(scfg, srho, "f32", args.path, args.steps, args.warmup, stream)
+        sb = alg_bytes_per_step(N, S, Q, "f32")
+        substrate = {"workload": "ternary_substrate_d2q9_2048", "walls": int(scfg["walls"]),
+                     "value": round(h["value"], 1), "ms_per_step": round(h["ms_per_step"], 5), "path": h["path"],
+                     "hbm_frac": round(sb / (h["ms_per_step"] / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "mass_drift": h["mass_drift"], "status": h["health"]["status"]}
+        del srho
+
     r = time_steps(cfg, rho0, args.storage, args.path, args.steps, args.warmup, stream)
     ms_per_step, value, wall, path = r["ms_per_step"], r["value"], r["wall"], r["path"]
     health, mass_drift = r["health"], r["mass_drift"]
@@ -448,7 +464,8 @@ def main():
                    "walls": int(cfg.get("walls", 0))},
         "hbm_frac": round(achieved / HBM_PEAK_GBS, 4),
         "wall_s": round(wall, 4), "mass_drift": mass_drift, "status": health["status"],
-        "roofline": roofline, "cpu_baseline": cpu, "f16s": f16s, "serving": serving, "phase_sweeps": phase_sweeps,
+        "roofline": roofline, "cpu_baseline": cpu, "f16s": f16s, "substrate": substrate, "serving": serving,
+        "phase_sweeps": phase_sweeps,
     }
     print(json.dumps(line), flush=True)
 
