@@ -28,21 +28,34 @@ pytestmark = pytest.mark.gpu
 
 def window_oracle(cfg, rho0, site, steps):
     """Oracle rho, mu and U at one site (x, y[, z]) after `steps`, from a
-    periodic window of half-width 3 steps + 4 around it."""
+    window of half-width 3 steps + 4 around it: periodic along open axes;
+    along an axis closed by walls the window is cut at the box's walls and
+    closed by walls where it ends inside the box, at least the half-width
+    from the site, which that wall (like a periodic window's wrap) cannot
+    reach within the steps."""
     R = 3 * steps + 4
-    W = 2 * R + 1
     shape = cfg["shape"]
+    walls = int(cfg.get("walls", 0))
     n = cfg["n_comp"]
-    idx = [np.arange(c - R, c + R + 1) % s for c, s in zip(site, shape)]
+    idx, centre = [], []
+    for a, (c, s) in enumerate(zip(site, shape)):
+        if walls >> a & 1:
+            lo, hi = max(0, c - R), min(s, c + R + 1)
+            idx.append(np.arange(lo, hi))
+            centre.append(c - lo)
+        else:
+            idx.append(np.arange(c - R, c + R + 1) % s)
+            centre.append(R)
     g = rho0.reshape((n,) + tuple(reversed(shape)))  # [n][z][y][x] or [n][y][x]
     if len(shape) == 2:
         g = g[:, idx[1]][:, :, idx[0]]
     else:
         g = g[:, idx[2]][:, :, idx[1]][:, :, :, idx[0]]
-    o = Oracle(OracleParams(**dict(cfg, shape=(W,) * len(shape))), np.ascontiguousarray(g.reshape(n, -1)))
+    wshape = tuple(len(i) for i in idx)
+    o = Oracle(OracleParams(**dict(cfg, shape=wshape)), np.ascontiguousarray(g.reshape(n, -1)))
     o.step(steps)
     ob = o.observe()
-    c = R * sum(W ** d for d in range(len(shape)))  # centre site of the window
+    c = site_index(centre, wshape)  # the site within the window
     return ob["rho"][:, c], ob["mu"][:, c], ob["U"][:, c]
 
 
@@ -209,17 +222,25 @@ def test_ternary_d3q19_256_sampled_sites_and_mass():
 
 
 def test_ternary_d3q19_256_walls_on_z():
-    """The same box closed by walls on z: the plane sweep (auto) bit for bit
-    equal to the split path after 6 steps, at the real launch configuration
-    (z-segments starting and ending at the walls), and mass kept over 50
-    steps."""
+    """The same box closed by walls on z: sampled sites after 4 steps
+    against the oracle (windows cut at the walls), the plane sweep (auto) bit
+    for bit equal to the split path after 6 steps at the real launch
+    configuration (z-segments starting and ending at the walls), and mass
+    kept over 50 steps."""
     from paper_0704_3444_amd import Simulation
 
     cfg, rho0 = LI.ternary_d3q19(256)
     cfg = dict(cfg, walls=0b100)
     sim = Simulation(cfg, rho0, storage="f32", path="auto")
     assert sim.path == "sweep"
-    sim.step(6)
+    sim.step(4)
+    out = sim.moments(fields=True)
+    # next to both walls, one plane in, a segment's first planes and the middle
+    sites = [(0, 0, 0), (255, 255, 255), (63, 64, 1), (128, 3, 254), (5, 200, 32), (200, 31, 128)]
+    print(f"[configs] D3Q19 256^3 walls on z: {len(sites)} sampled sites after 4 steps", flush=True)
+    check_sampled(cfg, rho0, out, sites, 4, TOL["f32"])
+    del out
+    sim.step(2)
     ref = Simulation(cfg, rho0, storage="f32", path="split")
     ref.step(6)
     a = sim.moments(fields=True)
