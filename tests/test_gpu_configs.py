@@ -10,6 +10,8 @@ at any size (conservation, agreement of precisions, permutation symmetry).
   interface (a slab), GPU vs the oracle over the same 20000 steps;
 * ternary D3Q19 256^3: sampled sites vs the oracle, mass conservation, and
   the same box between walls on z (sweep vs split);
+* the film cast on a substrate (walls on y), D2Q9 2048^2: sampled sites vs
+  the oracle;
 * five components, D2Q9 512^2: permutation symmetry and sampled sites vs
   the oracle.
 
@@ -256,6 +258,25 @@ def test_ternary_d3q19_256_walls_on_z():
     drift = float(np.max(np.abs(m["mass"] / rho0.sum(axis=1) - 1)))
     print(f"[configs] D3Q19 256^3 walls on z: mass drift after 50 steps {drift:.2e}", flush=True)
     assert drift < 1e-6
+
+
+def test_film_on_substrate_2048_sampled_sites():
+    """The film cast on a substrate at 2048^2 (walls on y, the FP32 strip
+    sweep at its tuned launch configuration): sampled sites after 4 steps
+    against the oracle (windows cut at the walls) next to both walls, at
+    the film's free face and in the bulk."""
+    from paper_0704_3444_amd import Simulation
+
+    cfg, rho0 = LI.ternary_film_on_substrate(2048)
+    sim = Simulation(cfg, rho0, storage="f32", path="auto")
+    assert sim.path == "sweep"
+    sim.step(4)
+    out = sim.moments(fields=True)
+    sim.close()
+    sites = [(0, 0), (2047, 2047), (100, 1), (1500, 2046), (7, 1023), (64, 1024), (1023, 1025), (300, 500),
+             (1777, 1600)]
+    print(f"[configs] film on a substrate 2048^2: {len(sites)} sampled sites after 4 steps", flush=True)
+    check_sampled(cfg, rho0, out, sites, 4, TOL["f32"])
 
 
 @pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 1e-5)])
