@@ -283,6 +283,70 @@ def test_d3q19_staging_destinations_are_uniform(asm3d):
     assert sorted(found) == [(n, w) for n in (1, 2, 3) for w in (0, 1)]
 
 
+def halo_unit_cover(lines, blocks, preds, at, n):
+    """For the explicit vmcnt(n) at line `at`: over every control path back to
+    the nearest direct 4-byte load into LDS (a halo-row unit load of the
+    D3Q19 sweep), how many more vector memory operations that load would
+    have needed after it to be complete at `at`.  Walking back, each vector
+    memory operation lowers the need by one, and a wait vmcnt(m) on the way
+    (the compiler's own, or an earlier explicit one) caps it at m, as that
+    wait leaves only the m latest operations in flight.  A path whose value
+    is above 0 would read the unit before it has landed."""
+    is_unit = lambda t: t.startswith("buffer_load_dword ") and t.endswith(" lds")
+    is_vmem = lambda t: t.startswith(("global_load", "buffer_load", "flat_load", "global_store", "buffer_store",
+                                      "flat_store"))
+    home = next(k for k, (_, a, b) in enumerate(blocks) if a <= at <= b)
+    found, todo, seen = set(), [(home, at - 1, n)], set()
+    while todo:
+        k, i, need = todo.pop()
+        a = blocks[k][1]
+        hit = False
+        while i >= a:
+            t = lines[i].strip()
+            if is_unit(t):
+                found.add(need)
+                hit = True
+                break
+            if is_vmem(t):
+                need -= 1
+            m = re.search(r"s_waitcnt\s.*vmcnt\((\d+)\)", t)
+            if m:
+                need = min(need, int(m.group(1)))
+            i -= 1
+        if hit:
+            continue
+        for q in preds[k]:
+            if (q, need) not in seen:
+                assert len(seen) < 100000, "a cycle without halo-row loads"
+                seen.add((q, need))
+                todo.append((q, blocks[q][2], need))
+    return found
+
+
+def test_d3q19_halo_unit_has_landed_at_its_wait(asm3d):
+    """The D3Q19 sweep reads a plane's halo-row unit (direct loads into LDS,
+    which the compiler does not track) after an explicit vmcnt(21): on every
+    control path into that wait the unit's last load must be complete, by
+    that wait (in the prologue the own unit's 19 loads and the 2 halo pieces
+    of the next plane follow the unit, in the iterations those and the
+    collision's 19 stores) or by the compiler's own waits for the own
+    unit's register loads, issued after the unit and read just before.
+    Checked for the periodic and the walled instantiations, whose wall
+    planes take a branch of their own (there the compiler guards the second
+    piece load with a branch on an empty lane mask, which the hardware never
+    takes: lanes 0 .. 33 always load)."""
+    checked = 0
+    for store, nc, walls, lines in kernels3d(asm3d):
+        blocks, preds = blocks_of(lines)
+        for i, line in enumerate(lines):
+            m = re.search(r"s_waitcnt\s.*vmcnt\((\d+)\)", line)
+            if m and "ASMSTART" in lines[i - 1] and int(m.group(1)) == 21:
+                needs = halo_unit_cover(lines, blocks, preds, i, 21)
+                assert needs and max(needs) <= 0, (store, nc, walls, i, needs)
+                checked += 1
+    assert checked >= 6
+
+
 def test_staging_destinations_are_uniform(asm):
     """A direct load's LDS destination is M0, one value for the whole wave.
     The compiler once merged a load issued by some lanes with the next load
