@@ -226,3 +226,37 @@ def test_film_on_substrate_sweep():
         sim.close()
         assert m["status"] == 0, storage
         assert float(np.max(np.abs(m["mass"] / rho0.sum(axis=1) - 1))) < 1e-6, storage
+
+
+@pytest.mark.parametrize("case", ["d2q9-substrate", "d3q19-z"])
+def test_walls_sweeps_long_runs(case):
+    """Long runs on the sweeps with walls: the film on a substrate (512^2,
+    20 000 steps, FP32 and shifted FP16) and a ternary D3Q19 box between
+    walls on z (128 x 32 x 64, 3000 steps, FP32): healthy, every
+    component's mass kept, and the FP32 state bit for bit the split path's."""
+    from paper_0704_3444_amd import Simulation
+
+    if case == "d2q9-substrate":
+        cfg, rho0 = LI.ternary_film_on_substrate(512)
+        steps, storages = 20000, ("f32", "f16s")
+    else:
+        cfg, _ = LI.ternary_d3q19(8)
+        cfg = dict(cfg, shape=(128, 32, 64), walls=0b100)
+        rho0 = LI.noisy_uniform(cfg, [0.3, 0.3, 0.4], 0.02, 1031)
+        steps, storages = 3000, ("f32",)
+    for storage in storages:
+        sim = Simulation(cfg, rho0, storage=storage, path="auto")
+        assert sim.path == "sweep"
+        sim.step(steps)
+        m = sim.moments(fields=storage == "f32")
+        f = sim.get_f() if storage == "f32" else None
+        sim.close()
+        drift = float(np.max(np.abs(m["mass"] / rho0.sum(axis=1) - 1)))
+        print(f"[walls-long] {case} {storage} {steps} steps: status {m['status']}, mass drift {drift:.2e}", flush=True)
+        assert m["status"] == 0 and drift < 1e-6, (storage, m["status"], drift)
+        if storage == "f32":
+            ref = Simulation(cfg, rho0, storage="f32", path="split")
+            ref.step(steps)
+            g = ref.get_f()
+            ref.close()
+            assert np.array_equal(f, g)
