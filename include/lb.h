@@ -153,7 +153,8 @@ size_t lb_workspace_bytes(const lb_params* p);
  * On the strip-sweep path (lb_path_in_use) of a grid of at least 2^20
  * sites, lb_init also chooses the sweep's segment length on the new state:
  * it takes 48 steps, then times up to 8 segment lengths (twice each: one
- * step to switch, then 4 between events on the stream), keeps the fastest
+ * step to switch, then 4 between events on the stream), times the two
+ * fastest again (twice each, alternately, over 12 steps), keeps the faster
  * and returns the state to rest equilibrium before returning (a few tens of
  * milliseconds at 2048^2).  Every segment length gives the same results bit
  * for bit; lb_step itself never times or waits.

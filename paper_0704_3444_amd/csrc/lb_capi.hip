@@ -254,20 +254,62 @@ void tune_sweep(Ctx& c) {
       }
     ok = hipEventSynchronize(ev[nev - 1]) == hipSuccess;
   }
-  int best = -1;
-  float best_ms = 0.f;
-  for (int i = 0; ok && i < nc; ++i)
+  // the two lengths with the shortest trials
+  int best = -1, second = -1;
+  float best_ms = 0.f, second_ms = 0.f;
+  for (int i = 0; ok && i < nc; ++i) {
+    float ms_i = -1.f;
     for (int q = 0; q < Tu::passes; ++q) {
       const int e = 2 * (q * nc + i);
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, ev[e], ev[e + 1]) != hipSuccess) continue;
-      if (best < 0 || ms < best_ms) {
-        best = i;
-        best_ms = ms;
-      }
+      if (ms_i < 0.f || ms < ms_i) ms_i = ms;
     }
+    if (ms_i < 0.f) continue;
+    if (best < 0 || ms_i < best_ms) {
+      second = best;
+      second_ms = best_ms;
+      best = i;
+      best_ms = ms_i;
+    } else if (second < 0 || ms_i < second_ms) {
+      second = i;
+      second_ms = ms_i;
+    }
+  }
   for (int i = 0; i < nev; ++i)
     if (ev[i]) (void)hipEventDestroy(ev[i]);
+  // the two again, alternately, over longer runs: short trials separate
+  // lengths a few percent apart, not the closest ones
+  if (ok && second >= 0) {
+    hipEvent_t rv[2 * 2 * Tu::rpasses] = {};
+    const int nrv = 2 * 2 * Tu::rpasses;
+    bool rok = true;
+    for (int i = 0; rok && i < nrv; ++i) rok = hipEventCreate(&rv[i]) == hipSuccess;
+    if (rok) {
+      const int pick[2] = {best, second};
+      for (int q = 0; q < Tu::rpasses; ++q)
+        for (int j = 0; j < 2; ++j) {
+          const int e = 2 * (2 * q + j);
+          c.sweep_rows = cand[pick[j]];
+          step_once(c);
+          (void)hipEventRecord(rv[e], c.stream);
+          for (int s = 0; s < Tu::rsteps; ++s) step_once(c);
+          (void)hipEventRecord(rv[e + 1], c.stream);
+        }
+      rok = hipEventSynchronize(rv[nrv - 1]) == hipSuccess;
+      float sum[2] = {0.f, 0.f};
+      for (int q = 0; rok && q < Tu::rpasses; ++q)
+        for (int j = 0; j < 2; ++j) {
+          const int e = 2 * (2 * q + j);
+          float ms = 0.f;
+          rok = hipEventElapsedTime(&ms, rv[e], rv[e + 1]) == hipSuccess;
+          sum[j] += ms;
+        }
+      if (rok && sum[1] < sum[0]) best = second;
+    }
+    for (int i = 0; i < nrv; ++i)
+      if (rv[i]) (void)hipEventDestroy(rv[i]);
+  }
   (void)hipGetLastError();
   c.sweep_rows = best >= 0 ? cand[best] : 0;
 }

@@ -25,12 +25,16 @@ int sweep_candidates(const Ctx& c, int* cand);
 // after a pause, which would otherwise favour whichever candidate runs
 // last), then, in each of `passes` passes, for each candidate one step that
 // switches to it and steps_per steps between two events on the context's
-// stream; the candidate with the shortest of its timings is kept.
+// stream; then the two candidates with the shortest timings again, in
+// rpasses alternating passes of one switching step and rsteps timed steps,
+// and the one with the smaller total is kept.
 struct SweepTuner {
   static constexpr int kMax = 8;
   static constexpr int warm = 48;
   static constexpr int steps_per = 4;
   static constexpr int passes = 2;
+  static constexpr int rsteps = 12;
+  static constexpr int rpasses = 2;
 };
 
 // Context behind the opaque lb_ctx handle.
